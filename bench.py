@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark: P_l(k) estimates per second at 512^3, l <= 4, on one MI355X.
+
+One step (= one estimate) is pkm_paint + pkm_compute_multipoles(ell_max=4) on a catalog
+already resident in HBM: 1e6 lognormal galaxies + 2e7 randoms in a 2500 Mpc/h box, TSC with
+interlacing and compensation, 64 uniform k bins up to the Nyquist frequency (17 transforms).
+Prints one JSON line (rank 0).  The FP32 form gives `value`; the FP64 form is reported
+beside it.  `roofline` covers the kernel stage with the largest device time, measured with
+HIP events on the plan's stream inside the timed region.  `cpu_baseline` times the FP64
+oracle on a bounded sample of the same estimate and scales it to estimates/s.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "P_ℓ(k) estimates/s at 512³ ℓ≤4 (FP32 vs FP64), HBM GB/s; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+NMESH, BOX, ELL_MAX = 512, 2500.0, 4
+OBSERVER = (0.0, 0.0, -1500.0)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stage_bytes(nmesh: int, es: int, n_part: int, nfields: int) -> dict:
+    """Algorithmic HBM bytes per estimate of each kernel stage (one read + one write of
+    every element a pass must touch; see the design doc for the derivation)."""
+    X = es * nmesh ** 3          # half spectrum (N x N x N/2 complex) == real mesh bytes
+    return {
+        "sums": 40.0 * n_part,
+        "fill": 2.0 * X,
+        "paint": 40.0 * n_part + 2.0 * X,
+        "zfwd": 4.0 * X,
+        "ycol": 4.0 * X + 2.0 * nfields * X,
+        "xcombine": 4.0 * X,
+        "iycol": 2.0 * X,
+        "zpre": (1.0 + nfields) * X,
+        "xpost": (1.0 + nfields) * X,
+        "reduce": 0.0,
+    }
+
+
+def run_form(precision: int, data, rand, edges, steps: int, warmup: int):
+    import torch
+    from paper_1704_02357_amd import Plan
+    plan = Plan(NMESH, BOX, observer=OBSERVER, window=3, interlaced=True, compensated=True, precision=precision,
+                ell_max_hint=ELL_MAX)
+    for _ in range(warmup):
+        plan.paint(data, rand)
+        res = plan.compute_multipoles(ELL_MAX, edges)
+    plan.reset_stats()
+    plan.set_stage_timing(True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        plan.paint(data, rand)
+        res = plan.compute_multipoles(ELL_MAX, edges)
+        lat.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = plan.stats()
+    plan.close()
+    return res, (t1 - t0), np.array(lat), st
+
+
+def cpu_baseline(data, rand, edges, workers: int) -> dict:
+    """FP64 oracle timed on a bounded sample of one estimate, scaled to estimates/s.
+
+    Sample: painting of 1/20 of the catalog (x20), one full-grid forward transform (x17
+    transforms), one harmonic field (Y_lm at every node and mode, product, accumulate; x14
+    fields) and one binning pass (x3 multipoles)."""
+    import scipy.fft as sfft
+    from oracle.estimator import default_params, k_thresholds, mode_bins, node_vectors, mode_vectors, binned_sums
+    from oracle.mesh import fkp_meshes
+    from oracle.catalog import catalog_scalars
+    from oracle.ylm import real_ylm
+    from synth import Catalog
+    p = default_params(NMESH, BOX, observer=OBSERVER, window=3, interlaced=True, compensated=True)
+    frac = 20
+    sub_d = Catalog(data.pos[::frac], data.w[::frac], data.nbar[::frac])
+    sub_r = Catalog(rand.pos[::frac], rand.w[::frac], rand.nbar[::frac])
+    t = {}
+    t0 = time.perf_counter()
+    sc = catalog_scalars(sub_d, sub_r, BOX)
+    d1, d2 = fkp_meshes(sub_d, sub_r, sc["alpha"], NMESH, BOX, p["box_origin"], 3, True)
+    t["paint"] = (time.perf_counter() - t0) * frac
+    t0 = time.perf_counter()
+    c = sfft.fftn(d1, workers=workers)
+    t["fft"] = (time.perf_counter() - t0) * 17
+    del d2
+    t0 = time.perf_counter()
+    xv = node_vectors(NMESH, BOX, p["box_origin"], p["observer"])
+    kv = mode_vectors(NMESH)
+    b = sfft.fftn(d1 * real_ylm(2, 1, xv), workers=workers)
+    a = real_ylm(2, 1, kv) * b
+    t["field"] = (time.perf_counter() - t0) * 14
+    del xv, kv, b
+    t0 = time.perf_counter()
+    bins = mode_bins(NMESH, k_thresholds(edges, BOX))
+    q = np.real(c * np.conj(a))
+    binned_sums(q, bins, len(edges) - 1)
+    t["bin"] = (time.perf_counter() - t0) * 3
+    sec = sum(t.values())
+    return {"value": 1.0 / sec, "unit": "estimates/s", "cores": workers, "kind": "oracle",
+            "sample": "FP64 numpy/scipy oracle: paint of 1/20 of the catalog (x20), one 512^3 complex FFT (x17), "
+                      "one Y_lm-weighted field incl. both harmonic evaluations (x14), one binning pass (x3); "
+                      f"seconds per estimate {sec:.1f} = " + ", ".join(f"{k} {v:.1f}" for k, v in t.items())}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ngal", type=int, default=1_000_000)
+    ap.add_argument("--random-factor", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    from synth import config_c2
+    t0 = time.perf_counter()
+    data, rand, info = config_c2(n_gal=args.ngal, random_factor=args.random_factor)
+    log(f"[bench] inputs: {info['n_data']} galaxies, {info['n_rand']} randoms ({time.perf_counter() - t0:.1f} s)")
+    kn = math.pi * NMESH / BOX
+    edges = np.arange(int(math.floor(kn / 0.01)) + 1, dtype=np.float64) * 0.01
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    gdata = (dev(data.pos), dev(data.w), dev(data.nbar))
+    grand = (dev(rand.pos), dev(rand.w), dev(rand.nbar))
+    torch.cuda.synchronize()
+    res32, sec32, lat32, st32 = run_form(0, gdata, grand, edges, args.steps, args.warmup)
+    log(f"[bench] fp32: {args.steps / sec32:.2f} est/s, {1e3 * sec32 / args.steps:.3f} ms/step")
+    k64 = args.fp64_steps or max(2, args.steps // 2)
+    res64, sec64, lat64, st64 = run_form(1, gdata, grand, edges, k64, max(1, args.warmup // 2))
+    log(f"[bench] fp64: {k64 / sec64:.2f} est/s")
+    # FP32 form against the FP64 form (same inputs): the per-bin rule of the parity tests
+    raw0 = res64["poles"][0] + res64["shot_noise"]
+    scale = np.maximum(np.abs(res64["poles"]), np.abs(raw0)[None, :])
+    ok = np.isfinite(res64["poles"])
+    fp32_err = float(np.max(np.abs(res32["poles"] - res64["poles"])[ok] / scale[ok]))
+    nfields = sum(2 * l + 1 for l in range(2, ELL_MAX + 1, 2))
+    n_part = info["n_data"] + info["n_rand"]
+    stages = {}
+    for name, ms in st32["stage_ms"].items():
+        nl = st32["stage_launches"][name]
+        if nl == 0 or ms <= 0:
+            continue
+        b = stage_bytes(NMESH, 4, n_part, nfields)[name] * args.steps
+        stages[name] = {"ms_total": round(ms, 3), "launches": nl, "ms_per_launch": round(ms / nl, 4),
+                        "algorithmic_GBps": round(b / (ms * 1e-3) / 1e9, 1) if b > 0 else None}
+    dom = max(stages, key=lambda k: stages[k]["ms_total"])
+    dom_bytes_per_launch = stage_bytes(NMESH, 4, n_part, nfields)[dom] * args.steps / stages[dom]["launches"]
+    achieved = dom_bytes_per_launch / (stages[dom]["ms_per_launch"] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": dom_bytes_per_launch}
+    total_model = sum(stage_bytes(NMESH, 4, n_part, nfields).values())
+    out = {
+        "metric": METRIC,
+        "value": round(args.steps / sec32, 3),
+        "unit": "estimates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * sec32 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded lognormal survey mock, resident in HBM)",
+        "config": {"workload": "512^3 mesh, L=2500 Mpc/h, TSC + interlacing + compensation, even l <= 4 "
+                               "(17 transforms), 64 k bins of 0.01 h/Mpc, 1e6 galaxies + 2e7 randoms",
+                   "nmesh": NMESH, "box_len": BOX, "ell_max": ELL_MAX, "n_kbins": len(edges) - 1,
+                   "n_data": info["n_data"], "n_rand": info["n_rand"]},
+        "latency_ms": {"p50": round(1e3 * float(np.percentile(lat32, 50)), 3),
+                       "p99": round(1e3 * float(np.percentile(lat32, 99)), 3)},
+        "fp64": {"value": round(k64 / sec64, 3), "ms_per_step": round(1e3 * sec64 / k64, 4),
+                 "latency_ms": {"p50": round(1e3 * float(np.percentile(lat64, 50)), 3),
+                                "p99": round(1e3 * float(np.percentile(lat64, 99)), 3)}},
+        "fp32_vs_fp64_max_scaled_err": fp32_err,
+        "model_GB_per_estimate_fp32": round(total_model / 1e9, 3),
+        "effective_GBps_fp32": round(total_model * args.steps / sec32 / 1e9, 1),
+        "roofline": roof,
+        "stages": stages,
+    }
+    if not args.no_cpu_baseline:
+        workers = max(1, min(16, os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(data, rand, edges, workers)
+        log(f"[bench] cpu baseline sample took {time.perf_counter() - t0:.1f} s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,224 @@
+/*
+ * pkm.h - C ABI of libpkm: FFT-based power-spectrum multipoles with a local line of sight
+ * (Hand, Li, Slepian & Seljak 2017, arXiv:1704.02357) on AMD Instinct MI355X (gfx950).
+ *
+ * What is computed.
+ *   The FKP field F = w [n - alpha n_s] / I^(1/2) (Sec. 2.1, eq. FKP-density) is painted on
+ *   an N^3 mesh (Sec. 2.3: NGP/CIC/TSC, optional interlacing and window compensation).  For
+ *   every even l <= ell_max the multipole
+ *       P_l(k) = (2l+1)/I  < F_0(k) F_l(-k) >_shell  - delta_l0 S            (eq. Pell-ours)
+ *       F_l(k) = 4 pi/(2l+1) sum_m Y_lm(khat) FT[F Y_lm(rhat)](k)           (eq. Fell)
+ *   is evaluated with 2l+1 transforms per l > 0 and the real harmonics of eq. real-Ylm.
+ *   Wedges P(k, mu) follow from eq. wedge-est with the wedge means of eq. Lbar (Sec. 2.2).
+ *
+ * Conventions (readings of points the paper leaves open):
+ *   - Node c of the mesh sits at box_origin + c L/N; painted taps wrap periodically.
+ *   - Mesh coordinate u = (x - o) * (N/L) in FP64.  NGP/TSC centre node floor(u + 1/2),
+ *     CIC base node floor(u).  The interlaced mesh is painted at u + 1/2 on every axis and
+ *     the two transforms are averaged with phase exp(+i pi (n_x+n_y+n_z)/N).
+ *   - Compensation: interlaced -> prod sinc^p(pi n_a/N); otherwise the alias-sum form
+ *     prod sqrt(A_p(sin^2(pi n_a/N))) (p = 1, 2, 3 for NGP, CIC, TSC), applied once to the
+ *     combined field before it is transformed back and harmonically weighted.
+ *   - Every mode with a component equal to -N/2 is zero and belongs to no bin; k = 0 belongs
+ *     to no bin.  Bin i holds the modes with T_i <= |n|^2 < T_{i+1},
+ *     T_i = ceil(((k_i * L) / (2 pi))^2) computed in FP64.
+ *   - alpha = N_data/N_randoms, I = alpha sum_r w^2 nbar, S = (sum_d w^2 + alpha^2 sum_r w^2)/I;
+ *     without randoms (periodic box) nbar = N_data/L^3, I = nbar sum_d w^2, S = sum_d w^2/I.
+ *
+ * Memory and ownership.
+ *   Every pointer argument is owned by the caller.  Host pointers are read (or written)
+ *   only during the call.  Catalog arrays with on_device = 1 are device pointers on the
+ *   plan's device, read on the plan's stream before the call returns.  A plan owns its
+ *   device meshes; the painted field stays resident from pkm_paint until the next
+ *   pkm_paint or pkm_plan_destroy, so several pkm_compute_multipoles calls may follow one
+ *   paint.  Calls are synchronous with respect to the host.  A plan is not thread safe;
+ *   distinct plans are independent.
+ *
+ * Errors.  Every function returns a pkm_status; nothing aborts or throws across the ABI.
+ *   On error the outputs are untouched and pkm_plan_last_error() holds a message.
+ *   PKM_EINVAL leaves the plan unchanged.  After PKM_EDEVICE the plan must be destroyed.
+ */
+#ifndef PKM_H
+#define PKM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PKM_ABI_VERSION 1
+
+typedef enum {
+  PKM_OK = 0,
+  PKM_EINVAL = 1,     /* invalid argument (plan unchanged) */
+  PKM_EORDER = 2,     /* compute before paint */
+  PKM_ENOMEM = 3,     /* device allocation failed or footprint above the budget */
+  PKM_EDEVICE = 4,    /* HIP runtime error; destroy the plan */
+  PKM_EBUSY = 5,      /* server queue full / request not finished */
+  PKM_ECANCELLED = 6  /* request cancelled */
+} pkm_status;
+
+enum { PKM_NGP = 1, PKM_CIC = 2, PKM_TSC = 3 };
+enum { PKM_FP32 = 0, PKM_FP64 = 1 };
+enum { PKM_LOS_LOCAL = 0, PKM_LOS_GLOBAL = 1 };
+
+/* Mesh and estimator parameters (Sec. 2.1, Sec. 2.3).
+ *   nmesh        N: 2^a 3^b with a >= 2, 16 <= N <= 1024.
+ *   box_len      L > 0 (cubic box [o, o + L)^3).
+ *   box_origin   o.
+ *   observer     position of the observer (local line of sight from it to each node).
+ *   los_mode/los PKM_LOS_GLOBAL uses the unit vector `los` in pkm_kmu_global only.
+ *   window       PKM_NGP | PKM_CIC | PKM_TSC.
+ *   interlaced   0/1: second mesh at +1/2 cell, averaged in Fourier space.
+ *   compensated  0/1: divide the combined field by the assignment window.
+ *   precision    PKM_FP32 (FP32 meshes/transforms, FP64 index math and sums) or PKM_FP64.
+ *   ell_max_hint largest ell_max later requested (sizes the field buffers); 0 means 4.
+ *   max_group    upper bound on weighted fields kept in HBM at once; 0 = automatic.      */
+typedef struct {
+  int32_t nmesh;
+  double box_len;
+  double box_origin[3];
+  double observer[3];
+  int32_t los_mode;
+  double los[3];
+  int32_t window;
+  int32_t interlaced;
+  int32_t compensated;
+  int32_t precision;
+  int32_t ell_max_hint;
+  int32_t max_group;
+} pkm_params;
+
+/* A catalog: n objects, positions pos[3*i + a] (FP64, absolute coordinates), optional
+ * weights w[i] (NULL -> 1) and number densities nbar[i] (required for randoms).
+ * on_device = 1: the three pointers are device pointers on the plan's device.            */
+typedef struct {
+  const double* pos;
+  const double* w;
+  const double* nbar;
+  int64_t n;
+  int32_t on_device;
+} pkm_catalog;
+
+/* Result of pkm_compute_multipoles.  The caller allocates:
+ *   poles   (ell_max/2 + 1) x (n_edges - 1) doubles, row l/2 holds P_l;
+ *   k_mean  n_edges - 1 doubles (mean |k| of the bin's modes, NaN if empty);
+ *   n_modes n_edges - 1 counts (full-sphere modes).
+ * Any of the three may be NULL.  The scalars are filled by the call.                      */
+typedef struct {
+  double* poles;
+  double* k_mean;
+  int64_t* n_modes;
+  double alpha;
+  double norm_I;
+  double shot_noise;
+  int32_t n_transforms;
+} pkm_result;
+
+/* Device, stream and optional allocator.  hip_stream is a hipStream_t (NULL = default
+ * stream).  alloc/free may route device allocations through a caller's allocator (e.g. a
+ * framework's caching allocator); NULL selects hipMalloc/hipFree.                          */
+typedef struct {
+  int32_t device_id;
+  void* hip_stream;
+  void* (*alloc)(size_t bytes, void* stream, void* ctx);
+  void (*free)(void* ptr, void* stream, void* ctx);
+  void* alloc_ctx;
+} pkm_device;
+
+/* Kernel stages reported by pkm_stats (stage_ms / stage_launches index). */
+enum {
+  PKM_STAGE_SUMS = 0,      /* catalog reductions */
+  PKM_STAGE_FILL = 1,      /* mesh zeroing */
+  PKM_STAGE_PAINT = 2,     /* mass assignment */
+  PKM_STAGE_ZFWD = 3,      /* forward z of the painted meshes */
+  PKM_STAGE_YCOL = 4,      /* forward y column passes (painted meshes and weighted fields) */
+  PKM_STAGE_XCOMBINE = 5,  /* x pass + interlace combine + compensation + inverse x */
+  PKM_STAGE_IYCOL = 6,     /* inverse y pass of the combined field */
+  PKM_STAGE_ZPRE = 7,      /* inverse z to D_c + Y_lm(xhat) weighting + forward z per field */
+  PKM_STAGE_XPOST = 8,     /* forward x per field + sum_m Y_lm(khat) B + product with C + binning */
+  PKM_STAGE_REDUCE = 9,    /* fixed-order reduction of the bin partial sums */
+  PKM_NSTAGES = 10
+};
+
+/* Per-plan counters.  stage_ms / stage_launches accumulate (since the last pkm_reset_stats)
+ * only while stage timing is enabled (pkm_set_stage_timing), from HIP events recorded on
+ * the plan's stream around every launch. */
+typedef struct {
+  int64_t device_bytes;      /* device memory held by the plan */
+  int32_t n_transforms;      /* transforms of the last paint + compute */
+  int32_t n_groups;          /* field groups of the last compute */
+  double ms_paint;           /* device time of the last pkm_paint */
+  double ms_compute;         /* device time of the last pkm_compute_multipoles */
+  double model_bytes_paint;  /* algorithmic HBM bytes of the last paint */
+  double model_bytes_compute;/* algorithmic HBM bytes of the last compute */
+  double stage_ms[10];
+  int64_t stage_launches[10];
+} pkm_stats_t;
+
+typedef struct pkm_plan pkm_plan;
+
+int pkm_abi_version(void);
+const char* pkm_status_str(pkm_status s);
+
+/* Validate the parameters, build twiddle / harmonic / compensation tables and allocate the
+ * plan's device buffers.  *out is set only on success.                                     */
+pkm_status pkm_plan_create(const pkm_params* p, const pkm_device* dev, pkm_plan** out);
+
+/* Sec. 2.1 (eq. FKP-density) and Sec. 2.3: catalog scalars, painting of data minus
+ * alpha x randoms (randoms NULL -> periodic box), forward transforms, interlace combine,
+ * compensation, and the inverse transform of the combined field.  Replaces any previous
+ * paint of this plan.                                                                       */
+pkm_status pkm_paint(pkm_plan* plan, const pkm_catalog* data, const pkm_catalog* randoms);
+
+/* Sec. 2.1 eq. Pell-ours / eq. Fell, binned as in Sec. 2.2 (uniform or arbitrary increasing
+ * k edges, n_edges >= 2, edges >= 0): every even l <= ell_max (ell_max even, 0..16).
+ * Requires a prior pkm_paint (else PKM_EORDER).                                           */
+pkm_status pkm_compute_multipoles(pkm_plan* plan, int32_t ell_max, const double* k_edges, int32_t n_edges,
+                                  pkm_result* out);
+
+/* Fixed line of sight (the plan's `los`): P(k_i, mu_j) = sum |C|^2 / (I N_ij) - S over the
+ * modes with mu = |khat . los| in [mu_j, mu_{j+1}) (mu = 1 in the last bin).  Outputs are
+ * (n_k_edges-1) x (n_mu_edges-1), row-major by k; either may be NULL.                      */
+pkm_status pkm_kmu_global(pkm_plan* plan, const double* k_edges, int32_t n_k_edges, const double* mu_edges,
+                          int32_t n_mu_edges, double* pkmu_out, int64_t* nmodes_out);
+
+/* Sec. 2.2 eq. wedge-est with eq. Lbar, host only, FP64:
+ *   wedges_out[i*(n_mu_edges-1) + j] = sum_{even l <= ell_max} poles[(l/2)*n_k + i] Lbar_l(mu_j, mu_{j+1}).
+ * mu edges strictly increasing in [0, 1].                                                   */
+pkm_status pkm_wedges(const double* poles, int32_t ell_max, int32_t n_k, const double* mu_edges, int32_t n_mu_edges,
+                      double* wedges_out);
+
+/* Sec. 3.1 eq. nonuniform-bins: the ell_max/2 + 2 edges (mu_0 = 0, last = 1) for which
+ * every bin but the first integrates L_{ell_max+1}(mu)/mu to zero.  Host only.             */
+pkm_status pkm_nonuniform_mu_edges(int32_t ell_max, double* edges_out);
+
+pkm_status pkm_stats(const pkm_plan* plan, pkm_stats_t* out);
+/* Enable (1) or disable (0) per-launch event timing; pkm_reset_stats clears the sums. */
+pkm_status pkm_set_stage_timing(pkm_plan* plan, int32_t enable);
+pkm_status pkm_reset_stats(pkm_plan* plan);
+const char* pkm_plan_last_error(const pkm_plan* plan);
+void pkm_plan_destroy(pkm_plan* plan);
+
+/* 3D transforms of the plan's size and precision on caller device buffers (the same passes
+ * the estimator runs).  Forward: real N^3 mesh (x, y, z; z contiguous) -> half spectrum
+ * N x N x N/2 complex (kz = 0..N/2-1; the kz = N/2 plane is not produced).  Inverse: half
+ * spectrum (kz = N/2 taken as zero) -> real mesh, normalised by 1/N^3.  `in` is not modified
+ * by the forward transform; the inverse overwrites `in`.                                   */
+pkm_status pkm_fft3d_forward(pkm_plan* plan, const void* in_real_dev, void* out_half_dev);
+pkm_status pkm_fft3d_inverse(pkm_plan* plan, void* in_half_dev, void* out_real_dev);
+
+/* Copy a resident plan buffer to host memory (test hook):
+ *   which = 0: painted mesh D1 (real N^3), 1: interlaced mesh D2 (real N^3),
+ *           2: combined field C (half spectrum N x N x N/2 complex),
+ *           3: D_c, the field that is harmonically weighted (real N^3).
+ * bytes must equal the buffer size (N^3 or N^3 complex/2 elements of the plan precision). */
+pkm_status pkm_plan_read_buffer(pkm_plan* plan, int32_t which, void* host_dst, size_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PKM_H */

@@ -1,0 +1,222 @@
+// Device-side building blocks shared by the estimator's kernels (gfx950, wave64):
+// complex arithmetic, small-radix DFTs, an LDS-resident Stockham FFT over a batch of
+// lines, the real/complex packing of a real-input transform, the real spherical-harmonic
+// recurrence and the integer k-bin search.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pkm {
+
+template <typename T> struct vec2;
+template <> struct vec2<float> { using type = float2; };
+template <> struct vec2<double> { using type = double2; };
+template <typename T> using cx = typename vec2<T>::type;
+
+template <typename T> __device__ __forceinline__ cx<T> mk(T re, T im) { cx<T> r; r.x = re; r.y = im; return r; }
+template <typename T> __device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T> __device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T> __device__ __forceinline__ cx<T> cconj(cx<T> a) { return mk<T>(a.x, -a.y); }
+template <typename T> __device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV> __device__ __forceinline__ cx<T> rot_mi(cx<T> a) {
+  return INV ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
+}
+
+// ---------------------------------------------------------------------------------------
+// Radix-R DFT on registers: y_s = sum_t x_t exp(-+2 pi i s t / R), R in {2,3,4,6,8}.
+// ---------------------------------------------------------------------------------------
+template <typename T, bool INV> __device__ __forceinline__ void dft2(cx<T>* v) {
+  cx<T> a = v[0], b = v[1];
+  v[0] = cadd<T>(a, b);
+  v[1] = csub<T>(a, b);
+}
+
+template <typename T, bool INV> __device__ __forceinline__ void dft4(cx<T>* v) {
+  cx<T> a0 = cadd<T>(v[0], v[2]), b0 = csub<T>(v[0], v[2]);
+  cx<T> a1 = cadd<T>(v[1], v[3]), b1 = rot_mi<T, INV>(csub<T>(v[1], v[3]));
+  v[0] = cadd<T>(a0, a1);
+  v[2] = csub<T>(a0, a1);
+  v[1] = cadd<T>(b0, b1);
+  v[3] = csub<T>(b0, b1);
+}
+
+template <typename T, bool INV> __device__ __forceinline__ void dft3(cx<T>* v) {
+  const T h = T(0.5);
+  const T s3 = INV ? T(-0.86602540378443864676) : T(0.86602540378443864676);
+  cx<T> t1 = cadd<T>(v[1], v[2]);
+  cx<T> t2 = csub<T>(v[1], v[2]);
+  cx<T> m = mk<T>(v[0].x - h * t1.x, v[0].y - h * t1.y);
+  // forward: y1 = m - i s3 t2, y2 = m + i s3 t2
+  cx<T> it = mk<T>(s3 * t2.y, -s3 * t2.x);  // -i * s3 * t2
+  v[0] = cadd<T>(v[0], t1);
+  v[1] = cadd<T>(m, it);
+  v[2] = csub<T>(m, it);
+}
+
+template <typename T, bool INV> __device__ __forceinline__ void dft6(cx<T>* v) {
+  // split t -> (t, t+3): a_t = x_t + x_{t+3}, b_t = (x_t - x_{t+3}) W6^t
+  cx<T> a[3], b[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    a[t] = cadd<T>(v[t], v[t + 3]);
+    b[t] = csub<T>(v[t], v[t + 3]);
+  }
+  const T c1 = T(0.5), s1 = INV ? T(0.86602540378443864676) : T(-0.86602540378443864676);
+  b[1] = cmul<T>(b[1], mk<T>(c1, s1));    // W6^1
+  b[2] = cmul<T>(b[2], mk<T>(-c1, s1));   // W6^2
+  dft3<T, INV>(a);
+  dft3<T, INV>(b);
+  v[0] = a[0]; v[2] = a[1]; v[4] = a[2];
+  v[1] = b[0]; v[3] = b[1]; v[5] = b[2];
+}
+
+template <typename T, bool INV> __device__ __forceinline__ void dft8(cx<T>* v) {
+  cx<T> a[4], b[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    a[t] = cadd<T>(v[t], v[t + 4]);
+    b[t] = csub<T>(v[t], v[t + 4]);
+  }
+  const T r = T(0.70710678118654752440);
+  // b_t *= W8^t
+  b[1] = INV ? mk<T>(r * (b[1].x - b[1].y), r * (b[1].x + b[1].y))
+             : mk<T>(r * (b[1].x + b[1].y), r * (b[1].y - b[1].x));
+  b[2] = rot_mi<T, INV>(b[2]);
+  b[3] = INV ? mk<T>(-r * (b[3].x + b[3].y), r * (b[3].x - b[3].y))
+             : mk<T>(r * (b[3].y - b[3].x), -r * (b[3].x + b[3].y));
+  dft4<T, INV>(a);
+  dft4<T, INV>(b);
+  v[0] = a[0]; v[2] = a[1]; v[4] = a[2]; v[6] = a[3];
+  v[1] = b[0]; v[3] = b[1]; v[5] = b[2]; v[7] = b[3];
+}
+
+template <typename T, int R, bool INV> __device__ __forceinline__ void dft_r(cx<T>* v) {
+  if constexpr (R == 2) dft2<T, INV>(v);
+  else if constexpr (R == 3) dft3<T, INV>(v);
+  else if constexpr (R == 4) dft4<T, INV>(v);
+  else if constexpr (R == 6) dft6<T, INV>(v);
+  else dft8<T, INV>(v);
+}
+
+// ---------------------------------------------------------------------------------------
+// Stockham (decimation-in-time, autosorting) FFT of a batch of lines resident in LDS.
+// Element i of a line sits at lds[off + i*es].  Each line is processed by Pt = L/E threads;
+// this thread is number t of its line.  At a stage of radix R and span m, butterfly b
+// (b = t + q*Pt, q < E/R) reads x_s = in[b + s L/R], multiplies by W_{mR}^{s k} (k = b mod m),
+// applies the radix-R DFT and writes y_s to out[(b/m) m R + k + s m].  The stage runs in
+// place: all reads finish at a barrier before any write.  Twiddles come from
+// tw[j] = exp(-2 pi i j / Ntw); W_{mR}^{q} = tw[q * Ntw/(mR)].  The caller must hold a
+// barrier between filling the lines and calling this; it returns after a barrier.
+// ---------------------------------------------------------------------------------------
+template <typename T, int E, int R, bool INV>
+__device__ __forceinline__ void stockham_stage(cx<T>* lds, int off, int es, int L, int m, int t, int Pt,
+                                               const cx<T>* __restrict__ tw, int Ntw) {
+  constexpr int NB = E / R;
+  cx<T> v[E];
+  const int Lr = L / R;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int b = t + q * Pt;
+#pragma unroll
+    for (int s = 0; s < R; ++s) v[q * R + s] = lds[off + (b + s * Lr) * es];
+  }
+  __syncthreads();
+  const int step = Ntw / (m * R);
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int b = t + q * Pt;
+    const int k = b % m;
+    const int base = (b - k) * R + k;  // (b/m) m R + k
+    if (k != 0) {
+#pragma unroll
+      for (int s = 1; s < R; ++s) {
+        cx<T> w = tw[s * k * step];
+        if (INV) w.y = -w.y;
+        v[q * R + s] = cmul<T>(v[q * R + s], w);
+      }
+    }
+    dft_r<T, R, INV>(&v[q * R]);
+#pragma unroll
+    for (int s = 0; s < R; ++s) lds[off + (base + s * m) * es] = v[q * R + s];
+  }
+  __syncthreads();
+}
+
+// Radix schedule packed 4 bits per stage (stage 0 in the low bits), nst stages.
+template <typename T, int E, bool INV>
+__device__ __forceinline__ void lds_fft(cx<T>* lds, int off, int es, int L, uint32_t sched, int nst, int t, int Pt,
+                                        const cx<T>* __restrict__ tw, int Ntw) {
+  int m = 1;
+  for (int st = 0; st < nst; ++st) {
+    const int r = (sched >> (4 * st)) & 15;
+    if constexpr (E % 8 == 0) {
+      if (r == 8) { stockham_stage<T, E, 8, INV>(lds, off, es, L, m, t, Pt, tw, Ntw); m *= 8; continue; }
+    }
+    if constexpr (E % 6 == 0) {
+      if (r == 6) { stockham_stage<T, E, 6, INV>(lds, off, es, L, m, t, Pt, tw, Ntw); m *= 6; continue; }
+    }
+    if constexpr (E % 4 == 0) {
+      if (r == 4) { stockham_stage<T, E, 4, INV>(lds, off, es, L, m, t, Pt, tw, Ntw); m *= 4; continue; }
+    }
+    if constexpr (E % 3 == 0) {
+      if (r == 3) { stockham_stage<T, E, 3, INV>(lds, off, es, L, m, t, Pt, tw, Ntw); m *= 3; continue; }
+    }
+    if constexpr (E % 2 == 0) {
+      if (r == 2) { stockham_stage<T, E, 2, INV>(lds, off, es, L, m, t, Pt, tw, Ntw); m *= 2; continue; }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Real spherical harmonics in Cartesian form, no trigonometry:
+//   Y_lm(u) = q_l^{|m|}(u_z) * Re/Im[(u_x + i u_y)^{|m|}]   (Re for m >= 0, Im for m < 0)
+// where q_l^m = N_lm P_l^m(t) / (1 - t^2)^{m/2} obeys
+//   q_m^m = c_m,  q_{m+1}^m = a_{m+1,m} t q_m^m,  q_l^m = a_lm t q_{l-1}^m - b_lm q_{l-2}^m.
+// The coefficient table (built in FP64 on the host, rounded to T) is laid out per |m|:
+// tab[m*STRIDE + 0] = c_m, tab[m*STRIDE + 2*(l-m)-1] = a_lm, tab[m*STRIDE + 2*(l-m)] = b_lm.
+// ---------------------------------------------------------------------------------------
+constexpr int YLM_LMAX = 16;
+constexpr int YLM_STRIDE = 2 * YLM_LMAX + 2;
+
+template <typename T>
+__device__ __forceinline__ T ylm_eval(int ell, int m, T ux, T uy, T uz, const T* __restrict__ tab) {
+  const int am = m < 0 ? -m : m;
+  // (ux + i uy)^am
+  T cr = T(1), ci = T(0);
+  for (int j = 0; j < am; ++j) {
+    const T nr = cr * ux - ci * uy;
+    ci = cr * uy + ci * ux;
+    cr = nr;
+  }
+  const T* c = tab + am * YLM_STRIDE;
+  T q0 = c[0];
+  if (ell > am) {
+    T q1 = c[1] * uz * q0;
+    for (int l = am + 2; l <= ell; ++l) {
+      const int j = l - am;
+      const T q2 = c[2 * j - 1] * uz * q1 - c[2 * j] * q0;
+      q0 = q1;
+      q1 = q2;
+    }
+    q0 = q1;
+  }
+  return q0 * (m >= 0 ? cr : ci);
+}
+
+// Bin index of an integer squared wavenumber: largest i with thr[i] <= n2, if i < nb; else -1.
+__device__ __forceinline__ int kbin_of(long long n2, const long long* __restrict__ thr, int nb) {
+  if (n2 < thr[0] || n2 >= thr[nb]) return -1;
+  int lo = 0, hi = nb;  // thr[lo] <= n2 < thr[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (thr[mid] <= n2) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace pkm

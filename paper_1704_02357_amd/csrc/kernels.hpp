@@ -1,0 +1,85 @@
+// Launch wrappers for the estimator's HIP kernels (definitions in kernels_*.hip).
+// Every wrapper enqueues on the given stream and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pkm {
+
+struct FftShape {
+  int n;            // mesh side N
+  int e_col;        // elements per thread for the length-N column transforms
+  int e_z;          // elements per thread for the length-N/2 line transforms
+  uint32_t sched_col;  // radix schedule (4 bits per stage) for length N
+  int nst_col;
+  uint32_t sched_z;    // radix schedule for length N/2
+  int nst_z;
+  int tile;         // columns per column-pass tile
+  int zlines;       // lines per z-pass block
+};
+
+struct BinSpec {
+  const long long* thr;  // device, nb+1 integer thresholds on |n|^2
+  int nb;
+  int hist_copies;       // per-block histogram copies (1 .. number of waves)
+};
+
+// Catalog sums: out2[0] = sum w^2, out2[1] = sum w^2 nbar (w, nbar may be null => 1).
+hipError_t launch_catalog_sums(const double* w, const double* nbar, int64_t n, double* partial, int nblk,
+                               double* out2, hipStream_t s);
+
+template <typename T> hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s);
+
+// Mass assignment of one catalog onto d1 (and d2 at +1/2 cell when d2 != null).
+template <typename T>
+hipError_t launch_paint(const double* pos, const double* w, int64_t n, double wscale, const double* origin,
+                        double scale, int nmesh, int window, T* d1, T* d2, hipStream_t s);
+
+// Forward real-to-half-complex transform along z of nbuf real meshes (nbuf <= 2).
+template <typename T>
+hipError_t launch_zfwd(const FftShape& fs, const T* in0, const T* in1, void* out0, void* out1, int nbuf,
+                       const void* tw, hipStream_t s);
+
+// Column transform along y (axis = 1) or x (axis = 0) of nbuf half-spectra in place.
+template <typename T>
+hipError_t launch_col(const FftShape& fs, void* const* bufs_dev, int nbuf, int axis, bool inverse,
+                      const void* tw, hipStream_t s);
+
+// x-pass of the forward transforms of the two painted meshes, interlace combine,
+// compensation and Nyquist zeroing; writes C and, when g_out != null, G = C inverse-
+// transformed along x.
+template <typename T>
+hipError_t launch_xcombine(const FftShape& fs, void* s1, void* s2, void* c_out, void* g_out, int interlaced,
+                           int compensated, const void* invw, const void* phase, const void* tw, hipStream_t s);
+
+// Inverse z (half-complex to real) of G, scaled to D_c, then for every field f in the group
+// the Y_lm(xhat)-weighted forward transform along z into bufs[f].  If real_in != null the
+// field D_c is read directly from that real mesh instead.  If real_out != null D_c is also
+// written there.
+template <typename T>
+hipError_t launch_zpre(const FftShape& fs, const void* g_in, const T* real_in, T* real_out, void* const* bufs_dev,
+                       int nf, const int* fields_dev, double scale, const double* off, double h, const void* ytab,
+                       const void* tw, hipStream_t s);
+
+// x-pass of every field of the group, sum over m of Y_lm(khat) B_lm per multipole slot,
+// product with C and binning.  Per block the partial sums are rows of nb bins:
+// [count, sum |k|, sum |C|^2] when with_l0, then one row of sum 4 pi Y Re[C conj B] per slot.
+template <typename T>
+hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const int* fields_dev, int nslots,
+                        int with_l0, const void* c_in, const void* ytab, const BinSpec& bs, double kf,
+                        double* partial, int* nblocks_out, const void* tw, hipStream_t s);
+
+// out[map[v]] (+)= sum_b partial[b*nvals + v] (map null -> identity), fixed order.
+hipError_t launch_reduce(const double* partial, int nblocks, int nvals, double* out, const int* map, int accumulate,
+                         hipStream_t s);
+
+// Global line of sight: (k, mu) cells; partial[block][cell*2 + {0: sum w, 1: sum w |C|^2}].
+template <typename T>
+hipError_t launch_kmu(const FftShape& fs, const void* c_in, const double* los, const BinSpec& bs,
+                      const double* mu_edges, int nmu, double* partial, int nblk, hipStream_t s);
+
+int xpass_blocks(const FftShape& fs);
+int xpass_threads(const FftShape& fs);
+
+}  // namespace pkm

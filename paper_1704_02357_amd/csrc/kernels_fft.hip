@@ -1,0 +1,581 @@
+// Transform passes of the multipole estimator (Sec. 2.1 eq. Pell-ours / eq. Fell, Sec. 2.3).
+//
+// Data layout.  A real mesh is R[x][y][z] (z contiguous).  A half spectrum is
+// H[x][y][kz] with kz in [0, N/2) contiguous: the kz = N/2 plane is never stored because
+// the combined field is zero on every Nyquist plane and those modes belong to no k bin.
+// x and y indices are frequencies in FFT order (j < N/2 -> j, else j - N).
+//
+// Passes (each one read and one write of every element, tiles staged through LDS):
+//   z pass   : real lines -> half-complex lines (length-N/2 complex FFT + split), optional
+//              pre-pass: inverse z of G to the real field D_c, then Y_lm(xhat) weighting
+//              and forward z for every field of a group.
+//   column   : length-N transforms along y or x over tiles of `tile` adjacent kz columns.
+//   xcombine : forward x of both painted meshes + interlace combine + compensation +
+//              Nyquist zero + l = 0 binning, then inverse x of C.
+//   xpost    : forward x of every field of a group, sum_m Y_lm(khat) B_lm, product with
+//              C, and binning into per-block partial sums.
+#include "kernels.hpp"
+#include "device_common.hpp"
+
+namespace pkm {
+
+namespace {
+
+constexpr double FOUR_PI = 12.566370614359172953850573533118;
+
+template <typename T> __device__ __forceinline__ cx<T> ld(const void* p, size_t i) {
+  return reinterpret_cast<const cx<T>*>(p)[i];
+}
+template <typename T> __device__ __forceinline__ void st(void* p, size_t i, cx<T> v) {
+  reinterpret_cast<cx<T>*>(p)[i] = v;
+}
+
+// Forward split of a packed half-length transform: X_k = E_k + W_N^k O_k.
+template <typename T>
+__device__ __forceinline__ cx<T> r2c_split(const cx<T>* line, int k, int nh, const cx<T>* __restrict__ tw) {
+  const cx<T> zk = line[k];
+  const cx<T> zm = cconj<T>(line[k == 0 ? 0 : nh - k]);
+  const cx<T> e = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y + zm.y));
+  const cx<T> d = mk<T>(T(0.5) * (zk.x - zm.x), T(0.5) * (zk.y - zm.y));
+  const cx<T> o = mk<T>(d.y, -d.x);  // d / i
+  return cadd<T>(e, cmul<T>(tw[k], o));
+}
+
+// Inverse split: Z_k = E_k + i O_k with E_k = (X_k + conj X_{nh-k})/2,
+// O_k = (X_k - conj X_{nh-k}) conj(W_N^k) / 2; X_{nh} = 0 and X_0 taken real.
+template <typename T>
+__device__ __forceinline__ cx<T> c2r_split(const cx<T>* line, int k, int nh, const cx<T>* __restrict__ tw) {
+  cx<T> xk = line[k];
+  cx<T> xp;
+  if (k == 0) {
+    xk.y = T(0);
+    xp = mk<T>(T(0), T(0));
+  } else {
+    xp = cconj<T>(line[nh - k]);
+  }
+  const cx<T> e = mk<T>(T(0.5) * (xk.x + xp.x), T(0.5) * (xk.y + xp.y));
+  const cx<T> d = mk<T>(T(0.5) * (xk.x - xp.x), T(0.5) * (xk.y - xp.y));
+  const cx<T> o = cmul<T>(d, cconj<T>(tw[k]));
+  return mk<T>(e.x - o.y, e.y + o.x);  // e + i o
+}
+
+// ------------------------------------------------------------------------------------------
+// z pass, forward (real -> half complex)
+// ------------------------------------------------------------------------------------------
+constexpr int ZMAX_THREADS = 256;
+constexpr int XMAX_THREADS = 512;
+
+template <typename T, int E>
+__global__ void __launch_bounds__(ZMAX_THREADS) k_zfwd(int n, int G, uint32_t sched, int nst, const T* __restrict__ in0, const T* __restrict__ in1,
+                       void* __restrict__ out0, void* __restrict__ out1, const cx<T>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+  const int nh = n >> 1;
+  const int lp = nh + 1;
+  const int pt = nh / E;
+  const T* in = blockIdx.y ? in1 : in0;
+  void* out = blockIdx.y ? out1 : out0;
+  const size_t line0 = (size_t)blockIdx.x * G;
+  const int tid = threadIdx.x;
+  const cx<T>* src = reinterpret_cast<const cx<T>*>(in) + line0 * nh;
+  for (int i = tid; i < G * nh; i += blockDim.x) lds[(i / nh) * lp + (i % nh)] = src[i];
+  __syncthreads();
+  const int t = tid % pt, g = tid / pt;
+  cx<T>* line = lds + g * lp;
+  lds_fft<T, E, false>(lds, g * lp, 1, nh, sched, nst, t, pt, tw, n);
+  const size_t ob = (line0 + g) * nh;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = t + pt * e;
+    st<T>(out, ob + k, r2c_split<T>(line, k, nh, tw));
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// column pass (length N along y or x), in place
+// ------------------------------------------------------------------------------------------
+template <typename T, int E, bool INV>
+__global__ void __launch_bounds__(XMAX_THREADS) k_col(int n, int tile, uint32_t sched, int nst, void* const* __restrict__ bufs, size_t row_stride,
+                      size_t outer_stride, const cx<T>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+  const int nh = n >> 1;
+  const int tiles = nh / tile;
+  const int outer = blockIdx.x / tiles;
+  const int kz0 = (blockIdx.x % tiles) * tile;
+  cx<T>* buf = reinterpret_cast<cx<T>*>(bufs[blockIdx.y]);
+  const size_t base = (size_t)outer * outer_stride + kz0;
+  const int pitch = tile + 1;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n * tile; i += blockDim.x) {
+    const int r = i / tile, c = i % tile;
+    lds[r * pitch + c] = buf[base + (size_t)r * row_stride + c];
+  }
+  __syncthreads();
+  const int pt = n / E;
+  const int c = tid % tile, t = tid / tile;
+  lds_fft<T, E, INV>(lds, c, pitch, n, sched, nst, t, pt, tw, n);
+  for (int i = tid; i < n * tile; i += blockDim.x) {
+    const int r = i / tile, cc = i % tile;
+    buf[base + (size_t)r * row_stride + cc] = lds[r * pitch + cc];
+  }
+}
+
+__device__ __forceinline__ int sfreq(int j, int n) { return j < (n >> 1) ? j : j - n; }
+
+// Histogram in LDS: `copies` copies of nvals doubles; wave w uses copy w % copies.
+__device__ __forceinline__ void hist_zero(double* h, int total) {
+  for (int i = threadIdx.x; i < total; i += blockDim.x) h[i] = 0.0;
+}
+__device__ __forceinline__ void hist_flush(const double* h, int copies, int nvals, double* out) {
+  for (int v = threadIdx.x; v < nvals; v += blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < copies; ++c) s += h[c * nvals + v];
+    out[v] = s;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// x pass of the painted meshes + combine + l=0 bin + inverse x of C
+// ------------------------------------------------------------------------------------------
+template <typename T, int E>
+__global__ void __launch_bounds__(XMAX_THREADS) k_xcombine(int n, int tile, uint32_t sched, int nst, const cx<T>* __restrict__ s1,
+                           const cx<T>* __restrict__ s2, cx<T>* __restrict__ cout, cx<T>* __restrict__ gout,
+                           int interlaced, int compensated, const T* __restrict__ invw,
+                           const cx<T>* __restrict__ phase, const cx<T>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nh = n >> 1;
+  const int pitch = tile + 1;
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+  const int tiles = nh / tile;
+  const int y = blockIdx.x / tiles;
+  const int kz0 = (blockIdx.x % tiles) * tile;
+  const size_t rs = (size_t)n * nh;
+  const size_t base = (size_t)y * nh + kz0;
+  const int tid = threadIdx.x;
+  const int pt = n / E;
+  const int c = tid % tile, t = tid / tile;
+  const int kz = kz0 + c;
+  cx<T> a1[E];
+  for (int i = tid; i < n * tile; i += blockDim.x) {
+    const int r = i / tile, cc = i % tile;
+    lds[r * pitch + cc] = s1[base + (size_t)r * rs + cc];
+  }
+  __syncthreads();
+  lds_fft<T, E, false>(lds, c, pitch, n, sched, nst, t, pt, tw, n);
+#pragma unroll
+  for (int e = 0; e < E; ++e) a1[e] = lds[(t + pt * e) * pitch + c];
+  if (interlaced) {
+    __syncthreads();
+    for (int i = tid; i < n * tile; i += blockDim.x) {
+      const int r = i / tile, cc = i % tile;
+      lds[r * pitch + cc] = s2[base + (size_t)r * rs + cc];
+    }
+    __syncthreads();
+    lds_fft<T, E, false>(lds, c, pitch, n, sched, nst, t, pt, tw, n);
+    const cx<T> pyz = cmul<T>(phase[y], phase[kz]);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int x = t + pt * e;
+      const cx<T> b = cmul<T>(lds[x * pitch + c], cmul<T>(phase[x], pyz));
+      a1[e] = mk<T>(T(0.5) * (a1[e].x + b.x), T(0.5) * (a1[e].y + b.y));
+    }
+  }
+  const bool ynyq = (y == nh);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int x = t + pt * e;
+    cx<T> v = a1[e];
+    if (compensated) v = cscale<T>(v, invw[x] * invw[y] * invw[kz]);
+    if (ynyq || x == nh) v = mk<T>(T(0), T(0));
+    a1[e] = v;
+    cout[base + c + (size_t)x * rs] = v;
+  }
+  if (gout == nullptr) return;
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) lds[(t + pt * e) * pitch + c] = a1[e];
+  __syncthreads();
+  lds_fft<T, E, true>(lds, c, pitch, n, sched, nst, t, pt, tw, n);
+  for (int i = tid; i < n * tile; i += blockDim.x) {
+    const int r = i / tile, cc = i % tile;
+    gout[base + (size_t)r * rs + cc] = lds[r * pitch + cc];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// z pre-pass: D_c from G (inverse z), then weighted forward z for every field of the group
+// ------------------------------------------------------------------------------------------
+template <typename T, int E>
+__global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n, int G, uint32_t sched, int nst, const cx<T>* __restrict__ gin,
+                       const T* __restrict__ real_in, T* __restrict__ real_out, void* const* __restrict__ bufs,
+                       int nf, const int* __restrict__ fields, T scale, double off0, double off1, double off2,
+                       double h, const T* __restrict__ ytab, const cx<T>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+  const int nh = n >> 1;
+  const int lp = nh + 1;
+  const int pt = nh / E;
+  const size_t line0 = (size_t)blockIdx.x * G;
+  const int tid = threadIdx.x;
+  const int t = tid % pt, g = tid / pt;
+  const size_t lineg = line0 + g;
+  cx<T>* line = lds + g * lp;
+  T r[2 * E];
+  if (real_in) {
+    const cx<T>* src = reinterpret_cast<const cx<T>*>(real_in) + lineg * nh;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const cx<T> v = src[t + pt * e];
+      r[2 * e] = v.x;
+      r[2 * e + 1] = v.y;
+    }
+  } else {
+    const cx<T>* src = gin + line0 * nh;
+    for (int i = tid; i < G * nh; i += blockDim.x) lds[(i / nh) * lp + (i % nh)] = src[i];
+    __syncthreads();
+    cx<T> z[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) z[e] = c2r_split<T>(line, t + pt * e, nh, tw);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) line[t + pt * e] = z[e];
+    __syncthreads();
+    lds_fft<T, E, true>(lds, g * lp, 1, nh, sched, nst, t, pt, tw, n);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const cx<T> v = line[t + pt * e];
+      r[2 * e] = v.x * scale;
+      r[2 * e + 1] = v.y * scale;
+    }
+    if (real_out) {
+      cx<T>* dst = reinterpret_cast<cx<T>*>(real_out) + lineg * nh;
+#pragma unroll
+      for (int e = 0; e < E; ++e) dst[t + pt * e] = mk<T>(r[2 * e], r[2 * e + 1]);
+    }
+    __syncthreads();
+  }
+  if (nf == 0) return;
+  // distance from the observer to this thread's nodes (x, y fixed by the line)
+  const int ix = (int)(lineg / n), iy = (int)(lineg % n);
+  const T px = (T)(off0 + ix * h), py = (T)(off1 + iy * h);
+  const T pxy2 = px * px + py * py;
+  T inv[2 * E];
+#pragma unroll
+  for (int q = 0; q < 2 * E; ++q) {
+    const int iz = 2 * (t + pt * (q >> 1)) + (q & 1);
+    const T pz = (T)(off2 + iz * h);
+    const T rr = sqrt(pxy2 + pz * pz);
+    inv[q] = rr > T(0) ? T(1) / rr : T(0);
+  }
+  for (int f = 0; f < nf; ++f) {
+    const int ell = fields[3 * f], m = fields[3 * f + 1];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      T yv[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const T iv = inv[2 * e + q];
+        const T pz = (T)(off2 + (2 * (t + pt * e) + q) * h);
+        yv[q] = iv > T(0) ? ylm_eval<T>(ell, m, px * iv, py * iv, pz * iv, ytab) : T(0);
+      }
+      line[t + pt * e] = mk<T>(r[2 * e] * yv[0], r[2 * e + 1] * yv[1]);
+    }
+    __syncthreads();
+    lds_fft<T, E, false>(lds, g * lp, 1, nh, sched, nst, t, pt, tw, n);
+    void* out = bufs[f];
+    const size_t ob = lineg * nh;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int k = t + pt * e;
+      st<T>(out, ob + k, r2c_split<T>(line, k, nh, tw));
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// x post-pass: forward x of each field, sum_m Y_lm(khat) B, product with C, binning
+// ------------------------------------------------------------------------------------------
+constexpr int MAX_SLOTS = 2;
+
+template <typename T, int E>
+__global__ void __launch_bounds__(XMAX_THREADS) k_xpost(int n, int tile, uint32_t sched, int nst, void* const* __restrict__ bufs, int nf,
+                        const int* __restrict__ fields, int nslots, int with_l0, double kf,
+                        const cx<T>* __restrict__ cin, const T* __restrict__ ytab,
+                        const long long* __restrict__ thr, int nb, int copies, double* __restrict__ partial,
+                        const cx<T>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nh = n >> 1;
+  const int pitch = tile + 1;
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+  double* hist = reinterpret_cast<double*>(smem + sizeof(cx<T>) * (size_t)n * pitch);
+  const int l0rows = with_l0 ? 3 : 0;
+  const int nvals = (l0rows + nslots) * nb;
+  hist_zero(hist, copies * nvals);
+  __syncthreads();
+  const int tiles = nh / tile;
+  const int y = blockIdx.x / tiles;
+  const int kz0 = (blockIdx.x % tiles) * tile;
+  const size_t rs = (size_t)n * nh;
+  const size_t base = (size_t)y * nh + kz0;
+  const int tid = threadIdx.x;
+  const int pt = n / E;
+  const int c = tid % tile, t = tid / tile;
+  const int kz = kz0 + c;
+  const int fy = sfreq(y, n);
+  T kinv[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int fx = sfreq(t + pt * e, n);
+    const T n2 = (T)fx * (T)fx + (T)fy * (T)fy + (T)kz * (T)kz;
+    kinv[e] = n2 > T(0) ? T(1) / sqrt(n2) : T(0);
+  }
+  cx<T> acc[MAX_SLOTS][E];
+#pragma unroll
+  for (int s = 0; s < MAX_SLOTS; ++s)
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[s][e] = mk<T>(T(0), T(0));
+  for (int f = 0; f < nf; ++f) {
+    const cx<T>* b = reinterpret_cast<const cx<T>*>(bufs[f]);
+    for (int i = tid; i < n * tile; i += blockDim.x) {
+      const int r = i / tile, cc = i % tile;
+      lds[r * pitch + cc] = b[base + (size_t)r * rs + cc];
+    }
+    __syncthreads();
+    lds_fft<T, E, false>(lds, c, pitch, n, sched, nst, t, pt, tw, n);
+    const int ell = fields[3 * f], m = fields[3 * f + 1], slot = fields[3 * f + 2];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const cx<T> v = lds[(t + pt * e) * pitch + c];
+      const T ki = kinv[e];
+      const T yv = ylm_eval<T>(ell, m, (T)sfreq(t + pt * e, n) * ki, (T)fy * ki, (T)kz * ki, ytab);
+      if (slot == 0) acc[0][e] = mk<T>(acc[0][e].x + yv * v.x, acc[0][e].y + yv * v.y);
+      else acc[1][e] = mk<T>(acc[1][e].x + yv * v.x, acc[1][e].y + yv * v.y);
+    }
+    __syncthreads();
+  }
+  const int wave = tid >> 6;
+  double* h = hist + (wave % copies) * nvals;
+  const bool ynyq = (y == nh);
+  const double omega = (kz == 0) ? 1.0 : 2.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int x = t + pt * e;
+    const int fx = sfreq(x, n);
+    const long long n2 = (long long)fx * fx + (long long)fy * fy + (long long)kz * kz;
+    if (ynyq || x == nh || n2 == 0) continue;
+    const int bin = kbin_of(n2, thr, nb);
+    if (bin < 0) continue;
+    const cx<T> cv = cin[base + c + (size_t)x * rs];
+    if (with_l0) {
+      atomicAdd(&h[bin], omega);
+      atomicAdd(&h[nb + bin], omega * kf * sqrt((double)n2));
+      atomicAdd(&h[2 * nb + bin], omega * ((double)cv.x * (double)cv.x + (double)cv.y * (double)cv.y));
+    }
+    for (int s = 0; s < nslots; ++s) {
+      const cx<T> a = s == 0 ? acc[0][e] : acc[1][e];
+      const double q = FOUR_PI * ((double)cv.x * (double)a.x + (double)cv.y * (double)a.y);
+      atomicAdd(&h[(l0rows + s) * nb + bin], omega * q);
+    }
+  }
+  __syncthreads();
+  hist_flush(hist, copies, nvals, partial + (size_t)blockIdx.x * nvals);
+}
+
+// ------------------------------------------------------------------------------------------
+// fixed-order reduction of per-block partial sums
+// ------------------------------------------------------------------------------------------
+constexpr int RED_THREADS = 256;
+__global__ void __launch_bounds__(RED_THREADS) k_reduce(const double* __restrict__ partial, int nblocks, int nvals,
+                                                        double* __restrict__ out, const int* __restrict__ map,
+                                                        int accumulate) {
+  __shared__ double s[RED_THREADS];
+  const int v = blockIdx.x;
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) a += partial[(size_t)b * nvals + v];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int h = RED_THREADS / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int o = map ? map[v] : v;
+    out[o] = accumulate ? out[o] + s[0] : s[0];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// global line of sight (k, mu) binning of |C|^2
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_kmu(int n, const cx<T>* __restrict__ cin, double l0, double l1, double l2,
+                      const long long* __restrict__ thr, int nb, const double* __restrict__ mue, int nmu,
+                      double* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* hist = reinterpret_cast<double*>(smem);
+  const int nvals = 2 * nb * nmu;
+  hist_zero(hist, nvals);
+  __syncthreads();
+  const int nh = n >> 1;
+  const size_t total = (size_t)n * n * nh;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int kz = (int)(i % nh);
+    const size_t xy = i / nh;
+    const int y = (int)(xy % n), x = (int)(xy / n);
+    if (x == nh || y == nh) continue;
+    const int fx = sfreq(x, n), fy = sfreq(y, n);
+    const long long n2 = (long long)fx * fx + (long long)fy * fy + (long long)kz * kz;
+    if (n2 == 0) continue;
+    const int kb = kbin_of(n2, thr, nb);
+    if (kb < 0) continue;
+    const double dot = __dadd_rn(__dadd_rn(__dmul_rn((double)fx, l0), __dmul_rn((double)fy, l1)),
+                                 __dmul_rn((double)kz, l2));
+    const double mu = __ddiv_rn(fabs(dot), __dsqrt_rn((double)n2));
+    // mu bin: last edge <= mu -> last bin; else largest j with mue[j] <= mu
+    int mb;
+    if (mu >= mue[nmu]) mb = nmu - 1;
+    else if (mu < mue[0]) mb = -1;
+    else {
+      int lo = 0, hi = nmu;
+      while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (mue[mid] <= mu) lo = mid; else hi = mid; }
+      mb = lo;
+    }
+    if (mb < 0) continue;
+    const cx<T> v = cin[i];
+    const double p2 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+    const double omega = (kz == 0) ? 1.0 : 2.0;
+    const int cell = kb * nmu + mb;
+    atomicAdd(&hist[2 * cell], omega);
+    atomicAdd(&hist[2 * cell + 1], omega * p2);
+  }
+  __syncthreads();
+  hist_flush(hist, 1, nvals, partial + (size_t)blockIdx.x * nvals);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------------
+static int zthreads(const FftShape& fs) { return (fs.n / 2 / fs.e_z) * fs.zlines; }
+static size_t zsmem(const FftShape& fs, size_t cs) { return cs * (size_t)fs.zlines * (fs.n / 2 + 1); }
+int xpass_threads(const FftShape& fs) { return (fs.n / fs.e_col) * fs.tile; }
+int xpass_blocks(const FftShape& fs) { return fs.n * ((fs.n / 2) / fs.tile); }
+static size_t colsmem(const FftShape& fs, size_t cs) { return cs * (size_t)fs.n * (fs.tile + 1); }
+
+#define PKM_DISPATCH_E(EVAL, CALL)            \
+  switch (EVAL) {                             \
+    case 4: { constexpr int E = 4; CALL; break; }   \
+    case 6: { constexpr int E = 6; CALL; break; }   \
+    case 8: { constexpr int E = 8; CALL; break; }   \
+    case 12: { constexpr int E = 12; CALL; break; } \
+    case 16: { constexpr int E = 16; CALL; break; } \
+    default: return hipErrorInvalidValue;     \
+  }
+
+template <typename T>
+hipError_t launch_zfwd(const FftShape& fs, const T* in0, const T* in1, void* out0, void* out1, int nbuf,
+                       const void* tw, hipStream_t s) {
+  const int lines = fs.n * fs.n;
+  dim3 grid(lines / fs.zlines, nbuf);
+  const size_t sm = zsmem(fs, sizeof(cx<T>));
+  PKM_DISPATCH_E(fs.e_z, (k_zfwd<T, E><<<grid, zthreads(fs), sm, s>>>(fs.n, fs.zlines, fs.sched_z, fs.nst_z, in0, in1,
+                                                                      out0, out1, (const cx<T>*)tw)));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_col(const FftShape& fs, void* const* bufs_dev, int nbuf, int axis, bool inverse, const void* tw,
+                      hipStream_t s) {
+  const size_t nh = fs.n / 2;
+  const size_t row_stride = axis == 1 ? nh : (size_t)fs.n * nh;
+  const size_t outer_stride = axis == 1 ? (size_t)fs.n * nh : nh;
+  dim3 grid(xpass_blocks(fs), nbuf);
+  const size_t sm = colsmem(fs, sizeof(cx<T>));
+  if (inverse) {
+    PKM_DISPATCH_E(fs.e_col, (k_col<T, E, true><<<grid, xpass_threads(fs), sm, s>>>(
+                                  fs.n, fs.tile, fs.sched_col, fs.nst_col, bufs_dev, row_stride, outer_stride,
+                                  (const cx<T>*)tw)));
+  } else {
+    PKM_DISPATCH_E(fs.e_col, (k_col<T, E, false><<<grid, xpass_threads(fs), sm, s>>>(
+                                  fs.n, fs.tile, fs.sched_col, fs.nst_col, bufs_dev, row_stride, outer_stride,
+                                  (const cx<T>*)tw)));
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xcombine(const FftShape& fs, void* s1, void* s2, void* c_out, void* g_out, int interlaced,
+                           int compensated, const void* invw, const void* phase, const void* tw, hipStream_t s) {
+  const size_t sm = colsmem(fs, sizeof(cx<T>));
+  PKM_DISPATCH_E(fs.e_col, (k_xcombine<T, E><<<xpass_blocks(fs), xpass_threads(fs), sm, s>>>(
+                               fs.n, fs.tile, fs.sched_col, fs.nst_col, (const cx<T>*)s1, (const cx<T>*)s2,
+                               (cx<T>*)c_out, (cx<T>*)g_out, interlaced, compensated, (const T*)invw,
+                               (const cx<T>*)phase, (const cx<T>*)tw)));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zpre(const FftShape& fs, const void* g_in, const T* real_in, T* real_out, void* const* bufs_dev,
+                       int nf, const int* fields_dev, double scale, const double* off, double h, const void* ytab,
+                       const void* tw, hipStream_t s) {
+  const int lines = fs.n * fs.n;
+  const size_t sm = zsmem(fs, sizeof(cx<T>));
+  PKM_DISPATCH_E(fs.e_z, (k_zpre<T, E><<<lines / fs.zlines, zthreads(fs), sm, s>>>(
+                             fs.n, fs.zlines, fs.sched_z, fs.nst_z, (const cx<T>*)g_in, real_in, real_out, bufs_dev,
+                             nf, fields_dev, (T)scale, off[0], off[1], off[2], h, (const T*)ytab,
+                             (const cx<T>*)tw)));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const int* fields_dev, int nslots,
+                        int with_l0, const void* c_in, const void* ytab, const BinSpec& bs, double kf,
+                        double* partial, int* nblocks_out, const void* tw, hipStream_t s) {
+  if (nslots < 0 || nslots > MAX_SLOTS) return hipErrorInvalidValue;
+  const int rows = (with_l0 ? 3 : 0) + nslots;
+  const size_t sm = colsmem(fs, sizeof(cx<T>)) + sizeof(double) * (size_t)bs.hist_copies * rows * bs.nb;
+  *nblocks_out = xpass_blocks(fs);
+  PKM_DISPATCH_E(fs.e_col, (k_xpost<T, E><<<xpass_blocks(fs), xpass_threads(fs), sm, s>>>(
+                               fs.n, fs.tile, fs.sched_col, fs.nst_col, bufs_dev, nf, fields_dev, nslots, with_l0,
+                               kf, (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies, partial,
+                               (const cx<T>*)tw)));
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partial, int nblocks, int nvals, double* out, const int* map, int accumulate,
+                         hipStream_t s) {
+  if (nvals <= 0) return hipSuccess;
+  k_reduce<<<nvals, RED_THREADS, 0, s>>>(partial, nblocks, nvals, out, map, accumulate);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_kmu(const FftShape& fs, const void* c_in, const double* los, const BinSpec& bs,
+                      const double* mu_edges, int nmu, double* partial, int nblk, hipStream_t s) {
+  const size_t sm = sizeof(double) * 2 * (size_t)bs.nb * nmu;
+  k_kmu<T><<<nblk, 256, sm, s>>>(fs.n, (const cx<T>*)c_in, los[0], los[1], los[2], bs.thr, bs.nb, mu_edges, nmu,
+                                 partial);
+  return hipGetLastError();
+}
+
+#define PKM_INST(T)                                                                                           \
+  template hipError_t launch_zfwd<T>(const FftShape&, const T*, const T*, void*, void*, int, const void*,         \
+                                     hipStream_t);                                                                \
+  template hipError_t launch_col<T>(const FftShape&, void* const*, int, int, bool, const void*, hipStream_t);    \
+  template hipError_t launch_xcombine<T>(const FftShape&, void*, void*, void*, void*, int, int, const void*,     \
+                                         const void*, const void*, hipStream_t);                                 \
+  template hipError_t launch_zpre<T>(const FftShape&, const void*, const T*, T*, void* const*, int, const int*,   \
+                                     double, const double*, double, const void*, const void*, hipStream_t);       \
+  template hipError_t launch_xpost<T>(const FftShape&, void* const*, int, const int*, int, int, const void*,     \
+                                      const void*, const BinSpec&, double, double*, int*, const void*,           \
+                                      hipStream_t);                                                              \
+  template hipError_t launch_kmu<T>(const FftShape&, const void*, const double*, const BinSpec&, const double*,   \
+                                    int, double*, int, hipStream_t);
+PKM_INST(float)
+PKM_INST(double)
+
+}  // namespace pkm

@@ -1,0 +1,924 @@
+// Plan, scheduling and C ABI of the multipole estimator (include/pkm.h).
+//
+// One plan = one mesh size, box, observer, window and precision.  pkm_paint runs
+//   catalog sums -> zero meshes -> paint (data, then -alpha x randoms) -> forward z of D1, D2
+//   -> forward y -> x pass with interlace combine + compensation (writes C and G = x-inverse
+//   of C) -> inverse y of G,
+// leaving C (the combined field, F_0 of eq. Pell-ours) and G (D_c, transformed along z only)
+// resident.  pkm_compute_multipoles then runs, per group of (l, m) fields,
+//   zpre (inverse z of G = D_c, Y_lm(xhat) weighting, forward z per field) -> forward y per
+//   field -> xpost (forward x, sum_m Y_lm(khat) B_lm, product with C, binning)
+// and one fixed-order reduction per group.  The l = 0 bin (|C|^2) and the mode counts are
+// taken in the first xpost pass.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/pkm.h"
+#include "kernels.hpp"
+#include "device_common.hpp"
+
+using namespace pkm;
+
+struct pkm_plan {
+  pkm_params p{};
+  pkm_device dev{};
+  hipStream_t stream = nullptr;
+  bool fp64 = false;
+  size_t es = 4;        // real element bytes
+  size_t mesh_bytes = 0;
+  FftShape fs{};
+  // resident buffers
+  void* d1 = nullptr;
+  void* d2 = nullptr;
+  void* s1 = nullptr;
+  void* s2 = nullptr;
+  void* c = nullptr;
+  void* g = nullptr;
+  std::vector<void*> fields;
+  void** ptrs_dev = nullptr;  // device array of buffer pointers (fields, then scratch slots)
+  int ptr_cap = 0;
+  int* ftab_dev = nullptr;    // (l, m, slot) per field, all groups
+  int ftab_cap = 0;
+  int* map_dev = nullptr;     // reduce map per value
+  int map_cap = 0;
+  void* tw = nullptr;
+  void* ytab = nullptr;
+  void* invw = nullptr;
+  void* phase = nullptr;
+  long long* thr_dev = nullptr;
+  int thr_cap = 0;
+  double* partial = nullptr;
+  size_t partial_cap = 0;  // doubles
+  double* out_dev = nullptr;
+  size_t out_cap = 0;
+  double* sums_dev = nullptr;  // 4 doubles + block partials
+  double* cat_dev = nullptr;   // staging for host catalogs
+  size_t cat_cap = 0;          // doubles
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // state
+  bool painted = false;
+  double alpha = 0, norm_I = 0, shot = 0;
+  int n_transforms = 0;
+  std::string err;
+  pkm_stats_t stats{};
+  int64_t bytes = 0;
+  std::unordered_map<void*, size_t> sizes;
+  // per-launch stage timing
+  bool stage_timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  size_t ev_used = 0;
+};
+
+namespace {
+
+constexpr int SUM_BLOCKS = 1024;
+
+struct Fail {
+  pkm_status st;
+};
+
+bool is_smooth(int n) {
+  if (n < 16 || n > 1024 || n % 4) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+// Radix schedule for length L with E elements per thread; radices must divide E.
+bool make_sched(int L, int E, uint32_t* sched, int* nst) {
+  static const int rad[] = {8, 6, 4, 3, 2};
+  int rem = L, k = 0;
+  uint32_t s = 0;
+  while (rem > 1) {
+    bool found = false;
+    for (int r : rad) {
+      if (E % r == 0 && rem % r == 0) {
+        s |= (uint32_t)r << (4 * k);
+        ++k;
+        rem /= r;
+        found = true;
+        break;
+      }
+    }
+    if (!found || k > 8) return false;
+  }
+  *sched = s;
+  *nst = k;
+  return L % E == 0;
+}
+
+int pick_e(int L) {
+  if ((L & (L - 1)) == 0) return L >= 256 ? 16 : (L >= 8 ? 8 : 4);
+  if (L % 12 == 0) return 12;
+  if (L % 6 == 0) return 6;
+  return 0;
+}
+
+void check_hip(pkm_plan* pl, hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (pl) pl->err = std::string(what) + " failed: " + hipGetErrorString(e);
+    throw Fail{e == hipErrorOutOfMemory ? PKM_ENOMEM : PKM_EDEVICE};
+  }
+}
+
+// Stage timing: events bracket each launch when enabled; resolved after the stream syncs.
+struct StageScope {
+  pkm_plan* pl;
+  int stage;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipEvent_t take() {
+    if (pl->ev_used == pl->ev_pool.size()) {
+      hipEvent_t e;
+      check_hip(pl, hipEventCreate(&e), "event");
+      pl->ev_pool.push_back(e);
+    }
+    return pl->ev_pool[pl->ev_used++];
+  }
+  StageScope(pkm_plan* p, int s) : pl(p), stage(s) {
+    if (!pl->stage_timing) return;
+    a = take();
+    b = take();
+    check_hip(pl, hipEventRecord(a, pl->stream), "event");
+  }
+  ~StageScope() {
+    if (!a) return;
+    if (hipEventRecord(b, pl->stream) == hipSuccess) pl->pending.push_back({stage, {a, b}});
+  }
+};
+
+void resolve_stages(pkm_plan* pl) {
+  for (auto& pe : pl->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
+      pl->stats.stage_ms[pe.first] += ms;
+      pl->stats.stage_launches[pe.first] += 1;
+    }
+  }
+  pl->pending.clear();
+  pl->ev_used = 0;
+}
+
+void* dalloc(pkm_plan* pl, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  void* ptr = nullptr;
+  if (pl->dev.alloc) {
+    ptr = pl->dev.alloc(bytes, pl->dev.hip_stream, pl->dev.alloc_ctx);
+    if (!ptr) {
+      pl->err = "device allocation of " + std::to_string(bytes) + " bytes failed";
+      throw Fail{PKM_ENOMEM};
+    }
+  } else {
+    hipError_t e = hipMalloc(&ptr, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      pl->err = "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e);
+      throw Fail{PKM_ENOMEM};
+    }
+  }
+  pl->bytes += (int64_t)bytes;
+  pl->sizes[ptr] = bytes;
+  return ptr;
+}
+
+void dfree(pkm_plan* pl, void* ptr) {
+  if (!ptr) return;
+  auto it = pl->sizes.find(ptr);
+  if (it != pl->sizes.end()) {
+    pl->bytes -= (int64_t)it->second;
+    pl->sizes.erase(it);
+  }
+  if (pl->dev.free) pl->dev.free(ptr, pl->dev.hip_stream, pl->dev.alloc_ctx);
+  else (void)hipFree(ptr);
+}
+
+template <typename T> void upload_tables(pkm_plan* pl) {
+  const int n = pl->p.nmesh;
+  std::vector<T> tw(2 * (size_t)n), invw(n), ph(2 * (size_t)n);
+  for (int j = 0; j < n; ++j) {
+    const double a = 2.0 * M_PI * (double)j / (double)n;
+    tw[2 * j] = (T)std::cos(a);
+    tw[2 * j + 1] = (T)(-std::sin(a));
+    const int f = j < n / 2 ? j : j - n;
+    const double x = M_PI * (double)f / (double)n;
+    double wc;
+    if (pl->p.interlaced) {
+      const double sinc = f == 0 ? 1.0 : std::sin(x) / x;
+      wc = std::pow(sinc, pl->p.window);
+    } else {
+      const double s2 = std::sin(x) * std::sin(x);
+      const double al = pl->p.window == 1 ? 1.0 : pl->p.window == 2 ? 1.0 - 2.0 / 3.0 * s2 : 1.0 - s2 + 2.0 / 15.0 * s2 * s2;
+      wc = std::sqrt(al);
+    }
+    invw[j] = (T)(1.0 / wc);
+    ph[2 * j] = (T)std::cos(x);
+    ph[2 * j + 1] = (T)std::sin(x);
+  }
+  // real-harmonic recurrence coefficients, per |m|
+  std::vector<T> yt((size_t)(YLM_LMAX + 1) * YLM_STRIDE, (T)0);
+  for (int m = 0; m <= YLM_LMAX; ++m) {
+    double q = 1.0;
+    for (int j = 1; j <= m; ++j) q *= (2.0 * j - 1.0) / (2.0 * j);
+    const double cmm = m == 0 ? std::sqrt(1.0 / (4.0 * M_PI)) : std::sqrt((2.0 * m + 1.0) / (2.0 * M_PI) * q);
+    T* c = yt.data() + (size_t)m * YLM_STRIDE;
+    c[0] = (T)cmm;
+    for (int l = m + 1; l <= YLM_LMAX; ++l) {
+      const int j = l - m;
+      const double l2 = (double)l * l, m2 = (double)m * m;
+      c[2 * j - 1] = (T)std::sqrt((4.0 * l2 - 1.0) / (l2 - m2));
+      c[2 * j] = (T)(j >= 2 ? std::sqrt(((l - 1.0) * (l - 1.0) - m2) * (2.0 * l + 1.0) / ((2.0 * l - 3.0) * (l2 - m2)))
+                            : 0.0);
+    }
+  }
+  check_hip(pl, hipMemcpy(pl->tw, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice), "upload twiddles");
+  check_hip(pl, hipMemcpy(pl->invw, invw.data(), invw.size() * sizeof(T), hipMemcpyHostToDevice), "upload window");
+  check_hip(pl, hipMemcpy(pl->phase, ph.data(), ph.size() * sizeof(T), hipMemcpyHostToDevice), "upload phase");
+  check_hip(pl, hipMemcpy(pl->ytab, yt.data(), yt.size() * sizeof(T), hipMemcpyHostToDevice), "upload ylm table");
+}
+
+int fields_for(int ell_max) {
+  int f = 0;
+  for (int l = 2; l <= ell_max; l += 2) f += 2 * l + 1;
+  return f;
+}
+
+void ensure_fields(pkm_plan* pl, int want) {
+  while ((int)pl->fields.size() < want) pl->fields.push_back(dalloc(pl, pl->mesh_bytes));
+  const int need_ptr = (int)pl->fields.size() + 8;
+  if (pl->ptr_cap < need_ptr) {
+    dfree(pl, pl->ptrs_dev);
+    pl->ptrs_dev = (void**)dalloc(pl, sizeof(void*) * need_ptr);
+    pl->ptr_cap = need_ptr;
+  }
+  std::vector<void*> host(pl->ptr_cap, nullptr);
+  for (size_t i = 0; i < pl->fields.size(); ++i) host[i] = pl->fields[i];
+  check_hip(pl, hipMemcpy(pl->ptrs_dev, host.data(), sizeof(void*) * pl->ptr_cap, hipMemcpyHostToDevice),
+            "upload field pointers");
+}
+
+// Device array [ptr_cap-8 .. ) holds ad-hoc pointers for single-buffer passes.
+void** scratch_ptrs(pkm_plan* pl, std::initializer_list<void*> ps) {
+  std::vector<void*> host(ps);
+  void** dst = pl->ptrs_dev + (pl->ptr_cap - 8);
+  check_hip(pl, hipMemcpy(dst, host.data(), sizeof(void*) * host.size(), hipMemcpyHostToDevice), "upload pointers");
+  return dst;
+}
+
+template <typename T> void run_paint(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* rand) {
+  hipStream_t s = pl->stream;
+  const int n = pl->p.nmesh;
+  const size_t cells = (size_t)n * n * n;
+  // stage host catalogs
+  auto stage = [&](const pkm_catalog* cat, size_t offset, const double** pos, const double** w, const double** nbar) {
+    if (cat->on_device) {
+      *pos = cat->pos;
+      *w = cat->w;
+      *nbar = cat->nbar;
+      return offset;
+    }
+    const size_t nn = (size_t)cat->n;
+    double* base = pl->cat_dev + offset;
+    check_hip(pl, hipMemcpyAsync(base, cat->pos, nn * 3 * sizeof(double), hipMemcpyHostToDevice, s), "upload pos");
+    *pos = base;
+    offset += nn * 3;
+    if (cat->w) {
+      check_hip(pl, hipMemcpyAsync(pl->cat_dev + offset, cat->w, nn * sizeof(double), hipMemcpyHostToDevice, s),
+                "upload w");
+      *w = pl->cat_dev + offset;
+      offset += nn;
+    } else *w = nullptr;
+    if (cat->nbar) {
+      check_hip(pl, hipMemcpyAsync(pl->cat_dev + offset, cat->nbar, nn * sizeof(double), hipMemcpyHostToDevice, s),
+                "upload nbar");
+      *nbar = pl->cat_dev + offset;
+      offset += nn;
+    } else *nbar = nullptr;
+    return offset;
+  };
+  size_t need = 0;
+  for (const pkm_catalog* cat : {data, rand})
+    if (cat && !cat->on_device) need += (size_t)cat->n * 3 + (cat->w ? cat->n : 0) + (cat->nbar ? cat->n : 0);
+  if (need > pl->cat_cap) {
+    dfree(pl, pl->cat_dev);
+    pl->cat_dev = nullptr;
+    pl->cat_cap = 0;
+    pl->cat_dev = (double*)dalloc(pl, need * sizeof(double));
+    pl->cat_cap = need;
+  }
+  const double *dp, *dw, *dn, *rp = nullptr, *rw = nullptr, *rn = nullptr;
+  size_t off = stage(data, 0, &dp, &dw, &dn);
+  if (rand) stage(rand, off, &rp, &rw, &rn);
+  check_hip(pl, hipEventRecord(pl->ev0, s), "event");
+  // catalog scalars (FP64, fixed-order reductions)
+  double sums[4] = {0, 0, 0, 0};
+  {
+    StageScope ss(pl, PKM_STAGE_SUMS);
+    check_hip(pl, launch_catalog_sums(dw, nullptr, data->n, pl->sums_dev + 4, SUM_BLOCKS, pl->sums_dev, s), "sums");
+    if (rand)
+      check_hip(pl, launch_catalog_sums(rw, rn, rand->n, pl->sums_dev + 4, SUM_BLOCKS, pl->sums_dev + 2, s), "sums");
+  }
+  check_hip(pl, hipMemcpyAsync(sums, pl->sums_dev, sizeof sums, hipMemcpyDeviceToHost, s), "download sums");
+  check_hip(pl, hipStreamSynchronize(s), "sync");
+  const double sd2 = sums[0];
+  if (rand) {
+    pl->alpha = (double)data->n / (double)rand->n;
+    pl->norm_I = pl->alpha * sums[3];
+    pl->shot = (sd2 + pl->alpha * pl->alpha * sums[2]) / pl->norm_I;
+  } else {
+    const double nbar = (double)data->n / (pl->p.box_len * pl->p.box_len * pl->p.box_len);
+    pl->alpha = 0.0;
+    pl->norm_I = nbar * sd2;
+    pl->shot = sd2 / pl->norm_I;
+  }
+  // paint
+  T* d1 = (T*)pl->d1;
+  T* d2 = pl->p.interlaced ? (T*)pl->d2 : nullptr;
+  {
+    StageScope ss(pl, PKM_STAGE_FILL);
+    check_hip(pl, launch_fill<T>(d1, cells, T(0), s), "fill");
+    if (d2) check_hip(pl, launch_fill<T>(d2, cells, T(0), s), "fill");
+  }
+  const double scale = (double)n / pl->p.box_len;
+  {
+    StageScope ss(pl, PKM_STAGE_PAINT);
+    check_hip(pl, launch_paint<T>(dp, dw, data->n, 1.0, pl->p.box_origin, scale, n, pl->p.window, d1, d2, s),
+              "paint");
+    if (rand)
+      check_hip(pl, launch_paint<T>(rp, rw, rand->n, -pl->alpha, pl->p.box_origin, scale, n, pl->p.window, d1, d2, s),
+                "paint randoms");
+  }
+  // forward transforms and combine
+  const int nbuf = d2 ? 2 : 1;
+  void** sp = scratch_ptrs(pl, {pl->s1, pl->s2, pl->g});
+  {
+    StageScope ss(pl, PKM_STAGE_ZFWD);
+    check_hip(pl, launch_zfwd<T>(pl->fs, d1, d2, pl->s1, pl->s2, nbuf, pl->tw, s), "zfwd");
+  }
+  {
+    StageScope ss(pl, PKM_STAGE_YCOL);
+    check_hip(pl, launch_col<T>(pl->fs, sp, nbuf, 1, false, pl->tw, s), "y pass");
+  }
+  const bool need_dc = pl->p.interlaced || pl->p.compensated;
+  {
+    StageScope ss(pl, PKM_STAGE_XCOMBINE);
+    check_hip(pl, launch_xcombine<T>(pl->fs, pl->s1, pl->s2, pl->c, need_dc ? pl->g : nullptr, pl->p.interlaced,
+                                     pl->p.compensated, pl->invw, pl->phase, pl->tw, s),
+              "x combine");
+  }
+  if (need_dc) {
+    StageScope ss(pl, PKM_STAGE_IYCOL);
+    check_hip(pl, launch_col<T>(pl->fs, sp + 2, 1, 1, true, pl->tw, s), "inverse y pass");
+  }
+  check_hip(pl, hipEventRecord(pl->ev1, s), "event");
+  check_hip(pl, hipStreamSynchronize(s), "sync");
+  resolve_stages(pl);
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, pl->ev0, pl->ev1);
+  pl->stats.ms_paint = ms;
+  const double R = (double)pl->mesh_bytes;
+  const double cat_bytes = 40.0 * (double)data->n + (rand ? 40.0 * (double)rand->n : 0.0);
+  pl->stats.model_bytes_paint = cat_bytes + nbuf * (2 * R) /*zero + scatter*/ + nbuf * (2 * R) /*z*/ +
+                                nbuf * (2 * R) /*y*/ + nbuf * R + 2 * R /*x combine*/ + (need_dc ? 2 * R : 0);
+  pl->painted = true;
+}
+
+template <typename T>
+void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, pkm_result* out) {
+  hipStream_t s = pl->stream;
+  const int n = pl->p.nmesh;
+  const int nb = n_edges - 1;
+  // integer thresholds T_i = ceil(((e_i * L) / (2 pi))^2)
+  std::vector<long long> thr(n_edges);
+  const double twopi = 2.0 * M_PI;
+  for (int i = 0; i < n_edges; ++i) {
+    const double t = (k_edges[i] * pl->p.box_len) / twopi;
+    const double t2 = t * t;
+    thr[i] = t2 >= 9.0e18 ? (long long)9.0e18 : (long long)std::ceil(t2);
+  }
+  if (pl->thr_cap < n_edges) {
+    dfree(pl, pl->thr_dev);
+    pl->thr_dev = (long long*)dalloc(pl, sizeof(long long) * n_edges);
+    pl->thr_cap = n_edges;
+  }
+  check_hip(pl, hipMemcpy(pl->thr_dev, thr.data(), sizeof(long long) * n_edges, hipMemcpyHostToDevice), "thr");
+  // fields and groups
+  struct F { int l, m, slot; };
+  std::vector<std::vector<F>> groups;
+  const int fmax = (int)pl->fields.size();
+  {
+    std::vector<F> cur;
+    int nl = 0, last_l = -1;
+    for (int l = 2; l <= ell_max; l += 2) {
+      for (int m = -l; m <= l; ++m) {
+        if ((int)cur.size() == fmax || (l != last_l && nl == 2)) {
+          groups.push_back(cur);
+          cur.clear();
+          nl = 0;
+          last_l = -1;
+        }
+        if (l != last_l) { ++nl; last_l = l; }
+        cur.push_back({l, m, nl - 1});
+      }
+    }
+    if (!cur.empty()) groups.push_back(cur);
+    if (groups.empty()) groups.push_back({});  // l = 0 only
+  }
+  const int rows = 3 + ell_max / 2;  // count, ksum, Q0, Q2, ...
+  {
+    const size_t col_lds_b = sizeof(T) * 2 * (size_t)n * (pl->fs.tile + 1);
+    if (col_lds_b + sizeof(double) * 5 * (size_t)nb > 160 * 1024) {
+      pl->err = "too many k bins for one pass";
+      throw Fail{PKM_EINVAL};
+    }
+  }
+  const int total_vals = rows * nb;
+  if (pl->out_cap < (size_t)total_vals) {
+    dfree(pl, pl->out_dev);
+    pl->out_dev = (double*)dalloc(pl, sizeof(double) * total_vals);
+    pl->out_cap = total_vals;
+  }
+  // table of (l, m, slot) for all groups, and reduce maps
+  std::vector<int> ftab, maps;
+  std::vector<int> fofs, mofs, nvals_g, nslots_g;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    fofs.push_back((int)ftab.size() / 3);
+    for (auto& f : groups[gi]) { ftab.push_back(f.l); ftab.push_back(f.m); ftab.push_back(f.slot); }
+    std::vector<int> slot_l;
+    for (auto& f : groups[gi]) if ((int)slot_l.size() <= f.slot) slot_l.push_back(f.l);
+    const bool first = gi == 0;
+    mofs.push_back((int)maps.size());
+    int nv = 0;
+    if (first) for (int r = 0; r < 3; ++r) for (int b = 0; b < nb; ++b) { maps.push_back(r * nb + b); ++nv; }
+    for (size_t si = 0; si < slot_l.size(); ++si)
+      for (int b = 0; b < nb; ++b) { maps.push_back((2 + slot_l[si] / 2) * nb + b); ++nv; }
+    nvals_g.push_back(nv);
+    nslots_g.push_back((int)slot_l.size());
+  }
+  if (pl->ftab_cap < (int)ftab.size() + 3) {
+    dfree(pl, pl->ftab_dev);
+    pl->ftab_dev = (int*)dalloc(pl, sizeof(int) * (ftab.size() + 3));
+    pl->ftab_cap = (int)ftab.size() + 3;
+  }
+  if (!ftab.empty())
+    check_hip(pl, hipMemcpy(pl->ftab_dev, ftab.data(), sizeof(int) * ftab.size(), hipMemcpyHostToDevice), "ftab");
+  if (pl->map_cap < (int)maps.size()) {
+    dfree(pl, pl->map_dev);
+    pl->map_dev = (int*)dalloc(pl, sizeof(int) * maps.size());
+    pl->map_cap = (int)maps.size();
+  }
+  check_hip(pl, hipMemcpy(pl->map_dev, maps.data(), sizeof(int) * maps.size(), hipMemcpyHostToDevice), "maps");
+  const int nblk = xpass_blocks(pl->fs);
+  int max_nv = 0;
+  for (int v : nvals_g) max_nv = std::max(max_nv, v);
+  if (pl->partial_cap < (size_t)nblk * max_nv) {
+    dfree(pl, pl->partial);
+    pl->partial = (double*)dalloc(pl, sizeof(double) * (size_t)nblk * max_nv);
+    pl->partial_cap = (size_t)nblk * max_nv;
+  }
+  // histogram copies per block: one per wave when the LDS budget allows
+  const int waves = (xpass_threads(pl->fs) + 63) / 64;
+  const size_t col_lds = sizeof(T) * 2 * (size_t)n * (pl->fs.tile + 1);
+  const size_t budget = 160 * 1024 - col_lds - 1024;
+  check_hip(pl, launch_fill<double>(pl->out_dev, total_vals, 0.0, s), "zero out");
+  check_hip(pl, hipEventRecord(pl->ev0, s), "event");
+  const bool dc_real = !(pl->p.interlaced || pl->p.compensated);
+  const double off[3] = {pl->p.box_origin[0] - pl->p.observer[0], pl->p.box_origin[1] - pl->p.observer[1],
+                         pl->p.box_origin[2] - pl->p.observer[2]};
+  const double h = pl->p.box_len / n;
+  const double dc_scale = 2.0 / ((double)n * n * n);
+  int nfields_total = 0;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const int nf = (int)groups[gi].size();
+    nfields_total += nf;
+    const int* ft = pl->ftab_dev + 3 * fofs[gi];
+    if (nf > 0) {
+      {
+        StageScope ss(pl, PKM_STAGE_ZPRE);
+        check_hip(pl, launch_zpre<T>(pl->fs, pl->g, dc_real ? (const T*)pl->d1 : nullptr, nullptr, pl->ptrs_dev, nf,
+                                     ft, dc_scale, off, h, pl->ytab, pl->tw, s),
+                  "zpre");
+      }
+      StageScope ss(pl, PKM_STAGE_YCOL);
+      check_hip(pl, launch_col<T>(pl->fs, pl->ptrs_dev, nf, 1, false, pl->tw, s), "field y pass");
+    }
+    const int nv = nvals_g[gi];
+    int copies = (int)std::min<size_t>((size_t)waves, budget / (sizeof(double) * (size_t)std::max(1, nv)));
+    copies = std::max(1, copies);
+    int nblocks = 0;
+    {
+    StageScope ss(pl, PKM_STAGE_XPOST);
+    check_hip(pl, launch_xpost<T>(pl->fs, pl->ptrs_dev, nf, ft, nslots_g[gi], gi == 0 ? 1 : 0, pl->c, pl->ytab,
+                                  BinSpec{pl->thr_dev, nb, copies}, (double)(2.0 * M_PI / pl->p.box_len), pl->partial,
+                                  &nblocks, pl->tw, s),
+              "xpost");
+    }
+    StageScope ss(pl, PKM_STAGE_REDUCE);
+    check_hip(pl, launch_reduce(pl->partial, nblocks, nv, pl->out_dev, pl->map_dev + mofs[gi], 1, s), "reduce");
+  }
+  check_hip(pl, hipEventRecord(pl->ev1, s), "event");
+  std::vector<double> res(total_vals);
+  check_hip(pl, hipMemcpyAsync(res.data(), pl->out_dev, sizeof(double) * total_vals, hipMemcpyDeviceToHost, s),
+            "download");
+  check_hip(pl, hipStreamSynchronize(s), "sync");
+  resolve_stages(pl);
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, pl->ev0, pl->ev1);
+  pl->stats.ms_compute = ms;
+  pl->stats.n_groups = (int)groups.size();
+  const double X = (double)pl->mesh_bytes;
+  pl->stats.model_bytes_compute = 0;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const double nf = (double)groups[gi].size();
+    pl->stats.model_bytes_compute += (nf > 0 ? X + nf * X : 0) + 2 * nf * X + nf * X + X;
+  }
+  const int n_fwd = pl->p.interlaced ? 2 : 1;
+  const int n_inv = (pl->p.interlaced || pl->p.compensated) ? 1 : 0;
+  pl->n_transforms = nfields_total + n_fwd + n_inv;
+  pl->stats.n_transforms = pl->n_transforms;
+  // normalise (FP64, host)
+  for (int b = 0; b < nb; ++b) {
+    const double cnt = res[b];
+    if (out->n_modes) out->n_modes[b] = (int64_t)llround(cnt);
+    if (out->k_mean) out->k_mean[b] = cnt > 0 ? res[nb + b] / cnt : NAN;
+    if (out->poles) {
+      for (int il = 0; il <= ell_max / 2; ++il) {
+        const double q = res[(2 + il) * nb + b];
+        double v = cnt > 0 ? q / (pl->norm_I * cnt) : NAN;
+        if (il == 0) v -= pl->shot;
+        out->poles[(size_t)il * nb + b] = v;
+      }
+    }
+  }
+  out->alpha = pl->alpha;
+  out->norm_I = pl->norm_I;
+  out->shot_noise = pl->shot;
+  out->n_transforms = pl->n_transforms;
+}
+
+template <typename T>
+void run_kmu(pkm_plan* pl, const double* k_edges, int nke, const double* mu_edges, int nme, double* pk, int64_t* nm) {
+  hipStream_t s = pl->stream;
+  const int nb = nke - 1, nmu = nme - 1;
+  std::vector<long long> thr(nke);
+  for (int i = 0; i < nke; ++i) {
+    const double t = (k_edges[i] * pl->p.box_len) / (2.0 * M_PI);
+    const double t2 = t * t;
+    thr[i] = t2 >= 9.0e18 ? (long long)9.0e18 : (long long)std::ceil(t2);
+  }
+  const int nvals = 2 * nb * nmu;
+  const int nblk = 1024;
+  long long* thr_d = (long long*)dalloc(pl, sizeof(long long) * nke);
+  double* mue_d = (double*)dalloc(pl, sizeof(double) * nme);
+  double* part = (double*)dalloc(pl, sizeof(double) * (size_t)nblk * nvals);
+  double* outd = (double*)dalloc(pl, sizeof(double) * nvals);
+  try {
+    check_hip(pl, hipMemcpy(thr_d, thr.data(), sizeof(long long) * nke, hipMemcpyHostToDevice), "thr");
+    check_hip(pl, hipMemcpy(mue_d, mu_edges, sizeof(double) * nme, hipMemcpyHostToDevice), "mu edges");
+    double l[3] = {pl->p.los[0], pl->p.los[1], pl->p.los[2]};
+    const double ln = std::sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]);
+    for (double& v : l) v /= ln;
+    check_hip(pl, launch_kmu<T>(pl->fs, pl->c, l, BinSpec{thr_d, nb, 1}, mue_d, nmu, part, nblk, s), "kmu");
+    check_hip(pl, launch_reduce(part, nblk, nvals, outd, nullptr, 0, s), "reduce");
+    std::vector<double> res(nvals);
+    check_hip(pl, hipMemcpy(res.data(), outd, sizeof(double) * nvals, hipMemcpyDeviceToHost), "download");
+    for (int i = 0; i < nb * nmu; ++i) {
+      const double cnt = res[2 * i];
+      if (nm) nm[i] = (int64_t)llround(cnt);
+      if (pk) pk[i] = cnt > 0 ? res[2 * i + 1] / (pl->norm_I * cnt) - pl->shot : NAN;
+    }
+  } catch (...) {
+    dfree(pl, thr_d); dfree(pl, mue_d); dfree(pl, part); dfree(pl, outd);
+    throw;
+  }
+  dfree(pl, thr_d); dfree(pl, mue_d); dfree(pl, part); dfree(pl, outd);
+}
+
+template <typename T> void run_fft_forward(pkm_plan* pl, const void* in, void* out) {
+  hipStream_t s = pl->stream;
+  check_hip(pl, launch_zfwd<T>(pl->fs, (const T*)in, nullptr, out, nullptr, 1, pl->tw, s), "zfwd");
+  void** sp = scratch_ptrs(pl, {out});
+  check_hip(pl, launch_col<T>(pl->fs, sp, 1, 1, false, pl->tw, s), "y pass");
+  check_hip(pl, launch_col<T>(pl->fs, sp, 1, 0, false, pl->tw, s), "x pass");
+  check_hip(pl, hipStreamSynchronize(s), "sync");
+}
+
+template <typename T> void run_fft_inverse(pkm_plan* pl, void* in, void* out) {
+  hipStream_t s = pl->stream;
+  void** sp = scratch_ptrs(pl, {in});
+  check_hip(pl, launch_col<T>(pl->fs, sp, 1, 0, true, pl->tw, s), "x pass");
+  check_hip(pl, launch_col<T>(pl->fs, sp, 1, 1, true, pl->tw, s), "y pass");
+  const double off[3] = {0, 0, 0};
+  const int n = pl->p.nmesh;
+  check_hip(pl, launch_zpre<T>(pl->fs, in, nullptr, (T*)out, pl->ptrs_dev, 0, pl->ftab_dev, 2.0 / ((double)n * n * n),
+                               off, 1.0, pl->ytab, pl->tw, s),
+            "z inverse");
+  check_hip(pl, hipStreamSynchronize(s), "sync");
+}
+
+template <typename T> void read_dc(pkm_plan* pl, void* host, size_t bytes) {
+  hipStream_t s = pl->stream;
+  if (!(pl->p.interlaced || pl->p.compensated)) {
+    check_hip(pl, hipMemcpy(host, pl->d1, bytes, hipMemcpyDeviceToHost), "read d1");
+    return;
+  }
+  void* tmp = dalloc(pl, pl->mesh_bytes);
+  const double off[3] = {0, 0, 0};
+  const int n = pl->p.nmesh;
+  hipError_t e = launch_zpre<T>(pl->fs, pl->g, nullptr, (T*)tmp, pl->ptrs_dev, 0, pl->ftab_dev,
+                                2.0 / ((double)n * n * n), off, 1.0, pl->ytab, pl->tw, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipMemcpy(host, tmp, bytes, hipMemcpyDeviceToHost);
+  dfree(pl, tmp);
+  check_hip(pl, e, "read D_c");
+}
+
+pkm_status validate_params(const pkm_params* p, std::string* why) {
+  if (!p) { *why = "params is NULL"; return PKM_EINVAL; }
+  if (!is_smooth(p->nmesh)) { *why = "nmesh must be 2^a 3^b with a >= 2 and 16 <= N <= 1024"; return PKM_EINVAL; }
+  if (!(p->box_len > 0) || !std::isfinite(p->box_len)) { *why = "box_len must be positive"; return PKM_EINVAL; }
+  if (p->window < 1 || p->window > 3) { *why = "window must be 1 (NGP), 2 (CIC) or 3 (TSC)"; return PKM_EINVAL; }
+  if (p->precision != PKM_FP32 && p->precision != PKM_FP64) { *why = "precision must be FP32 or FP64"; return PKM_EINVAL; }
+  if (p->ell_max_hint < 0 || p->ell_max_hint > 16 || p->ell_max_hint % 2) {
+    *why = "ell_max_hint must be even and in 0..16";
+    return PKM_EINVAL;
+  }
+  if (p->los_mode == PKM_LOS_GLOBAL) {
+    const double l2 = p->los[0] * p->los[0] + p->los[1] * p->los[1] + p->los[2] * p->los[2];
+    if (!(l2 > 0)) { *why = "los must be a nonzero vector"; return PKM_EINVAL; }
+  }
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->box_origin[a]) || !std::isfinite(p->observer[a])) {
+      *why = "box_origin and observer must be finite";
+      return PKM_EINVAL;
+    }
+  return PKM_OK;
+}
+
+pkm_status validate_catalog(const pkm_catalog* c, bool need_nbar, std::string* why) {
+  if (!c) { *why = "catalog is NULL"; return PKM_EINVAL; }
+  if (c->n < 0) { *why = "catalog size must be >= 0"; return PKM_EINVAL; }
+  if (c->n > 0 && !c->pos) { *why = "catalog positions are NULL"; return PKM_EINVAL; }
+  if (need_nbar && c->n > 0 && !c->nbar) { *why = "randoms need nbar"; return PKM_EINVAL; }
+  return PKM_OK;
+}
+
+template <typename F> pkm_status guarded(pkm_plan* pl, F&& f) {
+  try {
+    f();
+    return PKM_OK;
+  } catch (const Fail& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    if (pl) pl->err = "host allocation failed";
+    return PKM_ENOMEM;
+  } catch (...) {
+    if (pl) pl->err = "unexpected host exception";
+    return PKM_EDEVICE;
+  }
+}
+
+void free_all(pkm_plan* pl) {
+  for (void* f : pl->fields) dfree(pl, f);
+  pl->fields.clear();
+  for (void* ptr : {pl->d1, pl->d2, pl->s1, pl->s2, pl->c, pl->g, (void*)pl->ptrs_dev, (void*)pl->ftab_dev,
+                    (void*)pl->map_dev, pl->tw, pl->ytab, pl->invw, pl->phase, (void*)pl->thr_dev, (void*)pl->partial,
+                    (void*)pl->out_dev, (void*)pl->sums_dev, (void*)pl->cat_dev})
+    dfree(pl, ptr);
+  for (hipEvent_t e : pl->ev_pool) (void)hipEventDestroy(e);
+  if (pl->ev0) (void)hipEventDestroy(pl->ev0);
+  if (pl->ev1) (void)hipEventDestroy(pl->ev1);
+}
+
+}  // namespace
+
+// -------------------------------------------------------------------------------------------
+// C ABI
+// -------------------------------------------------------------------------------------------
+extern "C" {
+
+int pkm_abi_version(void) { return PKM_ABI_VERSION; }
+
+const char* pkm_status_str(pkm_status s) {
+  switch (s) {
+    case PKM_OK: return "ok";
+    case PKM_EINVAL: return "invalid argument";
+    case PKM_EORDER: return "compute before paint";
+    case PKM_ENOMEM: return "out of memory / over budget";
+    case PKM_EDEVICE: return "device error";
+    case PKM_EBUSY: return "busy";
+    case PKM_ECANCELLED: return "cancelled";
+  }
+  return "unknown status";
+}
+
+pkm_status pkm_plan_create(const pkm_params* p, const pkm_device* dev, pkm_plan** out) {
+  if (!out) return PKM_EINVAL;
+  std::string why;
+  pkm_status st = validate_params(p, &why);
+  if (st != PKM_OK) return st;
+  pkm_plan* pl = new (std::nothrow) pkm_plan();
+  if (!pl) return PKM_ENOMEM;
+  pl->p = *p;
+  if (pl->p.ell_max_hint == 0) pl->p.ell_max_hint = 4;
+  if (dev) pl->dev = *dev;
+  pl->stream = (hipStream_t)pl->dev.hip_stream;
+  pl->fp64 = p->precision == PKM_FP64;
+  pl->es = pl->fp64 ? 8 : 4;
+  const int n = p->nmesh;
+  pl->mesh_bytes = pl->es * (size_t)n * n * n;
+  FftShape& fs = pl->fs;
+  fs.n = n;
+  fs.e_col = pick_e(n);
+  fs.e_z = pick_e(n / 2);
+  // register budget: FP64 column passes and all z-line passes use at most 8 (or 12 / 6
+  // for lengths with a factor 3) elements per thread
+  if (pl->fp64 && fs.e_col == 16) fs.e_col = 8;
+  if (fs.e_z == 16) fs.e_z = 8;
+  if (!fs.e_col || !fs.e_z || !make_sched(n, fs.e_col, &fs.sched_col, &fs.nst_col) ||
+      !make_sched(n / 2, fs.e_z, &fs.sched_z, &fs.nst_z)) {
+    delete pl;
+    return PKM_EINVAL;
+  }
+  // tile columns: 128-byte rows, at most 512 threads per column-pass block
+  fs.tile = pl->fp64 ? 8 : 16;
+  const int pt_col = n / fs.e_col;
+  while (fs.tile > 1 && (pt_col * fs.tile > 512 || (n / 2) % fs.tile)) fs.tile /= 2;
+  const int pt_z = (n / 2) / fs.e_z;
+  int zl = 1;
+  while (zl * 2 * pt_z <= 256 && ((size_t)n * n) % (zl * 2) == 0) zl *= 2;
+  fs.zlines = zl;
+  st = guarded(pl, [&] {
+    check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
+    check_hip(pl, hipEventCreate(&pl->ev0), "event");
+    check_hip(pl, hipEventCreate(&pl->ev1), "event");
+    pl->d1 = dalloc(pl, pl->mesh_bytes);
+    if (p->interlaced) pl->d2 = dalloc(pl, pl->mesh_bytes);
+    pl->s1 = dalloc(pl, pl->mesh_bytes);
+    if (p->interlaced) pl->s2 = dalloc(pl, pl->mesh_bytes);
+    pl->c = dalloc(pl, pl->mesh_bytes);
+    pl->g = dalloc(pl, pl->mesh_bytes);
+    pl->tw = dalloc(pl, 2 * pl->es * n);
+    pl->invw = dalloc(pl, pl->es * n);
+    pl->phase = dalloc(pl, 2 * pl->es * n);
+    pl->ytab = dalloc(pl, pl->es * (YLM_LMAX + 1) * YLM_STRIDE);
+    pl->sums_dev = (double*)dalloc(pl, sizeof(double) * (4 + 2 * SUM_BLOCKS));
+    int want = fields_for(pl->p.ell_max_hint);
+    if (p->max_group > 0) want = std::min(want, p->max_group);
+    ensure_fields(pl, std::max(want, 1));
+    pl->ftab_dev = (int*)dalloc(pl, sizeof(int) * 3 * 64);
+    pl->ftab_cap = 3 * 64;
+    if (pl->fp64) upload_tables<double>(pl); else upload_tables<float>(pl);
+  });
+  if (st != PKM_OK) {
+    free_all(pl);
+    delete pl;
+    return st;
+  }
+  pl->stats.device_bytes = pl->bytes;
+  *out = pl;
+  return PKM_OK;
+}
+
+pkm_status pkm_paint(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* randoms) {
+  if (!pl) return PKM_EINVAL;
+  std::string why;
+  if (validate_catalog(data, false, &why) != PKM_OK || (randoms && validate_catalog(randoms, true, &why) != PKM_OK)) {
+    pl->err = why;
+    return PKM_EINVAL;
+  }
+  if (data->n == 0) {
+    pl->err = "data catalog is empty";
+    return PKM_EINVAL;
+  }
+  if (randoms && randoms->n == 0) {
+    pl->err = "random catalog is empty (pass NULL for a periodic box)";
+    return PKM_EINVAL;
+  }
+  pl->painted = false;
+  pkm_status st = guarded(pl, [&] {
+    check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
+    if (pl->fp64) run_paint<double>(pl, data, randoms); else run_paint<float>(pl, data, randoms);
+  });
+  pl->stats.device_bytes = pl->bytes;
+  return st;
+}
+
+pkm_status pkm_compute_multipoles(pkm_plan* pl, int32_t ell_max, const double* k_edges, int32_t n_edges,
+                                  pkm_result* out) {
+  if (!pl) return PKM_EINVAL;
+  if (!out || !k_edges || n_edges < 2) { pl->err = "need k_edges (n_edges >= 2) and a result"; return PKM_EINVAL; }
+  if (ell_max < 0 || ell_max > 16 || ell_max % 2) { pl->err = "ell_max must be even and in 0..16"; return PKM_EINVAL; }
+  for (int i = 0; i < n_edges; ++i) {
+    if (!(k_edges[i] >= 0.0) || !std::isfinite(k_edges[i])) { pl->err = "k edges must be finite and >= 0"; return PKM_EINVAL; }
+    if (i > 0 && !(k_edges[i] > k_edges[i - 1])) { pl->err = "k edges must be strictly increasing"; return PKM_EINVAL; }
+  }
+  if (!pl->painted) { pl->err = "pkm_paint must succeed before pkm_compute_multipoles"; return PKM_EORDER; }
+  pkm_status st = guarded(pl, [&] {
+    check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
+    const int need = fields_for(ell_max);
+    if ((int)pl->fields.size() < need && (pl->p.max_group <= 0 || (int)pl->fields.size() < pl->p.max_group))
+      ensure_fields(pl, pl->p.max_group > 0 ? std::min(need, pl->p.max_group) : need);
+    if (pl->fp64) run_compute<double>(pl, ell_max, k_edges, n_edges, out);
+    else run_compute<float>(pl, ell_max, k_edges, n_edges, out);
+  });
+  pl->stats.device_bytes = pl->bytes;
+  return st;
+}
+
+pkm_status pkm_kmu_global(pkm_plan* pl, const double* k_edges, int32_t n_k_edges, const double* mu_edges,
+                          int32_t n_mu_edges, double* pkmu_out, int64_t* nmodes_out) {
+  if (!pl) return PKM_EINVAL;
+  if (!k_edges || !mu_edges || n_k_edges < 2 || n_mu_edges < 2) { pl->err = "need k and mu edges"; return PKM_EINVAL; }
+  for (int i = 0; i < n_k_edges; ++i)
+    if (!(k_edges[i] >= 0) || (i > 0 && !(k_edges[i] > k_edges[i - 1]))) { pl->err = "bad k edges"; return PKM_EINVAL; }
+  for (int i = 0; i < n_mu_edges; ++i)
+    if (!(mu_edges[i] >= 0 && mu_edges[i] <= 1) || (i > 0 && !(mu_edges[i] > mu_edges[i - 1]))) {
+      pl->err = "mu edges must increase within [0, 1]";
+      return PKM_EINVAL;
+    }
+  if ((size_t)2 * (n_k_edges - 1) * (n_mu_edges - 1) * sizeof(double) > 48 * 1024) {
+    pl->err = "too many (k, mu) cells for one pass (limit 3072)";
+    return PKM_EINVAL;
+  }
+  if (pl->p.los_mode != PKM_LOS_GLOBAL) { pl->err = "plan was not created with los_mode = GLOBAL"; return PKM_EINVAL; }
+  if (!pl->painted) { pl->err = "pkm_paint must succeed first"; return PKM_EORDER; }
+  return guarded(pl, [&] {
+    check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
+    if (pl->fp64) run_kmu<double>(pl, k_edges, n_k_edges, mu_edges, n_mu_edges, pkmu_out, nmodes_out);
+    else run_kmu<float>(pl, k_edges, n_k_edges, mu_edges, n_mu_edges, pkmu_out, nmodes_out);
+  });
+}
+
+pkm_status pkm_stats(const pkm_plan* pl, pkm_stats_t* out) {
+  if (!pl || !out) return PKM_EINVAL;
+  *out = pl->stats;
+  out->device_bytes = pl->bytes;
+  return PKM_OK;
+}
+
+pkm_status pkm_set_stage_timing(pkm_plan* pl, int32_t enable) {
+  if (!pl) return PKM_EINVAL;
+  pl->stage_timing = enable != 0;
+  return PKM_OK;
+}
+
+pkm_status pkm_reset_stats(pkm_plan* pl) {
+  if (!pl) return PKM_EINVAL;
+  for (int i = 0; i < PKM_NSTAGES; ++i) {
+    pl->stats.stage_ms[i] = 0.0;
+    pl->stats.stage_launches[i] = 0;
+  }
+  return PKM_OK;
+}
+
+const char* pkm_plan_last_error(const pkm_plan* pl) { return pl ? pl->err.c_str() : "no plan"; }
+
+void pkm_plan_destroy(pkm_plan* pl) {
+  if (!pl) return;
+  (void)hipSetDevice(pl->dev.device_id);
+  if (pl->stream) (void)hipStreamSynchronize(pl->stream); else (void)hipDeviceSynchronize();
+  free_all(pl);
+  delete pl;
+}
+
+pkm_status pkm_fft3d_forward(pkm_plan* pl, const void* in, void* out) {
+  if (!pl || !in || !out) return PKM_EINVAL;
+  return guarded(pl, [&] {
+    check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
+    if (pl->fp64) run_fft_forward<double>(pl, in, out); else run_fft_forward<float>(pl, in, out);
+  });
+}
+
+pkm_status pkm_fft3d_inverse(pkm_plan* pl, void* in, void* out) {
+  if (!pl || !in || !out) return PKM_EINVAL;
+  return guarded(pl, [&] {
+    check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
+    if (pl->fp64) run_fft_inverse<double>(pl, in, out); else run_fft_inverse<float>(pl, in, out);
+  });
+}
+
+pkm_status pkm_plan_read_buffer(pkm_plan* pl, int32_t which, void* host, size_t bytes) {
+  if (!pl || !host) return PKM_EINVAL;
+  if (which < 0 || which > 3) { pl->err = "which must be 0..3"; return PKM_EINVAL; }
+  if (bytes != pl->mesh_bytes) { pl->err = "bytes must equal the mesh buffer size"; return PKM_EINVAL; }
+  if (!pl->painted) { pl->err = "nothing painted"; return PKM_EORDER; }
+  if (which == 1 && !pl->p.interlaced) { pl->err = "plan is not interlaced"; return PKM_EINVAL; }
+  return guarded(pl, [&] {
+    check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
+    check_hip(pl, hipStreamSynchronize(pl->stream), "sync");
+    if (which == 0) check_hip(pl, hipMemcpy(host, pl->d1, bytes, hipMemcpyDeviceToHost), "read");
+    else if (which == 1) check_hip(pl, hipMemcpy(host, pl->d2, bytes, hipMemcpyDeviceToHost), "read");
+    else if (which == 2) check_hip(pl, hipMemcpy(host, pl->c, bytes, hipMemcpyDeviceToHost), "read");
+    else if (pl->fp64) read_dc<double>(pl, host, bytes);
+    else read_dc<float>(pl, host, bytes);
+  });
+}
+
+}  // extern "C"

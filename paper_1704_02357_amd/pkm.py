@@ -1,0 +1,301 @@
+"""ctypes binding of libpkm (include/pkm.h): argument marshalling only.
+
+Every step of the estimator runs in the HIP library.  PyTorch supplies device memory (its
+caching allocator is passed to the library as the plan's allocator) and the HIP stream.
+If the library is missing the import of a Plan raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+NGP, CIC, TSC = 1, 2, 3
+FP32, FP64 = 0, 1
+LOS_LOCAL, LOS_GLOBAL = 0, 1
+STATUS = {0: "PKM_OK", 1: "PKM_EINVAL", 2: "PKM_EORDER", 3: "PKM_ENOMEM", 4: "PKM_EDEVICE", 5: "PKM_EBUSY",
+          6: "PKM_ECANCELLED"}
+
+
+class PkmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("nmesh", C.c_int32), ("box_len", C.c_double), ("box_origin", C.c_double * 3),
+                ("observer", C.c_double * 3), ("los_mode", C.c_int32), ("los", C.c_double * 3),
+                ("window", C.c_int32), ("interlaced", C.c_int32), ("compensated", C.c_int32),
+                ("precision", C.c_int32), ("ell_max_hint", C.c_int32), ("max_group", C.c_int32)]
+
+
+class Catalog(C.Structure):
+    _fields_ = [("pos", C.c_void_p), ("w", C.c_void_p), ("nbar", C.c_void_p), ("n", C.c_int64),
+                ("on_device", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("poles", C.c_void_p), ("k_mean", C.c_void_p), ("n_modes", C.c_void_p), ("alpha", C.c_double),
+                ("norm_I", C.c_double), ("shot_noise", C.c_double), ("n_transforms", C.c_int32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Device(C.Structure):
+    _fields_ = [("device_id", C.c_int32), ("hip_stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_ctx", C.c_void_p)]
+
+
+STAGES = ["sums", "fill", "paint", "zfwd", "ycol", "xcombine", "iycol", "zpre", "xpost", "reduce"]
+
+
+class Stats(C.Structure):
+    _fields_ = [("device_bytes", C.c_int64), ("n_transforms", C.c_int32), ("n_groups", C.c_int32),
+                ("ms_paint", C.c_double), ("ms_compute", C.c_double), ("model_bytes_paint", C.c_double),
+                ("model_bytes_compute", C.c_double), ("stage_ms", C.c_double * 10),
+                ("stage_launches", C.c_int64 * 10)]
+
+
+_LIB = None
+
+
+def lib_path() -> str:
+    return os.environ.get("PKM_LIBRARY", os.path.join(HERE, "libpkm.so"))
+
+
+def load_library():
+    """Load libpkm.so (raises OSError if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = lib_path()
+    if not os.path.exists(path):
+        raise OSError(f"{path} not found: build it with paper_1704_02357_amd/build.py")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    sig = {
+        "pkm_abi_version": (C.c_int, []),
+        "pkm_status_str": (C.c_char_p, [C.c_int]),
+        "pkm_plan_create": (C.c_int, [C.POINTER(Params), C.POINTER(Device), C.POINTER(P)]),
+        "pkm_paint": (C.c_int, [P, C.POINTER(Catalog), C.POINTER(Catalog)]),
+        "pkm_compute_multipoles": (C.c_int, [P, C.c_int32, P, C.c_int32, C.POINTER(Result)]),
+        "pkm_kmu_global": (C.c_int, [P, P, C.c_int32, P, C.c_int32, P, P]),
+        "pkm_wedges": (C.c_int, [P, C.c_int32, C.c_int32, P, C.c_int32, P]),
+        "pkm_nonuniform_mu_edges": (C.c_int, [C.c_int32, P]),
+        "pkm_stats": (C.c_int, [P, C.POINTER(Stats)]),
+        "pkm_set_stage_timing": (C.c_int, [P, C.c_int32]),
+        "pkm_reset_stats": (C.c_int, [P]),
+        "pkm_plan_last_error": (C.c_char_p, [P]),
+        "pkm_plan_destroy": (None, [P]),
+        "pkm_fft3d_forward": (C.c_int, [P, P, P]),
+        "pkm_fft3d_inverse": (C.c_int, [P, P, P]),
+        "pkm_plan_read_buffer": (C.c_int, [P, C.c_int32, P, C.c_size_t]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def _ptr(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def wedges(poles: np.ndarray, ell_max: int, mu_edges) -> np.ndarray:
+    """eq. wedge-est on the host (FP64): returns (n_k, n_mu)."""
+    lib = load_library()
+    poles = np.ascontiguousarray(poles, dtype=np.float64)
+    mu = np.ascontiguousarray(mu_edges, dtype=np.float64)
+    nk = poles.shape[1]
+    out = np.empty((nk, mu.size - 1))
+    st = lib.pkm_wedges(_ptr(poles), ell_max, nk, _ptr(mu), mu.size, _ptr(out))
+    if st:
+        raise PkmError(st, "pkm_wedges rejected its arguments")
+    return out
+
+
+def nonuniform_mu_edges(ell_max: int) -> np.ndarray:
+    lib = load_library()
+    out = np.empty(ell_max // 2 + 2)
+    st = lib.pkm_nonuniform_mu_edges(ell_max, _ptr(out))
+    if st:
+        raise PkmError(st, "pkm_nonuniform_mu_edges rejected its arguments")
+    return out
+
+
+class _TorchAllocator:
+    """Routes the library's device allocations through torch's caching allocator."""
+
+    def __init__(self, device: int):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.c_alloc = ALLOC_FN(self._alloc)
+        self.c_free = FREE_FN(self._free)
+
+    def _alloc(self, size, stream, ctx):
+        try:
+            return int(self.torch.cuda.caching_allocator_alloc(int(size), self.device, stream or 0))
+        except Exception:
+            return None
+
+    def _free(self, ptr, stream, ctx):
+        try:
+            self.torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+
+class Plan:
+    """One mesh configuration.  Inputs may be numpy arrays (host) or torch CUDA tensors."""
+
+    def __init__(self, nmesh: int, box_len: float, *, box_origin=None, observer=(0.0, 0.0, 0.0), window=TSC,
+                 interlaced=True, compensated=True, precision=FP32, ell_max_hint=4, max_group=0, los=None,
+                 device: int = 0, stream=None, torch_allocator: bool = True):
+        self.lib = load_library()
+        p = Params()
+        p.nmesh = int(nmesh)
+        p.box_len = float(box_len)
+        o = (-0.5 * box_len,) * 3 if box_origin is None else box_origin
+        for a in range(3):
+            p.box_origin[a] = float(o[a])
+            p.observer[a] = float(observer[a])
+        if los is not None:
+            p.los_mode = LOS_GLOBAL
+            for a in range(3):
+                p.los[a] = float(los[a])
+        p.window, p.interlaced, p.compensated = int(window), int(bool(interlaced)), int(bool(compensated))
+        p.precision, p.ell_max_hint, p.max_group = int(precision), int(ell_max_hint), int(max_group)
+        self.params = p
+        self.nmesh = p.nmesh
+        self.precision = p.precision
+        d = Device()
+        d.device_id = device
+        self._stream_obj = stream
+        if stream is not None:
+            d.hip_stream = C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+        self._alloc = None
+        if torch_allocator:
+            self._alloc = _TorchAllocator(device)
+            d.alloc = self._alloc.c_alloc
+            d.free = self._alloc.c_free
+        self.dev = d
+        h = C.c_void_p()
+        st = self.lib.pkm_plan_create(C.byref(p), C.byref(d), C.byref(h))
+        if st:
+            raise PkmError(st, "pkm_plan_create failed")
+        self.h = h
+        self._keep = []
+
+    # -- helpers ------------------------------------------------------------------------
+    def _check(self, st, what):
+        if st:
+            msg = self.lib.pkm_plan_last_error(self.h)
+            raise PkmError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def _catalog(self, cat):
+        if cat is None:
+            return None
+        pos, w, nbar = cat if isinstance(cat, tuple) else (cat.pos, cat.w, getattr(cat, "nbar", None))
+        c = Catalog()
+        on_dev = hasattr(pos, "is_cuda") and pos.is_cuda
+        if on_dev:
+            import torch
+            arrs = [None if a is None else a.to(torch.float64).contiguous() for a in (pos, w, nbar)]
+            c.pos, c.w, c.nbar = [None if a is None else a.data_ptr() for a in arrs]
+            c.n = int(arrs[0].shape[0])
+            c.on_device = 1
+        else:
+            arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (pos, w, nbar)]
+            c.pos, c.w, c.nbar = [None if a is None else a.ctypes.data for a in arrs]
+            c.n = int(arrs[0].shape[0])
+            c.on_device = 0
+        self._keep.append(arrs)
+        return c
+
+    # -- API ----------------------------------------------------------------------------
+    def paint(self, data, randoms=None):
+        self._keep = []
+        d = self._catalog(data)
+        r = self._catalog(randoms)
+        st = self.lib.pkm_paint(self.h, C.byref(d), C.byref(r) if r is not None else None)
+        self._keep = []
+        self._check(st, "pkm_paint")
+
+    def compute_multipoles(self, ell_max: int, k_edges) -> dict:
+        e = np.ascontiguousarray(k_edges, dtype=np.float64)
+        nb = e.size - 1
+        poles = np.empty((ell_max // 2 + 1, nb))
+        kmean = np.empty(nb)
+        nmodes = np.empty(nb, dtype=np.int64)
+        r = Result()
+        r.poles, r.k_mean, r.n_modes = poles.ctypes.data, kmean.ctypes.data, nmodes.ctypes.data
+        st = self.lib.pkm_compute_multipoles(self.h, int(ell_max), _ptr(e), e.size, C.byref(r))
+        self._check(st, "pkm_compute_multipoles")
+        return dict(poles=poles, k_mean=kmean, n_modes=nmodes, alpha=r.alpha, norm_I=r.norm_I,
+                    shot_noise=r.shot_noise, n_transforms=r.n_transforms, ells=list(range(0, ell_max + 1, 2)))
+
+    def kmu_global(self, k_edges, mu_edges):
+        ke = np.ascontiguousarray(k_edges, dtype=np.float64)
+        me = np.ascontiguousarray(mu_edges, dtype=np.float64)
+        pk = np.empty((ke.size - 1, me.size - 1))
+        nm = np.empty((ke.size - 1, me.size - 1), dtype=np.int64)
+        st = self.lib.pkm_kmu_global(self.h, _ptr(ke), ke.size, _ptr(me), me.size, _ptr(pk), _ptr(nm))
+        self._check(st, "pkm_kmu_global")
+        return pk, nm
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self.lib.pkm_stats(self.h, C.byref(s)), "pkm_stats")
+        out = {f: getattr(s, f) for f, _ in Stats._fields_ if not f.startswith("stage_")}
+        out["stage_ms"] = {STAGES[i]: s.stage_ms[i] for i in range(10)}
+        out["stage_launches"] = {STAGES[i]: int(s.stage_launches[i]) for i in range(10)}
+        return out
+
+    def set_stage_timing(self, on: bool):
+        self._check(self.lib.pkm_set_stage_timing(self.h, int(bool(on))), "pkm_set_stage_timing")
+
+    def reset_stats(self):
+        self._check(self.lib.pkm_reset_stats(self.h), "pkm_reset_stats")
+
+    def read_buffer(self, which: int) -> np.ndarray:
+        n = self.nmesh
+        rdt = np.float64 if self.precision == FP64 else np.float32
+        cdt = np.complex128 if self.precision == FP64 else np.complex64
+        if which == 2:
+            out = np.empty((n, n, n // 2), dtype=cdt)
+        else:
+            out = np.empty((n, n, n), dtype=rdt)
+        st = self.lib.pkm_plan_read_buffer(self.h, int(which), out.ctypes.data, out.nbytes)
+        self._check(st, "pkm_plan_read_buffer")
+        return out
+
+    def fft3d_forward(self, real_dev, out_dev):
+        self._check(self.lib.pkm_fft3d_forward(self.h, real_dev.data_ptr(), out_dev.data_ptr()), "pkm_fft3d_forward")
+
+    def fft3d_inverse(self, half_dev, out_dev):
+        self._check(self.lib.pkm_fft3d_inverse(self.h, half_dev.data_ptr(), out_dev.data_ptr()), "pkm_fft3d_inverse")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pkm_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,81 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared symbol, and its
+host-only entry points agree with the oracle; parameter validation rejects bad input
+before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pkm.h")
+
+
+def _lib():
+    from paper_1704_02357_amd.pkm import load_library, lib_path
+    if not os.path.exists(lib_path()):
+        pytest.skip("libpkm.so not built")
+    return load_library()
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pkm_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    lib = _lib()
+    syms = declared_symbols()
+    assert len(syms) >= 14
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert lib.pkm_abi_version() == 1
+    assert lib.pkm_status_str(0) == b"ok"
+    assert lib.pkm_status_str(2) == b"compute before paint"
+
+
+def test_wedges_match_oracle():
+    from paper_1704_02357_amd import wedges
+    from oracle.wedges import wedges as owedges
+    rng = np.random.default_rng(3)
+    poles = rng.normal(size=(9, 7))
+    for edges in (np.linspace(0, 1, 11), np.array([0, 0.05, 0.3, 0.31, 0.9, 1.0])):
+        got = wedges(poles, 16, edges)
+        ref = owedges(poles, list(range(0, 17, 2)), edges)
+        assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_nonuniform_edges_match_oracle():
+    from paper_1704_02357_amd import nonuniform_mu_edges
+    from oracle.systematics import nonuniform_mu_edges as oedges
+    # the oracle polishes roots of a degree-(lmax+1) polynomial in the monomial basis, whose
+    # coefficients reach ~1e4 at lmax = 16: its edges carry ~1e-12 absolute error there
+    for lmax in (2, 4, 8, 16):
+        assert np.max(np.abs(nonuniform_mu_edges(lmax) - oedges(lmax))) < 1e-10
+
+
+def test_wedges_validation():
+    lib = _lib()
+    poles = np.zeros((3, 4))
+    out = np.zeros((4, 2))
+    P = lambda a: a.ctypes.data_as(C.c_void_p)
+    bad = np.array([0.0, 0.7, 0.5])  # not increasing
+    assert lib.pkm_wedges(P(poles), 4, 4, P(bad), 3, P(out)) == 1
+    assert lib.pkm_wedges(P(poles), 3, 4, P(np.array([0, 0.5, 1.0])), 3, P(out)) == 1  # odd ell_max
+    assert lib.pkm_wedges(P(poles), 4, 4, P(np.array([0, 0.5, 1.5])), 3, P(out)) == 1  # outside [0, 1]
+    assert lib.pkm_nonuniform_mu_edges(3, P(np.zeros(4))) == 1
+
+
+@pytest.mark.parametrize("field,value", [("nmesh", 100), ("nmesh", 2048), ("nmesh", 54), ("box_len", -1.0),
+                                         ("window", 4), ("precision", 2), ("ell_max_hint", 5), ("ell_max_hint", 18)])
+def test_plan_create_rejects_bad_params(field, value):
+    lib = _lib()
+    from paper_1704_02357_amd.pkm import Params
+    p = Params()
+    p.nmesh, p.box_len, p.window, p.interlaced, p.compensated, p.precision = 64, 100.0, 3, 1, 1, 0
+    setattr(p, field, value)
+    h = C.c_void_p()
+    assert lib.pkm_plan_create(C.byref(p), None, C.byref(h)) == 1
+    assert not h.value
