@@ -126,6 +126,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ngal", type=int, default=1_000_000)
     ap.add_argument("--random-factor", type=float, default=20.0)
+    ap.add_argument("--fp32-only", action="store_true", help="skip the FP64 form (profiling runs)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a plain 1 GiB device copy (x3) first, to calibrate HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).",
@@ -135,6 +138,13 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.calib_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     from synth import config_c2
     t0 = time.perf_counter()
     data, rand, info = config_c2(n_gal=args.ngal, random_factor=args.random_factor)
@@ -148,8 +158,11 @@ def main():
     res32, sec32, lat32, st32 = run_form(0, gdata, grand, edges, args.steps, args.warmup)
     log(f"[bench] fp32: {args.steps / sec32:.2f} est/s, {1e3 * sec32 / args.steps:.3f} ms/step")
     k64 = args.fp64_steps or max(2, args.steps // 2)
-    res64, sec64, lat64, st64 = run_form(1, gdata, grand, edges, k64, max(1, args.warmup // 2))
-    log(f"[bench] fp64: {k64 / sec64:.2f} est/s")
+    if args.fp32_only:
+        res64, sec64, lat64, st64 = res32, float("nan"), np.full(1, np.nan), None
+    else:
+        res64, sec64, lat64, st64 = run_form(1, gdata, grand, edges, k64, max(1, args.warmup // 2))
+        log(f"[bench] fp64: {k64 / sec64:.2f} est/s")
     # FP32 form against the FP64 form (same inputs): the per-bin rule of the parity tests
     raw0 = res64["poles"][0] + res64["shot_noise"]
     scale = np.maximum(np.abs(res64["poles"]), np.abs(raw0)[None, :])
@@ -192,6 +205,8 @@ def main():
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat32, 50)), 3),
                        "p99": round(1e3 * float(np.percentile(lat32, 99)), 3)},
         "fp64": {"value": round(k64 / sec64, 3), "ms_per_step": round(1e3 * sec64 / k64, 4),
+                 "stage_ms_per_step": ({k: round(v / k64, 3) for k, v in st64["stage_ms"].items() if v > 0}
+                                       if not args.fp32_only else None),
                  "latency_ms": {"p50": round(1e3 * float(np.percentile(lat64, 50)), 3),
                                 "p99": round(1e3 * float(np.percentile(lat64, 99)), 3)}},
         "fp32_vs_fp64_max_scaled_err": fp32_err,

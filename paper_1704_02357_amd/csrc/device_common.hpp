@@ -208,6 +208,13 @@ __device__ __forceinline__ T ylm_eval(int ell, int m, T ux, T uy, T uz, const T*
   return q0 * (m >= 0 ? cr : ci);
 }
 
+// Atomic add to an LDS location (native ds_add_f32 / ds_add_f64; a plain atomicAdd through a
+// generic pointer may compile to a flat atomic).
+template <typename T> __device__ __forceinline__ void lds_atomic_add(T* p, T v) {
+  typedef __attribute__((address_space(3))) T LT;
+  __hip_atomic_fetch_add((LT*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Bin index of an integer squared wavenumber: largest i with thr[i] <= n2, if i < nb; else -1.
 __device__ __forceinline__ int kbin_of(long long n2, const long long* __restrict__ thr, int nb) {
   if (n2 < thr[0] || n2 >= thr[nb]) return -1;

@@ -31,10 +31,19 @@ hipError_t launch_catalog_sums(const double* w, const double* nbar, int64_t n, d
 
 template <typename T> hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s);
 
-// Mass assignment of one catalog onto d1 (and d2 at +1/2 cell when d2 != null).
+// Counting sort of particles by tile of their base node (tile side ts): per particle the
+// tile id and its rank within the tile (atomic counter), for catalog entries [base, base+n).
+hipError_t launch_tile_sort(const double* pos, int64_t n, int64_t base, const double* origin, double scale,
+                            int nmesh, int ts, int* count, int* tile_of, int* rank, hipStream_t s);
+// Exclusive scan of the tile counts (off has ntiles + 1 entries) and the permutation.
+hipError_t launch_tile_offsets(const int* count, int ntiles, int* off, const int* tile_of, const int* rank,
+                               int64_t ntot, int* perm, hipStream_t s);
+// Tile-wise painting of data (indices < nd, weight w) and randoms (weight -alpha w).
 template <typename T>
-hipError_t launch_paint(const double* pos, const double* w, int64_t n, double wscale, const double* origin,
-                        double scale, int nmesh, int window, T* d1, T* d2, hipStream_t s);
+hipError_t launch_paint_tiles(const int* off, const int* perm, int ntiles, int64_t nd, const double* dpos,
+                              const double* dw, const double* rpos, const double* rw, double alpha,
+                              const double* origin, double scale, int nmesh, int window, int ts, T* d1, T* d2,
+                              hipStream_t s);
 
 // Forward real-to-half-complex transform along z of nbuf real meshes (nbuf <= 2).
 template <typename T>

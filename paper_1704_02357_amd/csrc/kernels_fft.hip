@@ -27,7 +27,80 @@ template <typename T> __device__ __forceinline__ cx<T> ld(const void* p, size_t 
   return reinterpret_cast<const cx<T>*>(p)[i];
 }
 template <typename T> __device__ __forceinline__ void st(void* p, size_t i, cx<T> v) {
-  reinterpret_cast<cx<T>*>(p)[i] = v;
+  typedef __attribute__((address_space(1))) T GT;
+  GT* q = (GT*)p;
+  q[2 * i] = v.x;
+  q[2 * i + 1] = v.y;
+}
+
+// Global-memory accesses through address-space-1 pointers (buffer pointers read from a
+// device array would otherwise be generic and compile to flat instructions).
+#define PKM_GLOBAL __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ cx<T> gload(const cx<T>* p, size_t i) {
+  const PKM_GLOBAL T* q = (const PKM_GLOBAL T*)(const void*)p;
+  return mk<T>(q[2 * i], q[2 * i + 1]);
+}
+template <typename T> __device__ __forceinline__ void gstore(cx<T>* p, size_t i, cx<T> v) {
+  PKM_GLOBAL T* q = (PKM_GLOBAL T*)(void*)p;
+  q[2 * i] = v.x;
+  q[2 * i + 1] = v.y;
+}
+
+// Copy the twiddle table into LDS (n entries); returns the LDS copy.
+template <typename T>
+__device__ __forceinline__ cx<T>* stage_twiddles(cx<T>* dst, const cx<T>* __restrict__ tw, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = tw[i];
+  return dst;
+}
+
+// Tile of `tile` adjacent kz columns x n rows: element i = tid + j*bs (j < E) of the tile is
+// row i / tile, column i % tile.  All E loads are issued before any is consumed.
+template <typename T, int E>
+__device__ __forceinline__ void tile_load(cx<T>* v, const cx<T>* __restrict__ g, size_t base, size_t rs, int tile) {
+  const int bs = blockDim.x;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int i = threadIdx.x + j * bs;
+    v[j] = gload<T>(g, base + (size_t)(i / tile) * rs + (i % tile));
+  }
+}
+template <typename T, int E>
+__device__ __forceinline__ void tile_to_lds(cx<T>* lds, const cx<T>* v, int tile, int pitch) {
+  const int bs = blockDim.x;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int i = threadIdx.x + j * bs;
+    lds[(i / tile) * pitch + (i % tile)] = v[j];
+  }
+}
+template <typename T, int E>
+__device__ __forceinline__ void tile_store(cx<T>* __restrict__ g, const cx<T>* lds, size_t base, size_t rs, int tile,
+                                           int pitch) {
+  const int bs = blockDim.x;
+  cx<T> v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int i = threadIdx.x + j * bs;
+    v[j] = lds[(i / tile) * pitch + (i % tile)];
+  }
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int i = threadIdx.x + j * bs;
+    gstore<T>(g, base + (size_t)(i / tile) * rs + (i % tile), v[j]);
+  }
+}
+// G contiguous lines of nh complex: element i = tid + j*bs is line i / nh, entry i % nh.
+template <typename T, int E>
+__device__ __forceinline__ void lines_to_lds(cx<T>* lds, const cx<T>* __restrict__ src, int nh, int lp) {
+  const int bs = blockDim.x;
+  cx<T> v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) v[j] = gload<T>(src, threadIdx.x + j * bs);
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int i = threadIdx.x + j * bs;
+    lds[(i / nh) * lp + (i % nh)] = v[j];
+  }
 }
 
 // Forward split of a packed half-length transform: X_k = E_k + W_N^k O_k.
@@ -77,17 +150,17 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zfwd(int n, int G, uint32_t sc
   void* out = blockIdx.y ? out1 : out0;
   const size_t line0 = (size_t)blockIdx.x * G;
   const int tid = threadIdx.x;
-  const cx<T>* src = reinterpret_cast<const cx<T>*>(in) + line0 * nh;
-  for (int i = tid; i < G * nh; i += blockDim.x) lds[(i / nh) * lp + (i % nh)] = src[i];
+  cx<T>* twl = stage_twiddles<T>(lds + (size_t)G * lp, tw, n);
+  lines_to_lds<T, E>(lds, reinterpret_cast<const cx<T>*>(in) + line0 * nh, nh, lp);
   __syncthreads();
   const int t = tid % pt, g = tid / pt;
   cx<T>* line = lds + g * lp;
-  lds_fft<T, E, false>(lds, g * lp, 1, nh, sched, nst, t, pt, tw, n);
+  lds_fft<T, E, false>(lds, g * lp, 1, nh, sched, nst, t, pt, twl, n);
   const size_t ob = (line0 + g) * nh;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int k = t + pt * e;
-    st<T>(out, ob + k, r2c_split<T>(line, k, nh, tw));
+    st<T>(out, ob + k, r2c_split<T>(line, k, nh, twl));
   }
 }
 
@@ -107,18 +180,17 @@ __global__ void __launch_bounds__(XMAX_THREADS) k_col(int n, int tile, uint32_t 
   const size_t base = (size_t)outer * outer_stride + kz0;
   const int pitch = tile + 1;
   const int tid = threadIdx.x;
-  for (int i = tid; i < n * tile; i += blockDim.x) {
-    const int r = i / tile, c = i % tile;
-    lds[r * pitch + c] = buf[base + (size_t)r * row_stride + c];
+  cx<T>* twl = stage_twiddles<T>(lds + (size_t)n * pitch, tw, n);
+  {
+    cx<T> v[E];
+    tile_load<T, E>(v, buf, base, row_stride, tile);
+    tile_to_lds<T, E>(lds, v, tile, pitch);
   }
   __syncthreads();
   const int pt = n / E;
   const int c = tid % tile, t = tid / tile;
-  lds_fft<T, E, INV>(lds, c, pitch, n, sched, nst, t, pt, tw, n);
-  for (int i = tid; i < n * tile; i += blockDim.x) {
-    const int r = i / tile, cc = i % tile;
-    buf[base + (size_t)r * row_stride + cc] = lds[r * pitch + cc];
-  }
+  lds_fft<T, E, INV>(lds, c, pitch, n, sched, nst, t, pt, twl, n);
+  tile_store<T, E>(buf, lds, base, row_stride, tile, pitch);
 }
 
 __device__ __forceinline__ int sfreq(int j, int n) { return j < (n >> 1) ? j : j - n; }
@@ -157,22 +229,23 @@ __global__ void __launch_bounds__(XMAX_THREADS) k_xcombine(int n, int tile, uint
   const int c = tid % tile, t = tid / tile;
   const int kz = kz0 + c;
   cx<T> a1[E];
-  for (int i = tid; i < n * tile; i += blockDim.x) {
-    const int r = i / tile, cc = i % tile;
-    lds[r * pitch + cc] = s1[base + (size_t)r * rs + cc];
+  cx<T> v2[E];
+  cx<T>* twl = stage_twiddles<T>(lds + (size_t)n * pitch, tw, n);
+  {
+    cx<T> v[E];
+    tile_load<T, E>(v, s1, base, rs, tile);
+    if (interlaced) tile_load<T, E>(v2, s2, base, rs, tile);
+    tile_to_lds<T, E>(lds, v, tile, pitch);
   }
   __syncthreads();
-  lds_fft<T, E, false>(lds, c, pitch, n, sched, nst, t, pt, tw, n);
+  lds_fft<T, E, false>(lds, c, pitch, n, sched, nst, t, pt, twl, n);
 #pragma unroll
   for (int e = 0; e < E; ++e) a1[e] = lds[(t + pt * e) * pitch + c];
   if (interlaced) {
     __syncthreads();
-    for (int i = tid; i < n * tile; i += blockDim.x) {
-      const int r = i / tile, cc = i % tile;
-      lds[r * pitch + cc] = s2[base + (size_t)r * rs + cc];
-    }
+    tile_to_lds<T, E>(lds, v2, tile, pitch);
     __syncthreads();
-    lds_fft<T, E, false>(lds, c, pitch, n, sched, nst, t, pt, tw, n);
+    lds_fft<T, E, false>(lds, c, pitch, n, sched, nst, t, pt, twl, n);
     const cx<T> pyz = cmul<T>(phase[y], phase[kz]);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -189,18 +262,15 @@ __global__ void __launch_bounds__(XMAX_THREADS) k_xcombine(int n, int tile, uint
     if (compensated) v = cscale<T>(v, invw[x] * invw[y] * invw[kz]);
     if (ynyq || x == nh) v = mk<T>(T(0), T(0));
     a1[e] = v;
-    cout[base + c + (size_t)x * rs] = v;
+    gstore<T>(cout, base + c + (size_t)x * rs, v);
   }
   if (gout == nullptr) return;
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < E; ++e) lds[(t + pt * e) * pitch + c] = a1[e];
   __syncthreads();
-  lds_fft<T, E, true>(lds, c, pitch, n, sched, nst, t, pt, tw, n);
-  for (int i = tid; i < n * tile; i += blockDim.x) {
-    const int r = i / tile, cc = i % tile;
-    gout[base + (size_t)r * rs + cc] = lds[r * pitch + cc];
-  }
+  lds_fft<T, E, true>(lds, c, pitch, n, sched, nst, t, pt, twl, n);
+  tile_store<T, E>(gout, lds, base, rs, tile, pitch);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -221,6 +291,7 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n, int G, uint32_t sc
   const int t = tid % pt, g = tid / pt;
   const size_t lineg = line0 + g;
   cx<T>* line = lds + g * lp;
+  cx<T>* twl = stage_twiddles<T>(lds + (size_t)G * lp, tw, n);
   T r[2 * E];
   if (real_in) {
     const cx<T>* src = reinterpret_cast<const cx<T>*>(real_in) + lineg * nh;
@@ -231,17 +302,16 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n, int G, uint32_t sc
       r[2 * e + 1] = v.y;
     }
   } else {
-    const cx<T>* src = gin + line0 * nh;
-    for (int i = tid; i < G * nh; i += blockDim.x) lds[(i / nh) * lp + (i % nh)] = src[i];
+    lines_to_lds<T, E>(lds, gin + line0 * nh, nh, lp);
     __syncthreads();
     cx<T> z[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) z[e] = c2r_split<T>(line, t + pt * e, nh, tw);
+    for (int e = 0; e < E; ++e) z[e] = c2r_split<T>(line, t + pt * e, nh, twl);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) line[t + pt * e] = z[e];
     __syncthreads();
-    lds_fft<T, E, true>(lds, g * lp, 1, nh, sched, nst, t, pt, tw, n);
+    lds_fft<T, E, true>(lds, g * lp, 1, nh, sched, nst, t, pt, twl, n);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const cx<T> v = line[t + pt * e];
@@ -282,13 +352,13 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n, int G, uint32_t sc
       line[t + pt * e] = mk<T>(r[2 * e] * yv[0], r[2 * e + 1] * yv[1]);
     }
     __syncthreads();
-    lds_fft<T, E, false>(lds, g * lp, 1, nh, sched, nst, t, pt, tw, n);
+    lds_fft<T, E, false>(lds, g * lp, 1, nh, sched, nst, t, pt, twl, n);
     void* out = bufs[f];
     const size_t ob = lineg * nh;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int k = t + pt * e;
-      st<T>(out, ob + k, r2c_split<T>(line, k, nh, tw));
+      st<T>(out, ob + k, r2c_split<T>(line, k, nh, twl));
     }
     __syncthreads();
   }
@@ -297,7 +367,21 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n, int G, uint32_t sc
 // ------------------------------------------------------------------------------------------
 // x post-pass: forward x of each field, sum_m Y_lm(khat) B, product with C, binning
 // ------------------------------------------------------------------------------------------
-constexpr int MAX_SLOTS = 2;
+// Fields arrive ordered by slot (one slot per multipole l of the group).  One complex
+// accumulator per element holds sum_m Y_lm(khat) B_lm of the current slot.  After each
+// field's transform the thread scales its own LDS entries by Y_lm (a rolled loop, to keep
+// register pressure low) and adds them to the accumulator; at the last field of a slot the
+// accumulator is parked in the thread's own LDS entries and folded against C into the FP64
+// bin histogram.
+template <typename T>
+__device__ __forceinline__ void bin_fold(const cx<T>* a_lds, const cx<T>* __restrict__ cin, size_t gidx, int n2,
+                                         const long long* __restrict__ thr, int nb, double omega, double* h) {
+  const int bin = kbin_of(n2, thr, nb);
+  if (bin < 0) return;
+  const cx<T> a = *a_lds;
+  const cx<T> cv = gload<T>(cin, gidx);
+  lds_atomic_add<double>(&h[bin], omega * FOUR_PI * ((double)cv.x * (double)a.x + (double)cv.y * (double)a.y));
+}
 
 template <typename T, int E>
 __global__ void __launch_bounds__(XMAX_THREADS) k_xpost(int n, int tile, uint32_t sched, int nst, void* const* __restrict__ bufs, int nf,
@@ -309,11 +393,10 @@ __global__ void __launch_bounds__(XMAX_THREADS) k_xpost(int n, int tile, uint32_
   const int nh = n >> 1;
   const int pitch = tile + 1;
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
-  double* hist = reinterpret_cast<double*>(smem + sizeof(cx<T>) * (size_t)n * pitch);
+  double* hist = reinterpret_cast<double*>(smem + sizeof(cx<T>) * (size_t)n * (pitch + 1));
   const int l0rows = with_l0 ? 3 : 0;
   const int nvals = (l0rows + nslots) * nb;
   hist_zero(hist, copies * nvals);
-  __syncthreads();
   const int tiles = nh / tile;
   const int y = blockIdx.x / tiles;
   const int kz0 = (blockIdx.x % tiles) * tile;
@@ -324,59 +407,68 @@ __global__ void __launch_bounds__(XMAX_THREADS) k_xpost(int n, int tile, uint32_
   const int c = tid % tile, t = tid / tile;
   const int kz = kz0 + c;
   const int fy = sfreq(y, n);
-  T kinv[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int fx = sfreq(t + pt * e, n);
-    const T n2 = (T)fx * (T)fx + (T)fy * (T)fy + (T)kz * (T)kz;
-    kinv[e] = n2 > T(0) ? T(1) / sqrt(n2) : T(0);
-  }
-  cx<T> acc[MAX_SLOTS][E];
-#pragma unroll
-  for (int s = 0; s < MAX_SLOTS; ++s)
-#pragma unroll
-    for (int e = 0; e < E; ++e) acc[s][e] = mk<T>(T(0), T(0));
-  for (int f = 0; f < nf; ++f) {
-    const cx<T>* b = reinterpret_cast<const cx<T>*>(bufs[f]);
-    for (int i = tid; i < n * tile; i += blockDim.x) {
-      const int r = i / tile, cc = i % tile;
-      lds[r * pitch + cc] = b[base + (size_t)r * rs + cc];
-    }
-    __syncthreads();
-    lds_fft<T, E, false>(lds, c, pitch, n, sched, nst, t, pt, tw, n);
-    const int ell = fields[3 * f], m = fields[3 * f + 1], slot = fields[3 * f + 2];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const cx<T> v = lds[(t + pt * e) * pitch + c];
-      const T ki = kinv[e];
-      const T yv = ylm_eval<T>(ell, m, (T)sfreq(t + pt * e, n) * ki, (T)fy * ki, (T)kz * ki, ytab);
-      if (slot == 0) acc[0][e] = mk<T>(acc[0][e].x + yv * v.x, acc[0][e].y + yv * v.y);
-      else acc[1][e] = mk<T>(acc[1][e].x + yv * v.x, acc[1][e].y + yv * v.y);
-    }
-    __syncthreads();
-  }
-  const int wave = tid >> 6;
-  double* h = hist + (wave % copies) * nvals;
   const bool ynyq = (y == nh);
   const double omega = (kz == 0) ? 1.0 : 2.0;
+  double* h = hist + ((tid >> 6) % copies) * nvals;
+  cx<T>* twl = stage_twiddles<T>(lds + (size_t)n * pitch, tw, n);
+  cx<T> acc[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int x = t + pt * e;
-    const int fx = sfreq(x, n);
-    const long long n2 = (long long)fx * fx + (long long)fy * fy + (long long)kz * kz;
-    if (ynyq || x == nh || n2 == 0) continue;
-    const int bin = kbin_of(n2, thr, nb);
-    if (bin < 0) continue;
-    const cx<T> cv = cin[base + c + (size_t)x * rs];
-    if (with_l0) {
-      atomicAdd(&h[bin], omega);
-      atomicAdd(&h[nb + bin], omega * kf * sqrt((double)n2));
-      atomicAdd(&h[2 * nb + bin], omega * ((double)cv.x * (double)cv.x + (double)cv.y * (double)cv.y));
+  for (int e = 0; e < E; ++e) acc[e] = mk<T>(T(0), T(0));
+  cx<T> nxt[E];
+  if (nf > 0) tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[0]), base, rs, tile);
+  __syncthreads();
+  for (int f = 0; f < nf; ++f) {
+    tile_to_lds<T, E>(lds, nxt, tile, pitch);
+    // prefetch the next field's tile while this one is transformed
+    if (f + 1 < nf) tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[f + 1]), base, rs, tile);
+    __syncthreads();
+    lds_fft<T, E, false>(lds, c, pitch, n, sched, nst, t, pt, twl, n);
+    const int ell = fields[3 * f], m = fields[3 * f + 1], slot = fields[3 * f + 2];
+#pragma unroll 1
+    for (int e = 0; e < E; ++e) {
+      const int x = t + pt * e;
+      const T fx = (T)sfreq(x, n);
+      const T n2 = fx * fx + (T)fy * (T)fy + (T)kz * (T)kz;
+      const T ki = n2 > T(0) ? T(1) / sqrt(n2) : T(0);
+      const T yv = ylm_eval<T>(ell, m, fx * ki, (T)fy * ki, (T)kz * ki, ytab);
+      cx<T>* p = &lds[x * pitch + c];
+      *p = cscale<T>(*p, yv);
     }
-    for (int s = 0; s < nslots; ++s) {
-      const cx<T> a = s == 0 ? acc[0][e] : acc[1][e];
-      const double q = FOUR_PI * ((double)cv.x * (double)a.x + (double)cv.y * (double)a.y);
-      atomicAdd(&h[(l0rows + s) * nb + bin], omega * q);
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = cadd<T>(acc[e], lds[(t + pt * e) * pitch + c]);
+    if (f + 1 == nf || fields[3 * (f + 1) + 2] != slot) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        lds[(t + pt * e) * pitch + c] = acc[e];
+        acc[e] = mk<T>(T(0), T(0));
+      }
+      if (!ynyq) {
+        double* hs = h + (l0rows + slot) * nb;
+#pragma unroll 1
+        for (int e = 0; e < E; ++e) {
+          const int x = t + pt * e;
+          const int fx = sfreq(x, n);
+          const int n2 = fx * fx + fy * fy + kz * kz;
+          if (x == nh || n2 == 0) continue;
+          bin_fold<T>(&lds[x * pitch + c], cin, base + c + (size_t)x * rs, n2, thr, nb, omega, hs);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (with_l0 && !ynyq) {
+#pragma unroll 1
+    for (int e = 0; e < E; ++e) {
+      const int x = t + pt * e;
+      const int fx = sfreq(x, n);
+      const int n2 = fx * fx + fy * fy + kz * kz;
+      if (x == nh || n2 == 0) continue;
+      const int bin = kbin_of(n2, thr, nb);
+      if (bin < 0) continue;
+      const cx<T> cv = gload<T>(cin, base + c + (size_t)x * rs);
+      lds_atomic_add<double>(&h[bin], omega);
+      lds_atomic_add<double>(&h[nb + bin], omega * kf * sqrt((double)n2));
+      lds_atomic_add<double>(&h[2 * nb + bin], omega * ((double)cv.x * (double)cv.x + (double)cv.y * (double)cv.y));
     }
   }
   __syncthreads();
@@ -448,8 +540,8 @@ __global__ void k_kmu(int n, const cx<T>* __restrict__ cin, double l0, double l1
     const double p2 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
     const double omega = (kz == 0) ? 1.0 : 2.0;
     const int cell = kb * nmu + mb;
-    atomicAdd(&hist[2 * cell], omega);
-    atomicAdd(&hist[2 * cell + 1], omega * p2);
+    lds_atomic_add<double>(&hist[2 * cell], omega);
+    lds_atomic_add<double>(&hist[2 * cell + 1], omega * p2);
   }
   __syncthreads();
   hist_flush(hist, 1, nvals, partial + (size_t)blockIdx.x * nvals);
@@ -461,10 +553,10 @@ __global__ void k_kmu(int n, const cx<T>* __restrict__ cin, double l0, double l1
 // launchers
 // ------------------------------------------------------------------------------------------
 static int zthreads(const FftShape& fs) { return (fs.n / 2 / fs.e_z) * fs.zlines; }
-static size_t zsmem(const FftShape& fs, size_t cs) { return cs * (size_t)fs.zlines * (fs.n / 2 + 1); }
+static size_t zsmem(const FftShape& fs, size_t cs) { return cs * ((size_t)fs.zlines * (fs.n / 2 + 1) + fs.n); }
 int xpass_threads(const FftShape& fs) { return (fs.n / fs.e_col) * fs.tile; }
 int xpass_blocks(const FftShape& fs) { return fs.n * ((fs.n / 2) / fs.tile); }
-static size_t colsmem(const FftShape& fs, size_t cs) { return cs * (size_t)fs.n * (fs.tile + 1); }
+static size_t colsmem(const FftShape& fs, size_t cs) { return cs * (size_t)fs.n * (fs.tile + 2); }
 
 #define PKM_DISPATCH_E(EVAL, CALL)            \
   switch (EVAL) {                             \
@@ -535,7 +627,7 @@ template <typename T>
 hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const int* fields_dev, int nslots,
                         int with_l0, const void* c_in, const void* ytab, const BinSpec& bs, double kf,
                         double* partial, int* nblocks_out, const void* tw, hipStream_t s) {
-  if (nslots < 0 || nslots > MAX_SLOTS) return hipErrorInvalidValue;
+  if (nslots < 0) return hipErrorInvalidValue;
   const int rows = (with_l0 ? 3 : 0) + nslots;
   const size_t sm = colsmem(fs, sizeof(cx<T>)) + sizeof(double) * (size_t)bs.hist_copies * rows * bs.nb;
   *nblocks_out = xpass_blocks(fs);

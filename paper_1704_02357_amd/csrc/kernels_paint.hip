@@ -74,74 +74,189 @@ __device__ __forceinline__ int wrap(long long c, int n) {
   return (int)(r < 0 ? r + n : r);
 }
 
-// Per-axis taps of the assignment window at mesh coordinate u: nodes idx[0..nt) and weights.
-__device__ __forceinline__ int axis_taps(double u, int window, int nmesh, int* idx, double* wt) {
-  if (window == 1) {
-    const double c = floor(__dadd_rn(u, 0.5));
-    idx[0] = wrap((long long)c, nmesh);
-    wt[0] = 1.0;
-    return 1;
-  }
-  if (window == 2) {
-    const double c = floor(u);
-    const double d = __dsub_rn(u, c);
-    const long long ci = (long long)c;
-    idx[0] = wrap(ci, nmesh);
-    idx[1] = wrap(ci + 1, nmesh);
-    wt[0] = 1.0 - d;
-    wt[1] = d;
-    return 2;
-  }
-  const double c = floor(__dadd_rn(u, 0.5));
-  const double d = __dsub_rn(u, c);
-  const long long ci = (long long)c;
-  idx[0] = wrap(ci - 1, nmesh);
-  idx[1] = wrap(ci, nmesh);
-  idx[2] = wrap(ci + 1, nmesh);
-  const double a = 0.5 - d, b = 0.5 + d;
-  wt[0] = 0.5 * a * a;
-  wt[1] = 0.75 - d * d;
-  wt[2] = 0.5 * b * b;
-  return 3;
+// ---------------------------------------------------------------------------------------
+// Tile-sorted painting.  Particles are counting-sorted by the tile (TS^3 nodes) holding
+// their base node floor(u); each workgroup accumulates one tile plus its halo
+// ([t0 - 1, t0 + TS + 3) per axis, which holds every tap of NGP/CIC/TSC on both the plain
+// and the +1/2 interlaced mesh) in LDS, then adds the non-zero region cells to the global
+// meshes with atomics.  A tap that falls outside the region (only possible through FP64
+// rounding at a cell face) goes straight to a global atomic.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ void mesh_u(const double* __restrict__ pos, int64_t i, double o0, double o1, double o2,
+                                       double scale, double* u) {
+  u[0] = __dmul_rn(__dsub_rn(pos[3 * i + 0], o0), scale);
+  u[1] = __dmul_rn(__dsub_rn(pos[3 * i + 1], o1), scale);
+  u[2] = __dmul_rn(__dsub_rn(pos[3 * i + 2], o2), scale);
 }
 
-template <typename T>
-__device__ __forceinline__ void scatter(T* __restrict__ mesh, const double* u, double wgt, int window, int nmesh) {
-  int ix[3], iy[3], iz[3];
-  double wx[3], wy[3], wz[3];
-  const int nt = axis_taps(u[0], window, nmesh, ix, wx);
-  axis_taps(u[1], window, nmesh, iy, wy);
-  axis_taps(u[2], window, nmesh, iz, wz);
-  for (int a = 0; a < nt; ++a) {
-    const double wa = wgt * wx[a];
-    const size_t ba = (size_t)ix[a] * nmesh;
-    for (int b = 0; b < nt; ++b) {
-      const double wab = wa * wy[b];
-      const size_t bb = (ba + iy[b]) * nmesh;
-      for (int c = 0; c < nt; ++c) {
-        unsafeAtomicAdd(&mesh[bb + iz[c]], (T)(wab * wz[c]));
+__global__ void k_tile_count(const double* __restrict__ pos, int64_t n, int64_t base, double o0, double o1,
+                             double o2, double scale, int nmesh, int ts, int* __restrict__ count,
+                             int* __restrict__ tile_of, int* __restrict__ rank) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int tpa = nmesh / ts;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double u[3];
+    mesh_u(pos, i, o0, o1, o2, scale, u);
+    int tc[3];
+    for (int a = 0; a < 3; ++a) tc[a] = wrap((long long)floor(u[a]), nmesh) / ts;
+    const int tile = (tc[0] * tpa + tc[1]) * tpa + tc[2];
+    tile_of[base + i] = tile;
+    rank[base + i] = atomicAdd(&count[tile], 1);
+  }
+}
+
+constexpr int SCAN_THREADS = 1024;
+// Exclusive scan of count[0..n) into off[0..n], single workgroup, chunked.
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan(const int* __restrict__ count, int n, int* __restrict__ off) {
+  __shared__ int part[SCAN_THREADS];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < n; base += SCAN_THREADS) {
+    const int i = base + threadIdx.x;
+    const int v = i < n ? count[i] : 0;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < SCAN_THREADS; d <<= 1) {
+      const int add = (int)threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+      __syncthreads();
+      part[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (i < n) off[i] = carry + part[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == SCAN_THREADS - 1) carry += part[SCAN_THREADS - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) off[n] = carry;
+}
+
+__global__ void k_tile_scatter(const int* __restrict__ tile_of, const int* __restrict__ rank, int64_t n,
+                               const int* __restrict__ off, int* __restrict__ perm) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    perm[off[tile_of[i]] + rank[i]] = (int)i;
+}
+
+// Unwrapped taps of the window at u: nodes c0 + j (j < W) with weights wt[j].
+template <int W>
+__device__ __forceinline__ void taps_unwrapped(double u, long long* c0, double* wt) {
+  if constexpr (W == 1) {
+    *c0 = (long long)floor(__dadd_rn(u, 0.5));
+    wt[0] = 1.0;
+  } else if constexpr (W == 2) {
+    const double c = floor(u);
+    const double d = __dsub_rn(u, c);
+    *c0 = (long long)c;
+    wt[0] = 1.0 - d;
+    wt[1] = d;
+  } else {
+    const double c = floor(__dadd_rn(u, 0.5));
+    const double d = __dsub_rn(u, c);
+    *c0 = (long long)c - 1;
+    const double a = 0.5 - d, b = 0.5 + d;
+    wt[0] = 0.5 * a * a;
+    wt[1] = 0.75 - d * d;
+    wt[2] = 0.5 * b * b;
+  }
+}
+
+template <typename T, int W>
+__device__ __forceinline__ void tile_scatter(double* __restrict__ reg, T* __restrict__ mesh, const double* u,
+                                             double wgt, int nmesh, const long long* r0, int rsz) {
+  long long c0[3];
+  double w[3][W];
+  taps_unwrapped<W>(u[0], &c0[0], w[0]);
+  taps_unwrapped<W>(u[1], &c0[1], w[1]);
+  taps_unwrapped<W>(u[2], &c0[2], w[2]);
+  const int ra0 = (int)(c0[0] - r0[0]), rb0 = (int)(c0[1] - r0[1]), rc0 = (int)(c0[2] - r0[2]);
+  const bool inside = ra0 >= 0 && ra0 + W <= rsz && rb0 >= 0 && rb0 + W <= rsz && rc0 >= 0 && rc0 + W <= rsz;
+  if (inside) {
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+      const double wa = wgt * w[0][a];
+#pragma unroll
+      for (int b = 0; b < W; ++b) {
+        const double wab = wa * w[1][b];
+        const int row = ((ra0 + a) * rsz + (rb0 + b)) * rsz + rc0;
+#pragma unroll
+        for (int c = 0; c < W; ++c) lds_atomic_add<double>(&reg[row + c], wab * w[2][c]);
+      }
+    }
+    return;
+  }
+  // a tap outside the LDS region (FP64 rounding at a cell face): straight to the mesh
+#pragma unroll
+  for (int a = 0; a < W; ++a) {
+    const double wa = wgt * w[0][a];
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+      const double wab = wa * w[1][b];
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        const size_t g = ((size_t)wrap(c0[0] + a, nmesh) * nmesh + wrap(c0[1] + b, nmesh)) * nmesh +
+                         wrap(c0[2] + c, nmesh);
+        unsafeAtomicAdd(&mesh[g], (T)(wab * w[2][c]));
       }
     }
   }
 }
 
-template <typename T>
-__global__ void k_paint(const double* __restrict__ pos, const double* __restrict__ w, int64_t n, double wscale,
-                        double o0, double o1, double o2, double scale, int nmesh, int window, T* __restrict__ d1,
-                        T* __restrict__ d2) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+template <typename T, int W>
+__global__ void __launch_bounds__(256) k_paint_tiles(const int* __restrict__ off, const int* __restrict__ perm,
+                                                     int64_t nd, const double* __restrict__ dpos,
+                                                     const double* __restrict__ dw, const double* __restrict__ rpos,
+                                                     const double* __restrict__ rw, double alpha, double o0, double o1,
+                                                     double o2, double scale, int nmesh, int ts,
+                                                     T* __restrict__ d1, T* __restrict__ d2) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tile = blockIdx.x;
+  const int start = off[tile], end = off[tile + 1];
+  if (start == end) return;
+  const int rsz = ts + 4;
+  const int rcells = rsz * rsz * rsz;
+  double* r1 = reinterpret_cast<double*>(smem);   // FP64 accumulation for both precisions
+  double* r2 = r1 + rcells;
+  const int nreg = d2 ? 2 : 1;
+  for (int i = threadIdx.x; i < nreg * rcells; i += blockDim.x) r1[i] = 0.0;
+  const int tpa = nmesh / ts;
+  const int tz = tile % tpa, ty = (tile / tpa) % tpa, tx = tile / (tpa * tpa);
+  const int t0[3] = {tx * ts, ty * ts, tz * ts};
+  __syncthreads();
+  for (int j = start + threadIdx.x; j < end; j += blockDim.x) {
+    const int64_t i = perm[j];
+    const bool isd = i < nd;
+    const double* pos = isd ? dpos : rpos;
+    const int64_t k = isd ? i : i - nd;
+    const double* wp = isd ? dw : rw;
+    const double wgt = (wp ? wp[k] : 1.0) * (isd ? 1.0 : -alpha);
     double u[3];
-    u[0] = __dmul_rn(__dsub_rn(pos[3 * i + 0], o0), scale);
-    u[1] = __dmul_rn(__dsub_rn(pos[3 * i + 1], o1), scale);
-    u[2] = __dmul_rn(__dsub_rn(pos[3 * i + 2], o2), scale);
-    const double wgt = (w ? w[i] : 1.0) * wscale;
-    scatter<T>(d1, u, wgt, window, nmesh);
+    mesh_u(pos, k, o0, o1, o2, scale, u);
+    // region origin (unwrapped) = base tile origin of this particle's floor(u) - 1
+    long long r0[3];
+    for (int a = 0; a < 3; ++a) {
+      const long long cu = (long long)floor(u[a]);
+      r0[a] = cu - (wrap(cu, nmesh) - t0[a]) - 1;
+    }
+    tile_scatter<T, W>(r1, d1, u, wgt, nmesh, r0, rsz);
     if (d2) {
       u[0] = __dadd_rn(u[0], 0.5);
       u[1] = __dadd_rn(u[1], 0.5);
       u[2] = __dadd_rn(u[2], 0.5);
-      scatter<T>(d2, u, wgt, window, nmesh);
+      tile_scatter<T, W>(r2, d2, u, wgt, nmesh, r0, rsz);
+    }
+  }
+  __syncthreads();
+  for (int m = 0; m < nreg; ++m) {
+    const double* reg = m ? r2 : r1;
+    T* mesh = m ? d2 : d1;
+    for (int i = threadIdx.x; i < rcells; i += blockDim.x) {
+      const T v = (T)reg[i];
+      if (v == T(0)) continue;
+      const int rc = i % rsz, rb = (i / rsz) % rsz, ra = i / (rsz * rsz);
+      const size_t g = ((size_t)wrap(t0[0] - 1 + ra, nmesh) * nmesh + wrap(t0[1] - 1 + rb, nmesh)) * nmesh +
+                       wrap(t0[2] - 1 + rc, nmesh);
+      unsafeAtomicAdd(&mesh[g], v);
     }
   }
 }
@@ -165,22 +280,56 @@ template <typename T> hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s)
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_paint(const double* pos, const double* w, int64_t n, double wscale, const double* origin,
-                        double scale, int nmesh, int window, T* d1, T* d2, hipStream_t s) {
+hipError_t launch_tile_sort(const double* pos, int64_t n, int64_t base, const double* origin, double scale,
+                            int nmesh, int ts, int* count, int* tile_of, int* rank, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 16384) blocks = 16384;
-  k_paint<T><<<(unsigned)blocks, 256, 0, s>>>(pos, w, n, wscale, origin[0], origin[1], origin[2], scale, nmesh,
-                                             window, d1, d2);
+  k_tile_count<<<(unsigned)blocks, 256, 0, s>>>(pos, n, base, origin[0], origin[1], origin[2], scale, nmesh, ts,
+                                                count, tile_of, rank);
   return hipGetLastError();
 }
 
+hipError_t launch_tile_offsets(const int* count, int ntiles, int* off, const int* tile_of, const int* rank,
+                               int64_t ntot, int* perm, hipStream_t s) {
+  k_scan<<<1, SCAN_THREADS, 0, s>>>(count, ntiles, off);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || ntot == 0) return e;
+  int64_t blocks = (ntot + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  k_tile_scatter<<<(unsigned)blocks, 256, 0, s>>>(tile_of, rank, ntot, off, perm);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_paint_tiles(const int* off, const int* perm, int ntiles, int64_t nd, const double* dpos,
+                              const double* dw, const double* rpos, const double* rw, double alpha,
+                              const double* origin, double scale, int nmesh, int window, int ts, T* d1, T* d2,
+                              hipStream_t s) {
+  const int rsz = ts + 4;
+  const size_t sm = sizeof(double) * (size_t)rsz * rsz * rsz * (d2 ? 2 : 1);
+  if (window == 1)
+    k_paint_tiles<T, 1><<<ntiles, 256, sm, s>>>(off, perm, nd, dpos, dw, rpos, rw, alpha, origin[0], origin[1],
+                                                origin[2], scale, nmesh, ts, d1, d2);
+  else if (window == 2)
+    k_paint_tiles<T, 2><<<ntiles, 256, sm, s>>>(off, perm, nd, dpos, dw, rpos, rw, alpha, origin[0], origin[1],
+                                                origin[2], scale, nmesh, ts, d1, d2);
+  else if (window == 3)
+    k_paint_tiles<T, 3><<<ntiles, 256, sm, s>>>(off, perm, nd, dpos, dw, rpos, rw, alpha, origin[0], origin[1],
+                                                origin[2], scale, nmesh, ts, d1, d2);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template hipError_t launch_paint_tiles<float>(const int*, const int*, int, int64_t, const double*, const double*,
+                                              const double*, const double*, double, const double*, double, int, int,
+                                              int, float*, float*, hipStream_t);
+template hipError_t launch_paint_tiles<double>(const int*, const int*, int, int64_t, const double*, const double*,
+                                               const double*, const double*, double, const double*, double, int, int,
+                                               int, double*, double*, hipStream_t);
 template hipError_t launch_fill<float>(float*, size_t, float, hipStream_t);
+template hipError_t launch_fill<int>(int*, size_t, int, hipStream_t);
 template hipError_t launch_fill<double>(double*, size_t, double, hipStream_t);
-template hipError_t launch_paint<float>(const double*, const double*, int64_t, double, const double*, double, int,
-                                        int, float*, float*, hipStream_t);
-template hipError_t launch_paint<double>(const double*, const double*, int64_t, double, const double*, double, int,
-                                         int, double*, double*, hipStream_t);
 
 }  // namespace pkm

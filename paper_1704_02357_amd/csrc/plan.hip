@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <unordered_map>
@@ -61,6 +62,15 @@ struct pkm_plan {
   double* sums_dev = nullptr;  // 4 doubles + block partials
   double* cat_dev = nullptr;   // staging for host catalogs
   size_t cat_cap = 0;          // doubles
+  // tile sort of the particles
+  int ts = 16;                 // painting tile side
+  int ntiles = 0;
+  int* tile_count = nullptr;   // ntiles + 1
+  int* tile_off = nullptr;     // ntiles + 1
+  int* tile_of = nullptr;      // per particle
+  int* tile_rank = nullptr;
+  int* perm = nullptr;
+  size_t sort_cap = 0;         // particles
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // state
   bool painted = false;
@@ -337,22 +347,43 @@ template <typename T> void run_paint(pkm_plan* pl, const pkm_catalog* data, cons
     pl->norm_I = nbar * sd2;
     pl->shot = sd2 / pl->norm_I;
   }
-  // paint
+  // paint: tile sort, then per-tile LDS accumulation
   T* d1 = (T*)pl->d1;
   T* d2 = pl->p.interlaced ? (T*)pl->d2 : nullptr;
+  const double scale = (double)n / pl->p.box_len;
+  const int64_t nd = data->n, nr = rand ? rand->n : 0, ntot = nd + nr;
+  if ((size_t)ntot > pl->sort_cap) {
+    for (int** b : {&pl->tile_of, &pl->tile_rank, &pl->perm}) {
+      dfree(pl, *b);
+      *b = nullptr;
+    }
+    pl->sort_cap = 0;
+    pl->tile_of = (int*)dalloc(pl, sizeof(int) * ntot);
+    pl->tile_rank = (int*)dalloc(pl, sizeof(int) * ntot);
+    pl->perm = (int*)dalloc(pl, sizeof(int) * ntot);
+    pl->sort_cap = (size_t)ntot;
+  }
   {
     StageScope ss(pl, PKM_STAGE_FILL);
+    check_hip(pl, launch_fill<int>(pl->tile_count, (size_t)pl->ntiles, 0, s), "fill");
     check_hip(pl, launch_fill<T>(d1, cells, T(0), s), "fill");
     if (d2) check_hip(pl, launch_fill<T>(d2, cells, T(0), s), "fill");
   }
-  const double scale = (double)n / pl->p.box_len;
   {
     StageScope ss(pl, PKM_STAGE_PAINT);
-    check_hip(pl, launch_paint<T>(dp, dw, data->n, 1.0, pl->p.box_origin, scale, n, pl->p.window, d1, d2, s),
-              "paint");
+    check_hip(pl, launch_tile_sort(dp, nd, 0, pl->p.box_origin, scale, n, pl->ts, pl->tile_count, pl->tile_of,
+                                   pl->tile_rank, s),
+              "tile sort");
     if (rand)
-      check_hip(pl, launch_paint<T>(rp, rw, rand->n, -pl->alpha, pl->p.box_origin, scale, n, pl->p.window, d1, d2, s),
-                "paint randoms");
+      check_hip(pl, launch_tile_sort(rp, nr, nd, pl->p.box_origin, scale, n, pl->ts, pl->tile_count, pl->tile_of,
+                                     pl->tile_rank, s),
+                "tile sort");
+    check_hip(pl, launch_tile_offsets(pl->tile_count, pl->ntiles, pl->tile_off, pl->tile_of, pl->tile_rank, ntot,
+                                      pl->perm, s),
+              "tile offsets");
+    check_hip(pl, launch_paint_tiles<T>(pl->tile_off, pl->perm, pl->ntiles, nd, dp, dw, rp, rw, pl->alpha,
+                                        pl->p.box_origin, scale, n, pl->p.window, pl->ts, d1, d2, s),
+              "paint");
   }
   // forward transforms and combine
   const int nbuf = d2 ? 2 : 1;
@@ -413,11 +444,12 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
   std::vector<std::vector<F>> groups;
   const int fmax = (int)pl->fields.size();
   {
+    // fields ordered by l; a group holds at most fmax fields (any number of multipoles)
     std::vector<F> cur;
     int nl = 0, last_l = -1;
     for (int l = 2; l <= ell_max; l += 2) {
       for (int m = -l; m <= l; ++m) {
-        if ((int)cur.size() == fmax || (l != last_l && nl == 2)) {
+        if ((int)cur.size() == fmax) {
           groups.push_back(cur);
           cur.clear();
           nl = 0;
@@ -432,7 +464,7 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
   }
   const int rows = 3 + ell_max / 2;  // count, ksum, Q0, Q2, ...
   {
-    const size_t col_lds_b = sizeof(T) * 2 * (size_t)n * (pl->fs.tile + 1);
+    const size_t col_lds_b = sizeof(T) * 2 * (size_t)n * (pl->fs.tile + 2);
     if (col_lds_b + sizeof(double) * 5 * (size_t)nb > 160 * 1024) {
       pl->err = "too many k bins for one pass";
       throw Fail{PKM_EINVAL};
@@ -484,7 +516,7 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
   }
   // histogram copies per block: one per wave when the LDS budget allows
   const int waves = (xpass_threads(pl->fs) + 63) / 64;
-  const size_t col_lds = sizeof(T) * 2 * (size_t)n * (pl->fs.tile + 1);
+  const size_t col_lds = sizeof(T) * 2 * (size_t)n * (pl->fs.tile + 2);
   const size_t budget = 160 * 1024 - col_lds - 1024;
   check_hip(pl, launch_fill<double>(pl->out_dev, total_vals, 0.0, s), "zero out");
   check_hip(pl, hipEventRecord(pl->ev0, s), "event");
@@ -689,7 +721,8 @@ void free_all(pkm_plan* pl) {
   pl->fields.clear();
   for (void* ptr : {pl->d1, pl->d2, pl->s1, pl->s2, pl->c, pl->g, (void*)pl->ptrs_dev, (void*)pl->ftab_dev,
                     (void*)pl->map_dev, pl->tw, pl->ytab, pl->invw, pl->phase, (void*)pl->thr_dev, (void*)pl->partial,
-                    (void*)pl->out_dev, (void*)pl->sums_dev, (void*)pl->cat_dev})
+                    (void*)pl->out_dev, (void*)pl->sums_dev, (void*)pl->cat_dev, (void*)pl->tile_count,
+                    (void*)pl->tile_off, (void*)pl->tile_of, (void*)pl->tile_rank, (void*)pl->perm})
     dfree(pl, ptr);
   for (hipEvent_t e : pl->ev_pool) (void)hipEventDestroy(e);
   if (pl->ev0) (void)hipEventDestroy(pl->ev0);
@@ -769,6 +802,15 @@ pkm_status pkm_plan_create(const pkm_params* p, const pkm_device* dev, pkm_plan*
     pl->phase = dalloc(pl, 2 * pl->es * n);
     pl->ytab = dalloc(pl, pl->es * (YLM_LMAX + 1) * YLM_STRIDE);
     pl->sums_dev = (double*)dalloc(pl, sizeof(double) * (4 + 2 * SUM_BLOCKS));
+    pl->ts = 8;
+    if (const char* e = std::getenv("PKM_PAINT_TILE")) {  // tuning override: 4, 8 or 16
+      const int v = std::atoi(e);
+      if (v == 4 || v == 8 || v == 16) pl->ts = v;
+    }
+    while (n % pl->ts) pl->ts /= 2;
+    pl->ntiles = (n / pl->ts) * (n / pl->ts) * (n / pl->ts);
+    pl->tile_count = (int*)dalloc(pl, sizeof(int) * (pl->ntiles + 1));
+    pl->tile_off = (int*)dalloc(pl, sizeof(int) * (pl->ntiles + 1));
     int want = fields_for(pl->p.ell_max_hint);
     if (p->max_group > 0) want = std::min(want, p->max_group);
     ensure_fields(pl, std::max(want, 1));

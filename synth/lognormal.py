@@ -1,7 +1,7 @@
 """Seeded lognormal mock catalogs with a survey cut and radial redshift-space distortions.
 
 The paper measures on BOSS DR12 CMASS cutsky mocks, QPM boxes and cubic N-body boxes
-(Sec. 4.2 and Sec. 6); none are available here, so these seeded synthetic catalogs stand
+(Sec. 3.2 and Sec. 4.1); none are available here, so these seeded synthetic catalogs stand
 in for them with the same box scales and a BOSS-like number density.
 
 Recipe (all randomness from ``numpy.random.default_rng(seed)``, PCG64):
