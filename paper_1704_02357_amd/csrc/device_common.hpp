@@ -183,29 +183,48 @@ __device__ __forceinline__ void lds_fft(cx<T>* lds, int off, int es, int L, uint
 constexpr int YLM_LMAX = 16;
 constexpr int YLM_STRIDE = 2 * YLM_LMAX + 2;
 
-template <typename T>
-__device__ __forceinline__ T ylm_eval(int ell, int m, T ux, T uy, T uz, const T* __restrict__ tab) {
+// Y_lm at NV points at once: the recurrence order is the outer (wave-uniform) loop and the
+// points the inner unrolled loop, so every coefficient is loaded once (scalar) per step and
+// the NV chains run independently.
+template <typename T, int NV>
+__device__ __forceinline__ void ylm_vec(int ell, int m, const T* ux, const T* uy, const T* uz, T* out,
+                                        const T* __restrict__ tab) {
   const int am = m < 0 ? -m : m;
-  // (ux + i uy)^am
-  T cr = T(1), ci = T(0);
-  for (int j = 0; j < am; ++j) {
-    const T nr = cr * ux - ci * uy;
-    ci = cr * uy + ci * ux;
-    cr = nr;
-  }
   const T* c = tab + am * YLM_STRIDE;
-  T q0 = c[0];
-  if (ell > am) {
-    T q1 = c[1] * uz * q0;
-    for (int l = am + 2; l <= ell; ++l) {
-      const int j = l - am;
-      const T q2 = c[2 * j - 1] * uz * q1 - c[2 * j] * q0;
-      q0 = q1;
-      q1 = q2;
+  T cr[NV], ci[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) { cr[v] = T(1); ci[v] = T(0); }
+  for (int j = 0; j < am; ++j) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T nr = cr[v] * ux[v] - ci[v] * uy[v];
+      ci[v] = cr[v] * uy[v] + ci[v] * ux[v];
+      cr[v] = nr;
     }
-    q0 = q1;
   }
-  return q0 * (m >= 0 ? cr : ci);
+  const T c0 = c[0];
+  T q0[NV], q1[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) q0[v] = c0;
+  const int nrec = ell - am;
+  if (nrec >= 1) {
+    const T c1 = c[1];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) q1[v] = c1 * uz[v] * q0[v];
+    for (int j = 2; j <= nrec; ++j) {
+      const T a = c[2 * j - 1], b = c[2 * j];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const T q2 = a * uz[v] * q1[v] - b * q0[v];
+        q0[v] = q1[v];
+        q1[v] = q2;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) q0[v] = q1[v];
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[v] = q0[v] * (m < 0 ? ci[v] : cr[v]);
 }
 
 // Atomic add to an LDS location (native ds_add_f32 / ds_add_f64; a plain atomicAdd through a

@@ -17,6 +17,10 @@ struct FftShape {
   int nst_z;
   int tile;         // columns per column-pass tile
   int zlines;       // lines per z-pass block
+  int e_post;       // elements per thread in the post-pass (x transform + binning)
+  uint32_t sched_post;
+  int nst_post;
+  int tile_post;    // columns per post-pass tile
 };
 
 struct BinSpec {
@@ -90,5 +94,6 @@ hipError_t launch_kmu(const FftShape& fs, const void* c_in, const double* los, c
 
 int xpass_blocks(const FftShape& fs);
 int xpass_threads(const FftShape& fs);
+int post_blocks(const FftShape& fs);
 
 }  // namespace pkm

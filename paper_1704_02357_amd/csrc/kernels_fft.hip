@@ -46,6 +46,14 @@ template <typename T> __device__ __forceinline__ void gstore(cx<T>* p, size_t i,
   q[2 * i + 1] = v.y;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Remap so
+// that consecutive logical tiles (which share 128-byte rows when a tile is narrower than
+// that, and neighbouring rows otherwise) run on the same XCD one after the other.
+__device__ __forceinline__ int xcd_tile(int b, int nblk) {
+  if (nblk % 8) return b;
+  return (b % 8) * (nblk / 8) + b / 8;
+}
+
 // Copy the twiddle table into LDS (n entries); returns the LDS copy.
 template <typename T>
 __device__ __forceinline__ cx<T>* stage_twiddles(cx<T>* dst, const cx<T>* __restrict__ tw, int n) {
@@ -174,8 +182,9 @@ __global__ void __launch_bounds__(XMAX_THREADS) k_col(int n, int tile, uint32_t 
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
   const int nh = n >> 1;
   const int tiles = nh / tile;
-  const int outer = blockIdx.x / tiles;
-  const int kz0 = (blockIdx.x % tiles) * tile;
+  const int blk = xcd_tile(blockIdx.x, gridDim.x);
+  const int outer = blk / tiles;
+  const int kz0 = (blk % tiles) * tile;
   cx<T>* buf = reinterpret_cast<cx<T>*>(bufs[blockIdx.y]);
   const size_t base = (size_t)outer * outer_stride + kz0;
   const int pitch = tile + 1;
@@ -220,8 +229,9 @@ __global__ void __launch_bounds__(XMAX_THREADS) k_xcombine(int n, int tile, uint
   const int pitch = tile + 1;
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
   const int tiles = nh / tile;
-  const int y = blockIdx.x / tiles;
-  const int kz0 = (blockIdx.x % tiles) * tile;
+  const int blk = xcd_tile(blockIdx.x, gridDim.x);
+  const int y = blk / tiles;
+  const int kz0 = (blk % tiles) * tile;
   const size_t rs = (size_t)n * nh;
   const size_t base = (size_t)y * nh + kz0;
   const int tid = threadIdx.x;
@@ -338,18 +348,22 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n, int G, uint32_t sc
     const T rr = sqrt(pxy2 + pz * pz);
     inv[q] = rr > T(0) ? T(1) / rr : T(0);
   }
+  T ux[2 * E], uy[2 * E], uz[2 * E];
+#pragma unroll
+  for (int q = 0; q < 2 * E; ++q) {
+    const T pz = (T)(off2 + (2 * (t + pt * (q >> 1)) + (q & 1)) * h);
+    ux[q] = px * inv[q];
+    uy[q] = py * inv[q];
+    uz[q] = pz * inv[q];
+  }
   for (int f = 0; f < nf; ++f) {
-    const int ell = fields[3 * f], m = fields[3 * f + 1];
+    T yv[2 * E];
+    ylm_vec<T, 2 * E>(fields[3 * f], fields[3 * f + 1], ux, uy, uz, yv, ytab);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      T yv[2];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const T iv = inv[2 * e + q];
-        const T pz = (T)(off2 + (2 * (t + pt * e) + q) * h);
-        yv[q] = iv > T(0) ? ylm_eval<T>(ell, m, px * iv, py * iv, pz * iv, ytab) : T(0);
-      }
-      line[t + pt * e] = mk<T>(r[2 * e] * yv[0], r[2 * e + 1] * yv[1]);
+      const T y0 = inv[2 * e] > T(0) ? yv[2 * e] : T(0);
+      const T y1 = inv[2 * e + 1] > T(0) ? yv[2 * e + 1] : T(0);
+      line[t + pt * e] = mk<T>(r[2 * e] * y0, r[2 * e + 1] * y1);
     }
     __syncthreads();
     lds_fft<T, E, false>(lds, g * lp, 1, nh, sched, nst, t, pt, twl, n);
@@ -398,8 +412,9 @@ __global__ void __launch_bounds__(XMAX_THREADS) k_xpost(int n, int tile, uint32_
   const int nvals = (l0rows + nslots) * nb;
   hist_zero(hist, copies * nvals);
   const int tiles = nh / tile;
-  const int y = blockIdx.x / tiles;
-  const int kz0 = (blockIdx.x % tiles) * tile;
+  const int blk = xcd_tile(blockIdx.x, gridDim.x);
+  const int y = blk / tiles;
+  const int kz0 = (blk % tiles) * tile;
   const size_t rs = (size_t)n * nh;
   const size_t base = (size_t)y * nh + kz0;
   const int tid = threadIdx.x;
@@ -423,19 +438,29 @@ __global__ void __launch_bounds__(XMAX_THREADS) k_xpost(int n, int tile, uint32_
     if (f + 1 < nf) tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[f + 1]), base, rs, tile);
     __syncthreads();
     lds_fft<T, E, false>(lds, c, pitch, n, sched, nst, t, pt, twl, n);
-    const int ell = fields[3 * f], m = fields[3 * f + 1], slot = fields[3 * f + 2];
-#pragma unroll 1
-    for (int e = 0; e < E; ++e) {
-      const int x = t + pt * e;
-      const T fx = (T)sfreq(x, n);
-      const T n2 = fx * fx + (T)fy * (T)fy + (T)kz * (T)kz;
-      const T ki = n2 > T(0) ? T(1) / sqrt(n2) : T(0);
-      const T yv = ylm_eval<T>(ell, m, fx * ki, (T)fy * ki, (T)kz * ki, ytab);
-      cx<T>* p = &lds[x * pitch + c];
-      *p = cscale<T>(*p, yv);
-    }
+    const int slot = fields[3 * f + 2];
+    {
+      constexpr int H = E / 2;  // two halves keep the vectorised recurrence within registers
 #pragma unroll
-    for (int e = 0; e < E; ++e) acc[e] = cadd<T>(acc[e], lds[(t + pt * e) * pitch + c]);
+      for (int hh = 0; hh < 2; ++hh) {
+        T ux[H], uy[H], uz[H], yv[H];
+#pragma unroll
+        for (int v = 0; v < H; ++v) {
+          const T fx = (T)sfreq(t + pt * (hh * H + v), n);
+          const T n2 = fx * fx + (T)fy * (T)fy + (T)kz * (T)kz;
+          const T ki = n2 > T(0) ? T(1) / sqrt(n2) : T(0);
+          ux[v] = fx * ki;
+          uy[v] = (T)fy * ki;
+          uz[v] = (T)kz * ki;
+        }
+        ylm_vec<T, H>(fields[3 * f], fields[3 * f + 1], ux, uy, uz, yv, ytab);
+#pragma unroll
+        for (int v = 0; v < H; ++v) {
+          const cx<T> b = lds[(t + pt * (hh * H + v)) * pitch + c];
+          acc[hh * H + v] = mk<T>(acc[hh * H + v].x + yv[v] * b.x, acc[hh * H + v].y + yv[v] * b.y);
+        }
+      }
+    }
     if (f + 1 == nf || fields[3 * (f + 1) + 2] != slot) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -556,6 +581,7 @@ static int zthreads(const FftShape& fs) { return (fs.n / 2 / fs.e_z) * fs.zlines
 static size_t zsmem(const FftShape& fs, size_t cs) { return cs * ((size_t)fs.zlines * (fs.n / 2 + 1) + fs.n); }
 int xpass_threads(const FftShape& fs) { return (fs.n / fs.e_col) * fs.tile; }
 int xpass_blocks(const FftShape& fs) { return fs.n * ((fs.n / 2) / fs.tile); }
+int post_blocks(const FftShape& fs) { return fs.n * ((fs.n / 2) / fs.tile_post); }
 static size_t colsmem(const FftShape& fs, size_t cs) { return cs * (size_t)fs.n * (fs.tile + 2); }
 
 #define PKM_DISPATCH_E(EVAL, CALL)            \
@@ -629,12 +655,15 @@ hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const
                         double* partial, int* nblocks_out, const void* tw, hipStream_t s) {
   if (nslots < 0) return hipErrorInvalidValue;
   const int rows = (with_l0 ? 3 : 0) + nslots;
-  const size_t sm = colsmem(fs, sizeof(cx<T>)) + sizeof(double) * (size_t)bs.hist_copies * rows * bs.nb;
-  *nblocks_out = xpass_blocks(fs);
-  PKM_DISPATCH_E(fs.e_col, (k_xpost<T, E><<<xpass_blocks(fs), xpass_threads(fs), sm, s>>>(
-                               fs.n, fs.tile, fs.sched_col, fs.nst_col, bufs_dev, nf, fields_dev, nslots, with_l0,
-                               kf, (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies, partial,
-                               (const cx<T>*)tw)));
+  const size_t sm = sizeof(cx<T>) * (size_t)fs.n * (fs.tile_post + 2) +
+                    sizeof(double) * (size_t)bs.hist_copies * rows * bs.nb;
+  const int nblk = post_blocks(fs);
+  const int nthr = (fs.n / fs.e_post) * fs.tile_post;
+  *nblocks_out = nblk;
+  PKM_DISPATCH_E(fs.e_post, (k_xpost<T, E><<<nblk, nthr, sm, s>>>(
+                                fs.n, fs.tile_post, fs.sched_post, fs.nst_post, bufs_dev, nf, fields_dev, nslots,
+                                with_l0, kf, (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies,
+                                partial, (const cx<T>*)tw)));
   return hipGetLastError();
 }
 

@@ -464,7 +464,7 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
   }
   const int rows = 3 + ell_max / 2;  // count, ksum, Q0, Q2, ...
   {
-    const size_t col_lds_b = sizeof(T) * 2 * (size_t)n * (pl->fs.tile + 2);
+    const size_t col_lds_b = sizeof(T) * 2 * (size_t)n * (pl->fs.tile_post + 2);
     if (col_lds_b + sizeof(double) * 5 * (size_t)nb > 160 * 1024) {
       pl->err = "too many k bins for one pass";
       throw Fail{PKM_EINVAL};
@@ -506,7 +506,7 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
     pl->map_cap = (int)maps.size();
   }
   check_hip(pl, hipMemcpy(pl->map_dev, maps.data(), sizeof(int) * maps.size(), hipMemcpyHostToDevice), "maps");
-  const int nblk = xpass_blocks(pl->fs);
+  const int nblk = post_blocks(pl->fs);
   int max_nv = 0;
   for (int v : nvals_g) max_nv = std::max(max_nv, v);
   if (pl->partial_cap < (size_t)nblk * max_nv) {
@@ -515,8 +515,8 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
     pl->partial_cap = (size_t)nblk * max_nv;
   }
   // histogram copies per block: one per wave when the LDS budget allows
-  const int waves = (xpass_threads(pl->fs) + 63) / 64;
-  const size_t col_lds = sizeof(T) * 2 * (size_t)n * (pl->fs.tile + 2);
+  const int waves = ((n / pl->fs.e_post) * pl->fs.tile_post + 63) / 64;
+  const size_t col_lds = sizeof(T) * 2 * (size_t)n * (pl->fs.tile_post + 2);
   const size_t budget = 160 * 1024 - col_lds - 1024;
   check_hip(pl, launch_fill<double>(pl->out_dev, total_vals, 0.0, s), "zero out");
   check_hip(pl, hipEventRecord(pl->ev0, s), "event");
@@ -783,6 +783,23 @@ pkm_status pkm_plan_create(const pkm_params* p, const pkm_device* dev, pkm_plan*
   fs.tile = pl->fp64 ? 8 : 16;
   const int pt_col = n / fs.e_col;
   while (fs.tile > 1 && (pt_col * fs.tile > 512 || (n / 2) % fs.tile)) fs.tile /= 2;
+  // post-pass: at most 8 elements per thread (register budget of the fused recurrence)
+  fs.e_post = fs.e_col > 8 && fs.e_col % 8 == 0 ? 8 : fs.e_col;
+  if (fs.e_post == 12) fs.e_post = 6;
+  if (!make_sched(n, fs.e_post, &fs.sched_post, &fs.nst_post)) {
+    delete pl;
+    return PKM_EINVAL;
+  }
+  // 256-thread post-pass blocks (several resident per CU); narrow tiles share 128-byte rows
+  // through L2 because consecutive tiles run on the same XCD
+  {
+    const int pt_post = n / fs.e_post;
+    int tp = std::max(1, 256 / pt_post);
+    if (tp < 4) tp = std::max(1, 512 / pt_post);
+    tp = std::min(tp, 16);
+    while (tp > 1 && (n / 2) % tp) tp /= 2;
+    fs.tile_post = tp;
+  }
   const int pt_z = (n / 2) / fs.e_z;
   int zl = 1;
   while (zl * 2 * pt_z <= 256 && ((size_t)n * n) % (zl * 2) == 0) zl *= 2;
