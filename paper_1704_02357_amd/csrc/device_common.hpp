@@ -113,7 +113,11 @@ template <typename T, int R, bool INV> __device__ __forceinline__ void dft_r(cx<
 // tw[j] = exp(-2 pi i j / Ntw); W_{mR}^{q} = tw[q * Ntw/(mR)].  The caller must hold a
 // barrier between filling the lines and calling this; it returns after a barrier.
 // ---------------------------------------------------------------------------------------
-template <typename T, int E, int R, bool INV>
+// Physical LDS slot of element i: with PAD > 0 one spare slot follows every 2^PAD elements,
+// which breaks the power-of-two strides of the first Stockham stages across LDS banks.
+template <int PAD> __device__ __forceinline__ int padi(int i) { return PAD > 0 ? i + (i >> PAD) : i; }
+
+template <typename T, int E, int R, bool INV, int PAD>
 __device__ __forceinline__ void stockham_stage(cx<T>* lds, int off, int es, int L, int m, int t, int Pt,
                                                const cx<T>* __restrict__ tw, int Ntw) {
   constexpr int NB = E / R;
@@ -123,14 +127,15 @@ __device__ __forceinline__ void stockham_stage(cx<T>* lds, int off, int es, int 
   for (int q = 0; q < NB; ++q) {
     const int b = t + q * Pt;
 #pragma unroll
-    for (int s = 0; s < R; ++s) v[q * R + s] = lds[off + (b + s * Lr) * es];
+    for (int s = 0; s < R; ++s) v[q * R + s] = lds[off + padi<PAD>(b + s * Lr) * es];
   }
   __syncthreads();
   const int step = Ntw / (m * R);
+  const bool pow2 = (m & (m - 1)) == 0;
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const int b = t + q * Pt;
-    const int k = b % m;
+    const int k = pow2 ? (b & (m - 1)) : b % m;
     const int base = (b - k) * R + k;  // (b/m) m R + k
     if (k != 0) {
 #pragma unroll
@@ -142,32 +147,75 @@ __device__ __forceinline__ void stockham_stage(cx<T>* lds, int off, int es, int 
     }
     dft_r<T, R, INV>(&v[q * R]);
 #pragma unroll
-    for (int s = 0; s < R; ++s) lds[off + (base + s * m) * es] = v[q * R + s];
+    for (int s = 0; s < R; ++s) lds[off + padi<PAD>(base + s * m) * es] = v[q * R + s];
   }
   __syncthreads();
 }
 
+// Compile-time variant for power-of-two L: radices 8, then 4, then 2 (each dividing E), with
+// every index, span and twiddle step a constant.
+template <typename T, int E, int R, bool INV, int PAD, int L, int NTW, int M>
+__device__ __forceinline__ void stage_ct(cx<T>* lds, int off, int es, int t, const cx<T>* __restrict__ tw) {
+  constexpr int PT = L / E, NB = E / R, LR = L / R, STEP = NTW / (M * R);
+  cx<T> v[E];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int b = t + q * PT;
+#pragma unroll
+    for (int s = 0; s < R; ++s) v[q * R + s] = lds[off + padi<PAD>(b + s * LR) * es];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int b = t + q * PT;
+    const int k = b & (M - 1);
+    const int base = (b - k) * R + k;
+    if constexpr (M > 1) {
+#pragma unroll
+      for (int s = 1; s < R; ++s) {
+        cx<T> w = tw[s * k * STEP];
+        if (INV) w.y = -w.y;
+        v[q * R + s] = cmul<T>(v[q * R + s], w);
+      }
+    }
+    dft_r<T, R, INV>(&v[q * R]);
+#pragma unroll
+    for (int s = 0; s < R; ++s) lds[off + padi<PAD>(base + s * M) * es] = v[q * R + s];
+  }
+  __syncthreads();
+}
+
+template <typename T, int E, bool INV, int PAD, int L, int NTW, int M = 1>
+__device__ __forceinline__ void lds_fft_ct(cx<T>* lds, int off, int es, int t, const cx<T>* __restrict__ tw) {
+  constexpr int REM = L / M;
+  if constexpr (REM > 1) {
+    constexpr int R = (E % 8 == 0 && REM % 8 == 0) ? 8 : (E % 4 == 0 && REM % 4 == 0) ? 4 : 2;
+    stage_ct<T, E, R, INV, PAD, L, NTW, M>(lds, off, es, t, tw);
+    lds_fft_ct<T, E, INV, PAD, L, NTW, M * R>(lds, off, es, t, tw);
+  }
+}
+
 // Radix schedule packed 4 bits per stage (stage 0 in the low bits), nst stages.
-template <typename T, int E, bool INV>
+template <typename T, int E, bool INV, int PAD = 0>
 __device__ __forceinline__ void lds_fft(cx<T>* lds, int off, int es, int L, uint32_t sched, int nst, int t, int Pt,
                                         const cx<T>* __restrict__ tw, int Ntw) {
   int m = 1;
   for (int st = 0; st < nst; ++st) {
     const int r = (sched >> (4 * st)) & 15;
     if constexpr (E % 8 == 0) {
-      if (r == 8) { stockham_stage<T, E, 8, INV>(lds, off, es, L, m, t, Pt, tw, Ntw); m *= 8; continue; }
+      if (r == 8) { stockham_stage<T, E, 8, INV, PAD>(lds, off, es, L, m, t, Pt, tw, Ntw); m *= 8; continue; }
     }
     if constexpr (E % 6 == 0) {
-      if (r == 6) { stockham_stage<T, E, 6, INV>(lds, off, es, L, m, t, Pt, tw, Ntw); m *= 6; continue; }
+      if (r == 6) { stockham_stage<T, E, 6, INV, PAD>(lds, off, es, L, m, t, Pt, tw, Ntw); m *= 6; continue; }
     }
     if constexpr (E % 4 == 0) {
-      if (r == 4) { stockham_stage<T, E, 4, INV>(lds, off, es, L, m, t, Pt, tw, Ntw); m *= 4; continue; }
+      if (r == 4) { stockham_stage<T, E, 4, INV, PAD>(lds, off, es, L, m, t, Pt, tw, Ntw); m *= 4; continue; }
     }
     if constexpr (E % 3 == 0) {
-      if (r == 3) { stockham_stage<T, E, 3, INV>(lds, off, es, L, m, t, Pt, tw, Ntw); m *= 3; continue; }
+      if (r == 3) { stockham_stage<T, E, 3, INV, PAD>(lds, off, es, L, m, t, Pt, tw, Ntw); m *= 3; continue; }
     }
     if constexpr (E % 2 == 0) {
-      if (r == 2) { stockham_stage<T, E, 2, INV>(lds, off, es, L, m, t, Pt, tw, Ntw); m *= 2; continue; }
+      if (r == 2) { stockham_stage<T, E, 2, INV, PAD>(lds, off, es, L, m, t, Pt, tw, Ntw); m *= 2; continue; }
     }
   }
 }
@@ -183,48 +231,60 @@ __device__ __forceinline__ void lds_fft(cx<T>* lds, int off, int es, int L, uint
 constexpr int YLM_LMAX = 16;
 constexpr int YLM_STRIDE = 2 * YLM_LMAX + 2;
 
-// Y_lm at NV points at once: the recurrence order is the outer (wave-uniform) loop and the
-// points the inner unrolled loop, so every coefficient is loaded once (scalar) per step and
-// the NV chains run independently.
+// Running evaluation of real Y_lm at NV points over a sequence of fields.  The state keeps
+// (ux + i uy)^am and the recurrence pair (q_{l-1}^am, q_l^am) of the last field, so a field
+// with the same |m| and a larger l continues the recurrence, the -m partner of a field costs
+// nothing, and a field with |m| one larger costs one complex multiply plus a restart of the
+// recurrence.  Fields in any other order restart from scratch (still correct).  Control flow
+// depends only on (l, m), which are wave-uniform.
+template <typename T, int NV> struct YRun {
+  T cr[NV], ci[NV], q0[NV], q1[NV];
+  int am, l;
+};
+
+template <typename T, int NV> __device__ __forceinline__ void yrun_init(YRun<T, NV>& s) {
+  s.am = -1;
+  s.l = -1;
+}
+
 template <typename T, int NV>
-__device__ __forceinline__ void ylm_vec(int ell, int m, const T* ux, const T* uy, const T* uz, T* out,
-                                        const T* __restrict__ tab) {
+__device__ __forceinline__ void yrun_eval(YRun<T, NV>& s, int ell, int m, const T* ux, const T* uy, const T* uz,
+                                          T* out, const T* __restrict__ tab) {
   const int am = m < 0 ? -m : m;
-  const T* c = tab + am * YLM_STRIDE;
-  T cr[NV], ci[NV];
+  if (am != s.am || ell < s.l) {
+    if (s.am < 0 || am < s.am) {
 #pragma unroll
-  for (int v = 0; v < NV; ++v) { cr[v] = T(1); ci[v] = T(0); }
-  for (int j = 0; j < am; ++j) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const T nr = cr[v] * ux[v] - ci[v] * uy[v];
-      ci[v] = cr[v] * uy[v] + ci[v] * ux[v];
-      cr[v] = nr;
+      for (int v = 0; v < NV; ++v) { s.cr[v] = T(1); s.ci[v] = T(0); }
+      s.am = 0;
     }
-  }
-  const T c0 = c[0];
-  T q0[NV], q1[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) q0[v] = c0;
-  const int nrec = ell - am;
-  if (nrec >= 1) {
-    const T c1 = c[1];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) q1[v] = c1 * uz[v] * q0[v];
-    for (int j = 2; j <= nrec; ++j) {
-      const T a = c[2 * j - 1], b = c[2 * j];
+    for (int j = s.am; j < am; ++j) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const T q2 = a * uz[v] * q1[v] - b * q0[v];
-        q0[v] = q1[v];
-        q1[v] = q2;
+        const T nr = s.cr[v] * ux[v] - s.ci[v] * uy[v];
+        s.ci[v] = s.cr[v] * uy[v] + s.ci[v] * ux[v];
+        s.cr[v] = nr;
       }
     }
+    s.am = am;
+    const T c0 = tab[am * YLM_STRIDE];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) q0[v] = q1[v];
+    for (int v = 0; v < NV; ++v) { s.q1[v] = c0; s.q0[v] = T(0); }
+    s.l = am;
   }
+  const T* c = tab + am * YLM_STRIDE;
+  for (int l = s.l + 1; l <= ell; ++l) {
+    const int j = l - am;
+    const T a = c[2 * j - 1], b = c[2 * j];  // b = 0 for j = 1
 #pragma unroll
-  for (int v = 0; v < NV; ++v) out[v] = q0[v] * (m < 0 ? ci[v] : cr[v]);
+    for (int v = 0; v < NV; ++v) {
+      const T q2 = a * uz[v] * s.q1[v] - b * s.q0[v];
+      s.q0[v] = s.q1[v];
+      s.q1[v] = q2;
+    }
+  }
+  s.l = ell;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[v] = s.q1[v] * (m < 0 ? s.ci[v] : s.cr[v]);
 }
 
 // Atomic add to an LDS location (native ds_add_f32 / ds_add_f64; a plain atomicAdd through a

@@ -39,15 +39,17 @@ template <typename T> hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s)
 // tile id and its rank within the tile (atomic counter), for catalog entries [base, base+n).
 hipError_t launch_tile_sort(const double* pos, int64_t n, int64_t base, const double* origin, double scale,
                             int nmesh, int ts, int* count, int* tile_of, int* rank, hipStream_t s);
-// Exclusive scan of the tile counts (off has ntiles + 1 entries) and the permutation.
+// Exclusive scan of the tile counts (off has ntiles + 1 entries), then the particle payload
+// (x, y, z, w for data / -alpha w for randoms; 32 bytes each) written in tile order.
 hipError_t launch_tile_offsets(const int* count, int ntiles, int* off, const int* tile_of, const int* rank,
-                               int64_t ntot, int* perm, hipStream_t s);
-// Tile-wise painting of data (indices < nd, weight w) and randoms (weight -alpha w).
+                               int64_t nd, int64_t ntot, const double* dpos, const double* dw, const double* rpos,
+                               const double* rw, double alpha, void* payload, int* bsum, hipStream_t s);
+// Scratch entries needed by the tile scan (block sums).
+inline int tile_scan_scratch(int ntiles) { return (ntiles + 1023) / 1024 + 1; }
+// Tile-wise painting from the sorted payload.
 template <typename T>
-hipError_t launch_paint_tiles(const int* off, const int* perm, int ntiles, int64_t nd, const double* dpos,
-                              const double* dw, const double* rpos, const double* rw, double alpha,
-                              const double* origin, double scale, int nmesh, int window, int ts, T* d1, T* d2,
-                              hipStream_t s);
+hipError_t launch_paint_tiles(const int* off, const void* payload, int ntiles, const double* origin, double scale,
+                              int nmesh, int window, int ts, T* d1, T* d2, hipStream_t s);
 
 // Forward real-to-half-complex transform along z of nbuf real meshes (nbuf <= 2).
 template <typename T>

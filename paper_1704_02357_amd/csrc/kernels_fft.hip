@@ -22,6 +22,10 @@ namespace pkm {
 namespace {
 
 constexpr double FOUR_PI = 12.566370614359172953850573533118;
+constexpr int ZPAD = 3;  // z-line LDS layout: one spare slot per 8 complex
+__host__ __device__ constexpr int zpitch(int nh) { return nh + (nh >> ZPAD) + 1; }
+constexpr int XPAD = 3;  // post-pass tile: one spare row per 8 rows
+__host__ __device__ constexpr int xrows(int n) { return n + (n >> XPAD) + 1; }
 
 template <typename T> __device__ __forceinline__ cx<T> ld(const void* p, size_t i) {
   return reinterpret_cast<const cx<T>*>(p)[i];
@@ -63,13 +67,16 @@ __device__ __forceinline__ cx<T>* stage_twiddles(cx<T>* dst, const cx<T>* __rest
 
 // Tile of `tile` adjacent kz columns x n rows: element i = tid + j*bs (j < E) of the tile is
 // row i / tile, column i % tile.  All E loads are issued before any is consumed.
+__device__ __forceinline__ int tdiv(int i, int tile) { return (tile & (tile - 1)) == 0 ? i >> (__ffs(tile) - 1) : i / tile; }
+__device__ __forceinline__ int tmod(int i, int tile) { return (tile & (tile - 1)) == 0 ? i & (tile - 1) : i % tile; }
+
 template <typename T, int E>
 __device__ __forceinline__ void tile_load(cx<T>* v, const cx<T>* __restrict__ g, size_t base, size_t rs, int tile) {
   const int bs = blockDim.x;
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int i = threadIdx.x + j * bs;
-    v[j] = gload<T>(g, base + (size_t)(i / tile) * rs + (i % tile));
+    v[j] = gload<T>(g, base + (size_t)tdiv(i, tile) * rs + tmod(i, tile));
   }
 }
 template <typename T, int E>
@@ -78,9 +85,19 @@ __device__ __forceinline__ void tile_to_lds(cx<T>* lds, const cx<T>* v, int tile
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int i = threadIdx.x + j * bs;
-    lds[(i / tile) * pitch + (i % tile)] = v[j];
+    lds[tdiv(i, tile) * pitch + tmod(i, tile)] = v[j];
   }
 }
+template <typename T, int E>
+__device__ __forceinline__ void tile_to_lds_padded(cx<T>* lds, const cx<T>* v, int tile, int pitch) {
+  const int bs = blockDim.x;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int i = threadIdx.x + j * bs;
+    lds[padi<XPAD>(tdiv(i, tile)) * pitch + tmod(i, tile)] = v[j];
+  }
+}
+
 template <typename T, int E>
 __device__ __forceinline__ void tile_store(cx<T>* __restrict__ g, const cx<T>* lds, size_t base, size_t rs, int tile,
                                            int pitch) {
@@ -89,12 +106,12 @@ __device__ __forceinline__ void tile_store(cx<T>* __restrict__ g, const cx<T>* l
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int i = threadIdx.x + j * bs;
-    v[j] = lds[(i / tile) * pitch + (i % tile)];
+    v[j] = lds[tdiv(i, tile) * pitch + tmod(i, tile)];
   }
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int i = threadIdx.x + j * bs;
-    gstore<T>(g, base + (size_t)(i / tile) * rs + (i % tile), v[j]);
+    gstore<T>(g, base + (size_t)tdiv(i, tile) * rs + tmod(i, tile), v[j]);
   }
 }
 // G contiguous lines of nh complex: element i = tid + j*bs is line i / nh, entry i % nh.
@@ -107,15 +124,15 @@ __device__ __forceinline__ void lines_to_lds(cx<T>* lds, const cx<T>* __restrict
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int i = threadIdx.x + j * bs;
-    lds[(i / nh) * lp + (i % nh)] = v[j];
+    lds[(i / nh) * lp + padi<ZPAD>(i % nh)] = v[j];
   }
 }
 
 // Forward split of a packed half-length transform: X_k = E_k + W_N^k O_k.
 template <typename T>
 __device__ __forceinline__ cx<T> r2c_split(const cx<T>* line, int k, int nh, const cx<T>* __restrict__ tw) {
-  const cx<T> zk = line[k];
-  const cx<T> zm = cconj<T>(line[k == 0 ? 0 : nh - k]);
+  const cx<T> zk = line[padi<ZPAD>(k)];
+  const cx<T> zm = cconj<T>(line[padi<ZPAD>(k == 0 ? 0 : nh - k)]);
   const cx<T> e = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y + zm.y));
   const cx<T> d = mk<T>(T(0.5) * (zk.x - zm.x), T(0.5) * (zk.y - zm.y));
   const cx<T> o = mk<T>(d.y, -d.x);  // d / i
@@ -126,13 +143,13 @@ __device__ __forceinline__ cx<T> r2c_split(const cx<T>* line, int k, int nh, con
 // O_k = (X_k - conj X_{nh-k}) conj(W_N^k) / 2; X_{nh} = 0 and X_0 taken real.
 template <typename T>
 __device__ __forceinline__ cx<T> c2r_split(const cx<T>* line, int k, int nh, const cx<T>* __restrict__ tw) {
-  cx<T> xk = line[k];
+  cx<T> xk = line[padi<ZPAD>(k)];
   cx<T> xp;
   if (k == 0) {
     xk.y = T(0);
     xp = mk<T>(T(0), T(0));
   } else {
-    xp = cconj<T>(line[nh - k]);
+    xp = cconj<T>(line[padi<ZPAD>(nh - k)]);
   }
   const cx<T> e = mk<T>(T(0.5) * (xk.x + xp.x), T(0.5) * (xk.y + xp.y));
   const cx<T> d = mk<T>(T(0.5) * (xk.x - xp.x), T(0.5) * (xk.y - xp.y));
@@ -152,7 +169,7 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zfwd(int n, int G, uint32_t sc
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
   const int nh = n >> 1;
-  const int lp = nh + 1;
+  const int lp = zpitch(nh);
   const int pt = nh / E;
   const T* in = blockIdx.y ? in1 : in0;
   void* out = blockIdx.y ? out1 : out0;
@@ -163,7 +180,7 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zfwd(int n, int G, uint32_t sc
   __syncthreads();
   const int t = tid % pt, g = tid / pt;
   cx<T>* line = lds + g * lp;
-  lds_fft<T, E, false>(lds, g * lp, 1, nh, sched, nst, t, pt, twl, n);
+  lds_fft<T, E, false, ZPAD>(lds, g * lp, 1, nh, sched, nst, t, pt, twl, n);
   const size_t ob = (line0 + g) * nh;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -294,7 +311,7 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n, int G, uint32_t sc
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
   const int nh = n >> 1;
-  const int lp = nh + 1;
+  const int lp = zpitch(nh);
   const int pt = nh / E;
   const size_t line0 = (size_t)blockIdx.x * G;
   const int tid = threadIdx.x;
@@ -319,12 +336,12 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n, int G, uint32_t sc
     for (int e = 0; e < E; ++e) z[e] = c2r_split<T>(line, t + pt * e, nh, twl);
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) line[t + pt * e] = z[e];
+    for (int e = 0; e < E; ++e) line[padi<ZPAD>(t + pt * e)] = z[e];
     __syncthreads();
-    lds_fft<T, E, true>(lds, g * lp, 1, nh, sched, nst, t, pt, twl, n);
+    lds_fft<T, E, true, ZPAD>(lds, g * lp, 1, nh, sched, nst, t, pt, twl, n);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const cx<T> v = line[t + pt * e];
+      const cx<T> v = line[padi<ZPAD>(t + pt * e)];
       r[2 * e] = v.x * scale;
       r[2 * e + 1] = v.y * scale;
     }
@@ -356,18 +373,20 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n, int G, uint32_t sc
     uy[q] = py * inv[q];
     uz[q] = pz * inv[q];
   }
+  YRun<T, 2 * E> yr;
+  yrun_init(yr);
   for (int f = 0; f < nf; ++f) {
     T yv[2 * E];
-    ylm_vec<T, 2 * E>(fields[3 * f], fields[3 * f + 1], ux, uy, uz, yv, ytab);
+    yrun_eval<T, 2 * E>(yr, fields[4 * f + 1], fields[4 * f + 2], ux, uy, uz, yv, ytab);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const T y0 = inv[2 * e] > T(0) ? yv[2 * e] : T(0);
       const T y1 = inv[2 * e + 1] > T(0) ? yv[2 * e + 1] : T(0);
-      line[t + pt * e] = mk<T>(r[2 * e] * y0, r[2 * e + 1] * y1);
+      line[padi<ZPAD>(t + pt * e)] = mk<T>(r[2 * e] * y0, r[2 * e + 1] * y1);
     }
     __syncthreads();
-    lds_fft<T, E, false>(lds, g * lp, 1, nh, sched, nst, t, pt, twl, n);
-    void* out = bufs[f];
+    lds_fft<T, E, false, ZPAD>(lds, g * lp, 1, nh, sched, nst, t, pt, twl, n);
+    void* out = bufs[fields[4 * f]];
     const size_t ob = lineg * nh;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -397,8 +416,10 @@ __device__ __forceinline__ void bin_fold(const cx<T>* a_lds, const cx<T>* __rest
   lds_atomic_add<double>(&h[bin], omega * FOUR_PI * ((double)cv.x * (double)a.x + (double)cv.y * (double)a.y));
 }
 
+constexpr int XPOST_THREADS = 256;
+
 template <typename T, int E>
-__global__ void __launch_bounds__(XMAX_THREADS) k_xpost(int n, int tile, uint32_t sched, int nst, void* const* __restrict__ bufs, int nf,
+__global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n, int tile, uint32_t sched, int nst, void* const* __restrict__ bufs, int nf,
                         const int* __restrict__ fields, int nslots, int with_l0, double kf,
                         const cx<T>* __restrict__ cin, const T* __restrict__ ytab,
                         const long long* __restrict__ thr, int nb, int copies, double* __restrict__ partial,
@@ -407,7 +428,7 @@ __global__ void __launch_bounds__(XMAX_THREADS) k_xpost(int n, int tile, uint32_
   const int nh = n >> 1;
   const int pitch = tile + 1;
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
-  double* hist = reinterpret_cast<double*>(smem + sizeof(cx<T>) * (size_t)n * (pitch + 1));
+  double* hist = reinterpret_cast<double*>(smem + sizeof(cx<T>) * ((size_t)xrows(n) * pitch + n));
   const int l0rows = with_l0 ? 3 : 0;
   const int nvals = (l0rows + nslots) * nb;
   hist_zero(hist, copies * nvals);
@@ -419,52 +440,54 @@ __global__ void __launch_bounds__(XMAX_THREADS) k_xpost(int n, int tile, uint32_
   const size_t base = (size_t)y * nh + kz0;
   const int tid = threadIdx.x;
   const int pt = n / E;
-  const int c = tid % tile, t = tid / tile;
+  // rows fastest across the lanes of a wave (with the padded rows this keeps the Stockham
+  // stages close to bank-conflict free)
+  const int t = tid % pt, c = tid / pt;
   const int kz = kz0 + c;
   const int fy = sfreq(y, n);
   const bool ynyq = (y == nh);
   const double omega = (kz == 0) ? 1.0 : 2.0;
   double* h = hist + ((tid >> 6) % copies) * nvals;
-  cx<T>* twl = stage_twiddles<T>(lds + (size_t)n * pitch, tw, n);
+  cx<T>* twl = stage_twiddles<T>(lds + (size_t)xrows(n) * pitch, tw, n);
   cx<T> acc[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) acc[e] = mk<T>(T(0), T(0));
+  // unit wave vectors of this thread's modes
+  T ux[E], uy[E], uz[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const T fx = (T)sfreq(t + pt * e, n);
+    const T n2 = fx * fx + (T)fy * (T)fy + (T)kz * (T)kz;
+    const T ki = n2 > T(0) ? T(1) / sqrt(n2) : T(0);
+    ux[e] = fx * ki;
+    uy[e] = (T)fy * ki;
+    uz[e] = (T)kz * ki;
+  }
+  YRun<T, E> yr;
+  yrun_init(yr);
   cx<T> nxt[E];
-  if (nf > 0) tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[0]), base, rs, tile);
+  if (nf > 0) tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[0]]), base, rs, tile);
   __syncthreads();
   for (int f = 0; f < nf; ++f) {
-    tile_to_lds<T, E>(lds, nxt, tile, pitch);
+    tile_to_lds_padded<T, E>(lds, nxt, tile, pitch);
     // prefetch the next field's tile while this one is transformed
-    if (f + 1 < nf) tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[f + 1]), base, rs, tile);
+    if (f + 1 < nf) tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[4 * (f + 1)]]), base, rs, tile);
     __syncthreads();
-    lds_fft<T, E, false>(lds, c, pitch, n, sched, nst, t, pt, twl, n);
-    const int slot = fields[3 * f + 2];
+    lds_fft<T, E, false, XPAD>(lds, c, pitch, n, sched, nst, t, pt, twl, n);
+    const int slot = fields[4 * f + 3];
     {
-      constexpr int H = E / 2;  // two halves keep the vectorised recurrence within registers
-#pragma unroll
-      for (int hh = 0; hh < 2; ++hh) {
-        T ux[H], uy[H], uz[H], yv[H];
-#pragma unroll
-        for (int v = 0; v < H; ++v) {
-          const T fx = (T)sfreq(t + pt * (hh * H + v), n);
-          const T n2 = fx * fx + (T)fy * (T)fy + (T)kz * (T)kz;
-          const T ki = n2 > T(0) ? T(1) / sqrt(n2) : T(0);
-          ux[v] = fx * ki;
-          uy[v] = (T)fy * ki;
-          uz[v] = (T)kz * ki;
-        }
-        ylm_vec<T, H>(fields[3 * f], fields[3 * f + 1], ux, uy, uz, yv, ytab);
-#pragma unroll
-        for (int v = 0; v < H; ++v) {
-          const cx<T> b = lds[(t + pt * (hh * H + v)) * pitch + c];
-          acc[hh * H + v] = mk<T>(acc[hh * H + v].x + yv[v] * b.x, acc[hh * H + v].y + yv[v] * b.y);
-        }
-      }
-    }
-    if (f + 1 == nf || fields[3 * (f + 1) + 2] != slot) {
+      T yv[E];
+      yrun_eval<T, E>(yr, fields[4 * f + 1], fields[4 * f + 2], ux, uy, uz, yv, ytab);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        lds[(t + pt * e) * pitch + c] = acc[e];
+        const cx<T> b = lds[padi<XPAD>(t + pt * e) * pitch + c];
+        acc[e] = mk<T>(acc[e].x + yv[e] * b.x, acc[e].y + yv[e] * b.y);
+      }
+    }
+    if (f + 1 == nf || fields[4 * (f + 1) + 3] != slot) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        lds[padi<XPAD>(t + pt * e) * pitch + c] = acc[e];
         acc[e] = mk<T>(T(0), T(0));
       }
       if (!ynyq) {
@@ -475,7 +498,7 @@ __global__ void __launch_bounds__(XMAX_THREADS) k_xpost(int n, int tile, uint32_
           const int fx = sfreq(x, n);
           const int n2 = fx * fx + fy * fy + kz * kz;
           if (x == nh || n2 == 0) continue;
-          bin_fold<T>(&lds[x * pitch + c], cin, base + c + (size_t)x * rs, n2, thr, nb, omega, hs);
+          bin_fold<T>(&lds[padi<XPAD>(x) * pitch + c], cin, base + c + (size_t)x * rs, n2, thr, nb, omega, hs);
         }
       }
     }
@@ -578,7 +601,7 @@ __global__ void k_kmu(int n, const cx<T>* __restrict__ cin, double l0, double l1
 // launchers
 // ------------------------------------------------------------------------------------------
 static int zthreads(const FftShape& fs) { return (fs.n / 2 / fs.e_z) * fs.zlines; }
-static size_t zsmem(const FftShape& fs, size_t cs) { return cs * ((size_t)fs.zlines * (fs.n / 2 + 1) + fs.n); }
+static size_t zsmem(const FftShape& fs, size_t cs) { return cs * ((size_t)fs.zlines * zpitch(fs.n / 2) + fs.n); }
 int xpass_threads(const FftShape& fs) { return (fs.n / fs.e_col) * fs.tile; }
 int xpass_blocks(const FftShape& fs) { return fs.n * ((fs.n / 2) / fs.tile); }
 int post_blocks(const FftShape& fs) { return fs.n * ((fs.n / 2) / fs.tile_post); }
@@ -655,10 +678,11 @@ hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const
                         double* partial, int* nblocks_out, const void* tw, hipStream_t s) {
   if (nslots < 0) return hipErrorInvalidValue;
   const int rows = (with_l0 ? 3 : 0) + nslots;
-  const size_t sm = sizeof(cx<T>) * (size_t)fs.n * (fs.tile_post + 2) +
+  const size_t sm = sizeof(cx<T>) * ((size_t)xrows(fs.n) * (fs.tile_post + 1) + fs.n) +
                     sizeof(double) * (size_t)bs.hist_copies * rows * bs.nb;
   const int nblk = post_blocks(fs);
   const int nthr = (fs.n / fs.e_post) * fs.tile_post;
+  if (nthr > XPOST_THREADS) return hipErrorInvalidValue;
   *nblocks_out = nblk;
   PKM_DISPATCH_E(fs.e_post, (k_xpost<T, E><<<nblk, nthr, sm, s>>>(
                                 fs.n, fs.tile_post, fs.sched_post, fs.nst_post, bufs_dev, nf, fields_dev, nslots,

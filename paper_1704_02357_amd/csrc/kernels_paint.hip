@@ -106,36 +106,72 @@ __global__ void k_tile_count(const double* __restrict__ pos, int64_t n, int64_t 
 }
 
 constexpr int SCAN_THREADS = 1024;
-// Exclusive scan of count[0..n) into off[0..n], single workgroup, chunked.
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan(const int* __restrict__ count, int n, int* __restrict__ off) {
+// Exclusive scan in three launches: per-block scans (block sums out), one-block scan of
+// the block sums, and the addition of the scanned sums.  Coalesced throughout.
+__device__ __forceinline__ int block_scan_excl(int v, int* part) {
+  part[threadIdx.x] = v;
+  __syncthreads();
+  for (int d = 1; d < SCAN_THREADS; d <<= 1) {
+    const int add = (int)threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  return part[threadIdx.x] - v;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_blocks(const int* __restrict__ count, int n,
+                                                              int* __restrict__ off, int* __restrict__ bsum) {
+  __shared__ int part[SCAN_THREADS];
+  const int i = blockIdx.x * SCAN_THREADS + threadIdx.x;
+  const int v = i < n ? count[i] : 0;
+  const int ex = block_scan_excl(v, part);
+  if (i < n) off[i] = ex;
+  if (threadIdx.x == SCAN_THREADS - 1) bsum[blockIdx.x] = ex + v;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_sums(int* __restrict__ bsum, int nb, int* __restrict__ off,
+                                                            int n) {
   __shared__ int part[SCAN_THREADS];
   __shared__ int carry;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
-  for (int base = 0; base < n; base += SCAN_THREADS) {
+  for (int base = 0; base < nb; base += SCAN_THREADS) {
     const int i = base + threadIdx.x;
-    const int v = i < n ? count[i] : 0;
-    part[threadIdx.x] = v;
+    const int v = i < nb ? bsum[i] : 0;
+    const int ex = block_scan_excl(v, part);
+    if (i < nb) bsum[i] = carry + ex;
     __syncthreads();
-    for (int d = 1; d < SCAN_THREADS; d <<= 1) {
-      const int add = (int)threadIdx.x >= d ? part[threadIdx.x - d] : 0;
-      __syncthreads();
-      part[threadIdx.x] += add;
-      __syncthreads();
-    }
-    if (i < n) off[i] = carry + part[threadIdx.x] - v;
-    __syncthreads();
-    if (threadIdx.x == SCAN_THREADS - 1) carry += part[SCAN_THREADS - 1];
+    if (threadIdx.x == SCAN_THREADS - 1) carry += ex + v;
     __syncthreads();
   }
   if (threadIdx.x == 0) off[n] = carry;
 }
 
-__global__ void k_tile_scatter(const int* __restrict__ tile_of, const int* __restrict__ rank, int64_t n,
-                               const int* __restrict__ off, int* __restrict__ perm) {
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_add(const int* __restrict__ bsum, int n,
+                                                           int* __restrict__ off) {
+  const int i = blockIdx.x * SCAN_THREADS + threadIdx.x;
+  if (i < n) off[i] += bsum[blockIdx.x];
+}
+
+// Scatter each particle's payload (x, y, z, signed weight) to its slot in tile order.
+__global__ void k_tile_scatter(const int* __restrict__ tile_of, const int* __restrict__ rank, int64_t nd, int64_t n,
+                               const int* __restrict__ off, const double* __restrict__ dpos,
+                               const double* __restrict__ dw, const double* __restrict__ rpos,
+                               const double* __restrict__ rw, double alpha, double4* __restrict__ payload) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    perm[off[tile_of[i]] + rank[i]] = (int)i;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const bool isd = i < nd;
+    const int64_t k = isd ? i : i - nd;
+    const double* pos = isd ? dpos : rpos;
+    const double* wp = isd ? dw : rw;
+    double4 p;
+    p.x = pos[3 * k];
+    p.y = pos[3 * k + 1];
+    p.z = pos[3 * k + 2];
+    p.w = (wp ? wp[k] : 1.0) * (isd ? 1.0 : -alpha);
+    payload[off[tile_of[i]] + rank[i]] = p;
+  }
 }
 
 // Unwrapped taps of the window at u: nodes c0 + j (j < W) with weights wt[j].
@@ -203,11 +239,8 @@ __device__ __forceinline__ void tile_scatter(double* __restrict__ reg, T* __rest
 }
 
 template <typename T, int W>
-__global__ void __launch_bounds__(256) k_paint_tiles(const int* __restrict__ off, const int* __restrict__ perm,
-                                                     int64_t nd, const double* __restrict__ dpos,
-                                                     const double* __restrict__ dw, const double* __restrict__ rpos,
-                                                     const double* __restrict__ rw, double alpha, double o0, double o1,
-                                                     double o2, double scale, int nmesh, int ts,
+__global__ void __launch_bounds__(256) k_paint_tiles(const int* __restrict__ off, const double4* __restrict__ payload,
+                                                     double o0, double o1, double o2, double scale, int nmesh, int ts,
                                                      T* __restrict__ d1, T* __restrict__ d2) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tile = blockIdx.x;
@@ -224,14 +257,12 @@ __global__ void __launch_bounds__(256) k_paint_tiles(const int* __restrict__ off
   const int t0[3] = {tx * ts, ty * ts, tz * ts};
   __syncthreads();
   for (int j = start + threadIdx.x; j < end; j += blockDim.x) {
-    const int64_t i = perm[j];
-    const bool isd = i < nd;
-    const double* pos = isd ? dpos : rpos;
-    const int64_t k = isd ? i : i - nd;
-    const double* wp = isd ? dw : rw;
-    const double wgt = (wp ? wp[k] : 1.0) * (isd ? 1.0 : -alpha);
+    const double4 p = payload[j];
+    const double wgt = p.w;
     double u[3];
-    mesh_u(pos, k, o0, o1, o2, scale, u);
+    u[0] = __dmul_rn(__dsub_rn(p.x, o0), scale);
+    u[1] = __dmul_rn(__dsub_rn(p.y, o1), scale);
+    u[2] = __dmul_rn(__dsub_rn(p.z, o2), scale);
     // region origin (unwrapped) = base tile origin of this particle's floor(u) - 1
     long long r0[3];
     for (int a = 0; a < 3; ++a) {
@@ -291,43 +322,44 @@ hipError_t launch_tile_sort(const double* pos, int64_t n, int64_t base, const do
 }
 
 hipError_t launch_tile_offsets(const int* count, int ntiles, int* off, const int* tile_of, const int* rank,
-                               int64_t ntot, int* perm, hipStream_t s) {
-  k_scan<<<1, SCAN_THREADS, 0, s>>>(count, ntiles, off);
+                               int64_t nd, int64_t ntot, const double* dpos, const double* dw, const double* rpos,
+                               const double* rw, double alpha, void* payload, int* bsum, hipStream_t s) {
+  const int nblk = (ntiles + SCAN_THREADS - 1) / SCAN_THREADS;
+  k_scan_blocks<<<nblk, SCAN_THREADS, 0, s>>>(count, ntiles, off, bsum);
+  k_scan_sums<<<1, SCAN_THREADS, 0, s>>>(bsum, nblk, off, ntiles);
+  k_scan_add<<<nblk, SCAN_THREADS, 0, s>>>(bsum, ntiles, off);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ntot == 0) return e;
   int64_t blocks = (ntot + 255) / 256;
   if (blocks > 16384) blocks = 16384;
-  k_tile_scatter<<<(unsigned)blocks, 256, 0, s>>>(tile_of, rank, ntot, off, perm);
+  k_tile_scatter<<<(unsigned)blocks, 256, 0, s>>>(tile_of, rank, nd, ntot, off, dpos, dw, rpos, rw, alpha,
+                                                  (double4*)payload);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_paint_tiles(const int* off, const int* perm, int ntiles, int64_t nd, const double* dpos,
-                              const double* dw, const double* rpos, const double* rw, double alpha,
-                              const double* origin, double scale, int nmesh, int window, int ts, T* d1, T* d2,
-                              hipStream_t s) {
+hipError_t launch_paint_tiles(const int* off, const void* payload, int ntiles, const double* origin, double scale,
+                              int nmesh, int window, int ts, T* d1, T* d2, hipStream_t s) {
   const int rsz = ts + 4;
   const size_t sm = sizeof(double) * (size_t)rsz * rsz * rsz * (d2 ? 2 : 1);
   if (window == 1)
-    k_paint_tiles<T, 1><<<ntiles, 256, sm, s>>>(off, perm, nd, dpos, dw, rpos, rw, alpha, origin[0], origin[1],
-                                                origin[2], scale, nmesh, ts, d1, d2);
+    k_paint_tiles<T, 1><<<ntiles, 256, sm, s>>>(off, (const double4*)payload, origin[0], origin[1], origin[2],
+                                                scale, nmesh, ts, d1, d2);
   else if (window == 2)
-    k_paint_tiles<T, 2><<<ntiles, 256, sm, s>>>(off, perm, nd, dpos, dw, rpos, rw, alpha, origin[0], origin[1],
-                                                origin[2], scale, nmesh, ts, d1, d2);
+    k_paint_tiles<T, 2><<<ntiles, 256, sm, s>>>(off, (const double4*)payload, origin[0], origin[1], origin[2],
+                                                scale, nmesh, ts, d1, d2);
   else if (window == 3)
-    k_paint_tiles<T, 3><<<ntiles, 256, sm, s>>>(off, perm, nd, dpos, dw, rpos, rw, alpha, origin[0], origin[1],
-                                                origin[2], scale, nmesh, ts, d1, d2);
+    k_paint_tiles<T, 3><<<ntiles, 256, sm, s>>>(off, (const double4*)payload, origin[0], origin[1], origin[2],
+                                                scale, nmesh, ts, d1, d2);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-template hipError_t launch_paint_tiles<float>(const int*, const int*, int, int64_t, const double*, const double*,
-                                              const double*, const double*, double, const double*, double, int, int,
-                                              int, float*, float*, hipStream_t);
-template hipError_t launch_paint_tiles<double>(const int*, const int*, int, int64_t, const double*, const double*,
-                                               const double*, const double*, double, const double*, double, int, int,
-                                               int, double*, double*, hipStream_t);
+template hipError_t launch_paint_tiles<float>(const int*, const void*, int, const double*, double, int, int, int,
+                                              float*, float*, hipStream_t);
+template hipError_t launch_paint_tiles<double>(const int*, const void*, int, const double*, double, int, int, int,
+                                               double*, double*, hipStream_t);
 template hipError_t launch_fill<float>(float*, size_t, float, hipStream_t);
 template hipError_t launch_fill<int>(int*, size_t, int, hipStream_t);
 template hipError_t launch_fill<double>(double*, size_t, double, hipStream_t);

@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -69,7 +70,8 @@ struct pkm_plan {
   int* tile_off = nullptr;     // ntiles + 1
   int* tile_of = nullptr;      // per particle
   int* tile_rank = nullptr;
-  int* perm = nullptr;
+  void* payload = nullptr;     // 32 bytes per particle, tile order
+  int* scan_sums = nullptr;    // block sums of the tile scan
   size_t sort_cap = 0;         // particles
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // state
@@ -353,14 +355,16 @@ template <typename T> void run_paint(pkm_plan* pl, const pkm_catalog* data, cons
   const double scale = (double)n / pl->p.box_len;
   const int64_t nd = data->n, nr = rand ? rand->n : 0, ntot = nd + nr;
   if ((size_t)ntot > pl->sort_cap) {
-    for (int** b : {&pl->tile_of, &pl->tile_rank, &pl->perm}) {
+    for (int** b : {&pl->tile_of, &pl->tile_rank}) {
       dfree(pl, *b);
       *b = nullptr;
     }
+    dfree(pl, pl->payload);
+    pl->payload = nullptr;
     pl->sort_cap = 0;
     pl->tile_of = (int*)dalloc(pl, sizeof(int) * ntot);
     pl->tile_rank = (int*)dalloc(pl, sizeof(int) * ntot);
-    pl->perm = (int*)dalloc(pl, sizeof(int) * ntot);
+    pl->payload = dalloc(pl, 32 * (size_t)ntot);
     pl->sort_cap = (size_t)ntot;
   }
   {
@@ -378,11 +382,11 @@ template <typename T> void run_paint(pkm_plan* pl, const pkm_catalog* data, cons
       check_hip(pl, launch_tile_sort(rp, nr, nd, pl->p.box_origin, scale, n, pl->ts, pl->tile_count, pl->tile_of,
                                      pl->tile_rank, s),
                 "tile sort");
-    check_hip(pl, launch_tile_offsets(pl->tile_count, pl->ntiles, pl->tile_off, pl->tile_of, pl->tile_rank, ntot,
-                                      pl->perm, s),
+    check_hip(pl, launch_tile_offsets(pl->tile_count, pl->ntiles, pl->tile_off, pl->tile_of, pl->tile_rank, nd, ntot,
+                                      dp, dw, rp, rw, pl->alpha, pl->payload, pl->scan_sums, s),
               "tile offsets");
-    check_hip(pl, launch_paint_tiles<T>(pl->tile_off, pl->perm, pl->ntiles, nd, dp, dw, rp, rw, pl->alpha,
-                                        pl->p.box_origin, scale, n, pl->p.window, pl->ts, d1, d2, s),
+    check_hip(pl, launch_paint_tiles<T>(pl->tile_off, pl->payload, pl->ntiles, pl->p.box_origin, scale, n,
+                                        pl->p.window, pl->ts, d1, d2, s),
               "paint");
   }
   // forward transforms and combine
@@ -464,7 +468,7 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
   }
   const int rows = 3 + ell_max / 2;  // count, ksum, Q0, Q2, ...
   {
-    const size_t col_lds_b = sizeof(T) * 2 * (size_t)n * (pl->fs.tile_post + 2);
+    const size_t col_lds_b = sizeof(T) * 2 * ((size_t)(n + n / 8 + 1) * (pl->fs.tile_post + 1) + n);
     if (col_lds_b + sizeof(double) * 5 * (size_t)nb > 160 * 1024) {
       pl->err = "too many k bins for one pass";
       throw Fail{PKM_EINVAL};
@@ -476,14 +480,27 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
     pl->out_dev = (double*)dalloc(pl, sizeof(double) * total_vals);
     pl->out_cap = total_vals;
   }
-  // table of (l, m, slot) for all groups, and reduce maps
+  // Per group two field tables of (buffer, l, m, slot): the pre-pass walks the fields
+  // |m|-major (|m| ascending, then l, +m before -m) so the harmonic recurrence of one field
+  // continues from the previous one; the post-pass walks them l-major (slots contiguous),
+  // |m| ascending with +m before -m.  Buffer b of a group holds its b-th field (l-major).
   std::vector<int> ftab, maps;
-  std::vector<int> fofs, mofs, nvals_g, nslots_g;
+  std::vector<int> fofs, pofs, mofs, nvals_g, nslots_g;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
-    fofs.push_back((int)ftab.size() / 3);
-    for (auto& f : groups[gi]) { ftab.push_back(f.l); ftab.push_back(f.m); ftab.push_back(f.slot); }
+    const auto& g = groups[gi];
+    std::vector<int> idx(g.size());
+    for (size_t i = 0; i < g.size(); ++i) idx[i] = (int)i;
+    auto key_pre = [&](int i) { return std::make_tuple(std::abs(g[i].m), g[i].l, g[i].m < 0); };
+    auto key_post = [&](int i) { return std::make_tuple(g[i].slot, std::abs(g[i].m), g[i].m < 0); };
+    std::vector<int> pre = idx, post = idx;
+    std::stable_sort(pre.begin(), pre.end(), [&](int a, int b) { return key_pre(a) < key_pre(b); });
+    std::stable_sort(post.begin(), post.end(), [&](int a, int b) { return key_post(a) < key_post(b); });
+    fofs.push_back((int)ftab.size() / 4);
+    for (int i : pre) { ftab.push_back(i); ftab.push_back(g[i].l); ftab.push_back(g[i].m); ftab.push_back(g[i].slot); }
+    pofs.push_back((int)ftab.size() / 4);
+    for (int i : post) { ftab.push_back(i); ftab.push_back(g[i].l); ftab.push_back(g[i].m); ftab.push_back(g[i].slot); }
     std::vector<int> slot_l;
-    for (auto& f : groups[gi]) if ((int)slot_l.size() <= f.slot) slot_l.push_back(f.l);
+    for (auto& f : g) if ((int)slot_l.size() <= f.slot) slot_l.push_back(f.l);
     const bool first = gi == 0;
     mofs.push_back((int)maps.size());
     int nv = 0;
@@ -493,10 +510,10 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
     nvals_g.push_back(nv);
     nslots_g.push_back((int)slot_l.size());
   }
-  if (pl->ftab_cap < (int)ftab.size() + 3) {
+  if (pl->ftab_cap < (int)ftab.size() + 4) {
     dfree(pl, pl->ftab_dev);
-    pl->ftab_dev = (int*)dalloc(pl, sizeof(int) * (ftab.size() + 3));
-    pl->ftab_cap = (int)ftab.size() + 3;
+    pl->ftab_dev = (int*)dalloc(pl, sizeof(int) * (ftab.size() + 4));
+    pl->ftab_cap = (int)ftab.size() + 4;
   }
   if (!ftab.empty())
     check_hip(pl, hipMemcpy(pl->ftab_dev, ftab.data(), sizeof(int) * ftab.size(), hipMemcpyHostToDevice), "ftab");
@@ -516,7 +533,7 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
   }
   // histogram copies per block: one per wave when the LDS budget allows
   const int waves = ((n / pl->fs.e_post) * pl->fs.tile_post + 63) / 64;
-  const size_t col_lds = sizeof(T) * 2 * (size_t)n * (pl->fs.tile_post + 2);
+  const size_t col_lds = sizeof(T) * 2 * ((size_t)(n + n / 8 + 1) * (pl->fs.tile_post + 1) + n);
   const size_t budget = 160 * 1024 - col_lds - 1024;
   check_hip(pl, launch_fill<double>(pl->out_dev, total_vals, 0.0, s), "zero out");
   check_hip(pl, hipEventRecord(pl->ev0, s), "event");
@@ -529,7 +546,8 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const int nf = (int)groups[gi].size();
     nfields_total += nf;
-    const int* ft = pl->ftab_dev + 3 * fofs[gi];
+    const int* ft = pl->ftab_dev + 4 * fofs[gi];
+    const int* ftp = pl->ftab_dev + 4 * pofs[gi];
     if (nf > 0) {
       {
         StageScope ss(pl, PKM_STAGE_ZPRE);
@@ -546,7 +564,7 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
     int nblocks = 0;
     {
     StageScope ss(pl, PKM_STAGE_XPOST);
-    check_hip(pl, launch_xpost<T>(pl->fs, pl->ptrs_dev, nf, ft, nslots_g[gi], gi == 0 ? 1 : 0, pl->c, pl->ytab,
+    check_hip(pl, launch_xpost<T>(pl->fs, pl->ptrs_dev, nf, ftp, nslots_g[gi], gi == 0 ? 1 : 0, pl->c, pl->ytab,
                                   BinSpec{pl->thr_dev, nb, copies}, (double)(2.0 * M_PI / pl->p.box_len), pl->partial,
                                   &nblocks, pl->tw, s),
               "xpost");
@@ -722,7 +740,8 @@ void free_all(pkm_plan* pl) {
   for (void* ptr : {pl->d1, pl->d2, pl->s1, pl->s2, pl->c, pl->g, (void*)pl->ptrs_dev, (void*)pl->ftab_dev,
                     (void*)pl->map_dev, pl->tw, pl->ytab, pl->invw, pl->phase, (void*)pl->thr_dev, (void*)pl->partial,
                     (void*)pl->out_dev, (void*)pl->sums_dev, (void*)pl->cat_dev, (void*)pl->tile_count,
-                    (void*)pl->tile_off, (void*)pl->tile_of, (void*)pl->tile_rank, (void*)pl->perm})
+                    (void*)pl->tile_off, (void*)pl->tile_of, (void*)pl->tile_rank, pl->payload,
+                    (void*)pl->scan_sums})
     dfree(pl, ptr);
   for (hipEvent_t e : pl->ev_pool) (void)hipEventDestroy(e);
   if (pl->ev0) (void)hipEventDestroy(pl->ev0);
@@ -795,7 +814,6 @@ pkm_status pkm_plan_create(const pkm_params* p, const pkm_device* dev, pkm_plan*
   {
     const int pt_post = n / fs.e_post;
     int tp = std::max(1, 256 / pt_post);
-    if (tp < 4) tp = std::max(1, 512 / pt_post);
     tp = std::min(tp, 16);
     while (tp > 1 && (n / 2) % tp) tp /= 2;
     fs.tile_post = tp;
@@ -828,11 +846,12 @@ pkm_status pkm_plan_create(const pkm_params* p, const pkm_device* dev, pkm_plan*
     pl->ntiles = (n / pl->ts) * (n / pl->ts) * (n / pl->ts);
     pl->tile_count = (int*)dalloc(pl, sizeof(int) * (pl->ntiles + 1));
     pl->tile_off = (int*)dalloc(pl, sizeof(int) * (pl->ntiles + 1));
+    pl->scan_sums = (int*)dalloc(pl, sizeof(int) * tile_scan_scratch(pl->ntiles));
     int want = fields_for(pl->p.ell_max_hint);
     if (p->max_group > 0) want = std::min(want, p->max_group);
     ensure_fields(pl, std::max(want, 1));
-    pl->ftab_dev = (int*)dalloc(pl, sizeof(int) * 3 * 64);
-    pl->ftab_cap = 3 * 64;
+    pl->ftab_dev = (int*)dalloc(pl, sizeof(int) * 4 * 64);
+    pl->ftab_cap = 4 * 64;
     if (pl->fp64) upload_tables<double>(pl); else upload_tables<float>(pl);
   });
   if (st != PKM_OK) {
