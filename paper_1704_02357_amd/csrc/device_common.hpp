@@ -152,47 +152,160 @@ __device__ __forceinline__ void stockham_stage(cx<T>* lds, int off, int es, int 
   __syncthreads();
 }
 
-// Compile-time variant for power-of-two L: radices 8, then 4, then 2 (each dividing E), with
-// every index, span and twiddle step a constant.
-template <typename T, int E, int R, bool INV, int PAD, int L, int NTW, int M>
-__device__ __forceinline__ void stage_ct(cx<T>* lds, int off, int es, int t, const cx<T>* __restrict__ tw) {
-  constexpr int PT = L / E, NB = E / R, LR = L / R, STEP = NTW / (M * R);
-  cx<T> v[E];
-#pragma unroll
-  for (int q = 0; q < NB; ++q) {
-    const int b = t + q * PT;
-#pragma unroll
-    for (int s = 0; s < R; ++s) v[q * R + s] = lds[off + padi<PAD>(b + s * LR) * es];
+// ---------------------------------------------------------------------------------------
+// Compile-time Stockham FFT for power-of-two L with the line held in registers on entry and
+// exit.  Radices 8, then 4, then 2 (each dividing E); spans, strides and twiddle offsets are
+// constants.  Element e of the register array u is position t + PT*e of the line (PT = L/E
+// threads per line, this thread number t).  The first stage reads its inputs straight from
+// u and the last stage's outputs are exactly the positions t + PT*e again, so only the
+// exchanges between stages go through LDS (at lds[off + padi<PAD>(i)*es]).
+//
+// Twiddles come from a per-stage table (ct_twiddles): the stage of span M and radix R keeps
+// W_{MR}^{sk} at offset ct_tw_off(M) + k(R-1) + (s-1), so lanes with consecutive k read
+// consecutive entries instead of the strided, bank-conflicting reads of a W_N^j table.
+//
+// WAVE = true when every line lies inside one wavefront: the stage exchanges then need only
+// a wavefront-level ordering (LDS operations of one wave complete in issue order).
+// ---------------------------------------------------------------------------------------
+__host__ __device__ constexpr int ct_radix(int e, int rem) {
+  return (e % 8 == 0 && rem % 8 == 0) ? 8 : (e % 4 == 0 && rem % 4 == 0) ? 4 : 2;
+}
+// Offset of the twiddles of the stage with span mstage (all stages with span < mstage).
+__host__ __device__ constexpr int ct_tw_off(int e, int L, int mstage) {
+  int m = 1, sz = 0;
+  while (m < mstage && m < L) {
+    const int r = ct_radix(e, L / m);
+    if (m > 1) sz += m * (r - 1);
+    m *= r;
   }
-  __syncthreads();
+  return sz;
+}
+__host__ __device__ constexpr int ct_tw_total(int e, int L) { return ct_tw_off(e, L, L); }
+__host__ __device__ constexpr int ct_last_radix(int e, int L) {
+  int m = 1, r = 2;
+  while (m < L) {
+    r = ct_radix(e, L / m);
+    m *= r;
+  }
+  return r;
+}
+
+// Fill the per-stage table from tw[j] = exp(-2 pi i j / NTW) (NTW a multiple of L).
+template <typename T, int E, int L, int NTW>
+__device__ __forceinline__ void ct_twiddles(cx<T>* dst, const cx<T>* __restrict__ tw) {
+  constexpr int total = ct_tw_total(E, L);
+  for (int i = threadIdx.x; i < total; i += blockDim.x) {
+    int m = 1, off = 0;
+    for (;;) {
+      const int r = ct_radix(E, L / m);
+      if (m > 1) {
+        const int sz = m * (r - 1);
+        if (i < off + sz) {
+          const int j = i - off;
+          const int k = j / (r - 1), s = j % (r - 1) + 1;
+          dst[i] = tw[s * k * (NTW / (m * r))];
+          break;
+        }
+        off += sz;
+      }
+      m *= r;
+    }
+  }
+}
+
+// Ordering of LDS accesses between the threads that share a line.
+template <bool WAVE> __device__ __forceinline__ void ct_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Stage of span M: inputs v[q*R + s] = x[b + s*L/R], b = t + q*PT.
+template <typename T, int E, int PAD, int L, int M>
+__device__ __forceinline__ void ct_gather(const cx<T>* lds, int off, int es, int t, cx<T>* v) {
+  constexpr int R = ct_radix(E, L / M), PT = L / E, NB = E / R, LR = L / R;
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+#pragma unroll
+    for (int s = 0; s < R; ++s) v[q * R + s] = lds[off + padi<PAD>(t + q * PT + s * LR) * es];
+}
+template <typename T, int E, bool INV, int L, int M>
+__device__ __forceinline__ void ct_butterflies(int t, cx<T>* v, const cx<T>* twst) {
+  constexpr int R = ct_radix(E, L / M), PT = L / E, NB = E / R, OFF = ct_tw_off(E, L, M);
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    const int b = t + q * PT;
-    const int k = b & (M - 1);
-    const int base = (b - k) * R + k;
     if constexpr (M > 1) {
+      const int k = (t + q * PT) & (M - 1);
 #pragma unroll
       for (int s = 1; s < R; ++s) {
-        cx<T> w = tw[s * k * STEP];
+        cx<T> w = twst[OFF + k * (R - 1) + (s - 1)];
         if (INV) w.y = -w.y;
         v[q * R + s] = cmul<T>(v[q * R + s], w);
       }
     }
     dft_r<T, R, INV>(&v[q * R]);
+  }
+}
+// Outputs y_s of butterfly b go to (b/M) M R + (b mod M) + s M.
+template <typename T, int E, int PAD, int L, int M>
+__device__ __forceinline__ void ct_scatter(cx<T>* lds, int off, int es, int t, const cx<T>* v) {
+  constexpr int R = ct_radix(E, L / M), PT = L / E, NB = E / R;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int b = t + q * PT;
+    const int k = b & (M - 1);
+    const int base = (b - k) * R + k;
 #pragma unroll
     for (int s = 0; s < R; ++s) lds[off + padi<PAD>(base + s * M) * es] = v[q * R + s];
   }
-  __syncthreads();
+}
+template <typename T, int E, bool INV, int PAD, int L, bool WAVE, int M>
+__device__ __forceinline__ void ct_rest(cx<T>* lds, int off, int es, int t, cx<T>* v, const cx<T>* twst) {
+  ct_butterflies<T, E, INV, L, M>(t, v, twst);
+  constexpr int R = ct_radix(E, L / M);
+  if constexpr (M * R < L) {
+    ct_sync<WAVE>();
+    ct_scatter<T, E, PAD, L, M>(lds, off, es, t, v);
+    ct_sync<WAVE>();
+    ct_gather<T, E, PAD, L, M * R>(lds, off, es, t, v);
+    ct_rest<T, E, INV, PAD, L, WAVE, M * R>(lds, off, es, t, v, twst);
+  }
 }
 
-template <typename T, int E, bool INV, int PAD, int L, int NTW, int M = 1>
-__device__ __forceinline__ void lds_fft_ct(cx<T>* lds, int off, int es, int t, const cx<T>* __restrict__ tw) {
-  constexpr int REM = L / M;
-  if constexpr (REM > 1) {
-    constexpr int R = (E % 8 == 0 && REM % 8 == 0) ? 8 : (E % 4 == 0 && REM % 4 == 0) ? 4 : 2;
-    stage_ct<T, E, R, INV, PAD, L, NTW, M>(lds, off, es, t, tw);
-    lds_fft_ct<T, E, INV, PAD, L, NTW, M * R>(lds, off, es, t, tw);
-  }
+// Transform of u in place (registers).  The caller must have finished every read of the
+// line's LDS slots by the threads of the line (ct_sync<WAVE> or stronger) and the twiddle
+// table must be visible.  On return the LDS slots hold intermediate data.
+template <typename T, int E, bool INV, int PAD, int L, bool WAVE>
+__device__ __forceinline__ void ct_fft_regs(cx<T>* lds, int off, int es, int t, cx<T>* u, const cx<T>* twst) {
+  constexpr int R0 = ct_radix(E, L), NB0 = E / R0;
+  constexpr int RL = ct_last_radix(E, L), NBL = E / RL;
+  cx<T> v[E];
+#pragma unroll
+  for (int q = 0; q < NB0; ++q)
+#pragma unroll
+    for (int s = 0; s < R0; ++s) v[q * R0 + s] = u[q + s * NB0];
+  ct_rest<T, E, INV, PAD, L, WAVE, 1>(lds, off, es, t, v, twst);
+#pragma unroll
+  for (int q = 0; q < NBL; ++q)
+#pragma unroll
+    for (int s = 0; s < RL; ++s) u[q + s * NBL] = v[q * RL + s];
+}
+
+// Same with the input line already in LDS (filled and made visible by the caller).
+template <typename T, int E, bool INV, int PAD, int L, bool WAVE>
+__device__ __forceinline__ void ct_fft_lds_in(cx<T>* lds, int off, int es, int t, cx<T>* u, const cx<T>* twst) {
+  constexpr int RL = ct_last_radix(E, L), NBL = E / RL;
+  cx<T> v[E];
+  ct_gather<T, E, PAD, L, 1>(lds, off, es, t, v);
+  ct_rest<T, E, INV, PAD, L, WAVE, 1>(lds, off, es, t, v, twst);
+#pragma unroll
+  for (int q = 0; q < NBL; ++q)
+#pragma unroll
+    for (int s = 0; s < RL; ++s) u[q + s * NBL] = v[q * RL + s];
 }
 
 // Radix schedule packed 4 bits per stage (stage 0 in the low bits), nst stages.

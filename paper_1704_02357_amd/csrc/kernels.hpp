@@ -23,6 +23,9 @@ struct FftShape {
   int tile_post;    // columns per post-pass tile
 };
 
+// LDS bytes of a post-pass block without its histograms.
+size_t xpost_base_bytes(const FftShape& fs, bool fp64);
+
 struct BinSpec {
   const long long* thr;  // device, nb+1 integer thresholds on |n|^2
   int nb;

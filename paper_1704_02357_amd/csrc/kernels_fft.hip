@@ -11,9 +11,14 @@
 //              and forward z for every field of a group.
 //   column   : length-N transforms along y or x over tiles of `tile` adjacent kz columns.
 //   xcombine : forward x of both painted meshes + interlace combine + compensation +
-//              Nyquist zero + l = 0 binning, then inverse x of C.
+//              Nyquist zero, then inverse x of C.
 //   xpost    : forward x of every field of a group, sum_m Y_lm(khat) B_lm, product with
 //              C, and binning into per-block partial sums.
+//
+// Every kernel takes two extra template constants: NC (mesh side) and TC (tile width, or
+// lines per block for the z passes).  For power-of-two meshes the launchers instantiate them
+// with the plan's values, so all index arithmetic and the radix schedule fold to constants;
+// NC = TC = 0 selects the runtime-generic path used for the other sizes.
 #include "kernels.hpp"
 #include "device_common.hpp"
 
@@ -26,16 +31,9 @@ constexpr int ZPAD = 3;  // z-line LDS layout: one spare slot per 8 complex
 __host__ __device__ constexpr int zpitch(int nh) { return nh + (nh >> ZPAD) + 1; }
 constexpr int XPAD = 3;  // post-pass tile: one spare row per 8 rows
 __host__ __device__ constexpr int xrows(int n) { return n + (n >> XPAD) + 1; }
-
-template <typename T> __device__ __forceinline__ cx<T> ld(const void* p, size_t i) {
-  return reinterpret_cast<const cx<T>*>(p)[i];
-}
-template <typename T> __device__ __forceinline__ void st(void* p, size_t i, cx<T> v) {
-  typedef __attribute__((address_space(1))) T GT;
-  GT* q = (GT*)p;
-  q[2 * i] = v.x;
-  q[2 * i + 1] = v.y;
-}
+constexpr int ZMAX_THREADS = 256;
+constexpr int XMAX_THREADS = 512;
+constexpr int XPOST_THREADS = 256;
 
 // Global-memory accesses through address-space-1 pointers (buffer pointers read from a
 // device array would otherwise be generic and compile to flat instructions).
@@ -65,68 +63,83 @@ __device__ __forceinline__ cx<T>* stage_twiddles(cx<T>* dst, const cx<T>* __rest
   return dst;
 }
 
-// Tile of `tile` adjacent kz columns x n rows: element i = tid + j*bs (j < E) of the tile is
-// row i / tile, column i % tile.  All E loads are issued before any is consumed.
 __device__ __forceinline__ int tdiv(int i, int tile) { return (tile & (tile - 1)) == 0 ? i >> (__ffs(tile) - 1) : i / tile; }
 __device__ __forceinline__ int tmod(int i, int tile) { return (tile & (tile - 1)) == 0 ? i & (tile - 1) : i % tile; }
 
+// Tile of `tile` adjacent kz columns x n rows: element i = tid + j*bs (j < E) of the tile is
+// row i / tile, column i % tile.  All E loads are issued before any is consumed.  With
+// RPAD > 0 the LDS row index is padded (one spare row per 2^RPAD rows).
 template <typename T, int E>
-__device__ __forceinline__ void tile_load(cx<T>* v, const cx<T>* __restrict__ g, size_t base, size_t rs, int tile) {
-  const int bs = blockDim.x;
+__device__ __forceinline__ void tile_load(cx<T>* v, const cx<T>* __restrict__ g, size_t base, size_t rs, int tile,
+                                          int bs) {
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int i = threadIdx.x + j * bs;
     v[j] = gload<T>(g, base + (size_t)tdiv(i, tile) * rs + tmod(i, tile));
   }
 }
-template <typename T, int E>
-__device__ __forceinline__ void tile_to_lds(cx<T>* lds, const cx<T>* v, int tile, int pitch) {
-  const int bs = blockDim.x;
+template <typename T, int E, int RPAD>
+__device__ __forceinline__ void tile_to_lds(cx<T>* lds, const cx<T>* v, int tile, int pitch, int bs) {
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int i = threadIdx.x + j * bs;
-    lds[tdiv(i, tile) * pitch + tmod(i, tile)] = v[j];
-  }
-}
-template <typename T, int E>
-__device__ __forceinline__ void tile_to_lds_padded(cx<T>* lds, const cx<T>* v, int tile, int pitch) {
-  const int bs = blockDim.x;
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const int i = threadIdx.x + j * bs;
-    lds[padi<XPAD>(tdiv(i, tile)) * pitch + tmod(i, tile)] = v[j];
-  }
-}
-
-template <typename T, int E>
-__device__ __forceinline__ void tile_store(cx<T>* __restrict__ g, const cx<T>* lds, size_t base, size_t rs, int tile,
-                                           int pitch) {
-  const int bs = blockDim.x;
-  cx<T> v[E];
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const int i = threadIdx.x + j * bs;
-    v[j] = lds[tdiv(i, tile) * pitch + tmod(i, tile)];
-  }
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const int i = threadIdx.x + j * bs;
-    gstore<T>(g, base + (size_t)tdiv(i, tile) * rs + tmod(i, tile), v[j]);
+    lds[padi<RPAD>(tdiv(i, tile)) * pitch + tmod(i, tile)] = v[j];
   }
 }
 // G contiguous lines of nh complex: element i = tid + j*bs is line i / nh, entry i % nh.
 template <typename T, int E>
-__device__ __forceinline__ void lines_to_lds(cx<T>* lds, const cx<T>* __restrict__ src, int nh, int lp) {
-  const int bs = blockDim.x;
+__device__ __forceinline__ void lines_to_lds(cx<T>* lds, const cx<T>* __restrict__ src, int nh, int lp, int bs) {
   cx<T> v[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) v[j] = gload<T>(src, threadIdx.x + j * bs);
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int i = threadIdx.x + j * bs;
-    lds[(i / nh) * lp + padi<ZPAD>(i % nh)] = v[j];
+    lds[tdiv(i, nh) * lp + padi<ZPAD>(tmod(i, nh))] = v[j];
   }
 }
+
+// Runtime description of one line transform (generic path).
+struct LineRt {
+  int L;           // line length
+  uint32_t sched;  // radix schedule
+  int nst;
+  int pt;          // threads per line
+  int ntw;         // entries of the W_ntw^j table
+};
+
+// Line transform with the line in registers on entry and exit (element e = position
+// t + pt*e).  LC > 0: compile-time schedule (WAVE = the line lies inside one wavefront);
+// LC = 0: generic schedule through the LDS line, block-wide barriers.
+template <typename T, int E, bool INV, int PAD, int LC, bool WAVE>
+__device__ __forceinline__ void xf_regs(cx<T>* lds, int off, int es, const LineRt& rt, int t, cx<T>* u,
+                                        const cx<T>* twst, const cx<T>* __restrict__ twl) {
+  if constexpr (LC > 0) {
+    ct_fft_regs<T, E, INV, PAD, LC, WAVE>(lds, off, es, t, u, twst);
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[off + padi<PAD>(t + rt.pt * e) * es] = u[e];
+    __syncthreads();
+    lds_fft<T, E, INV, PAD>(lds, off, es, rt.L, rt.sched, rt.nst, t, rt.pt, twl, rt.ntw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) u[e] = lds[off + padi<PAD>(t + rt.pt * e) * es];
+  }
+}
+// Same with the input line already in LDS (filled, and a block barrier since).
+template <typename T, int E, bool INV, int PAD, int LC, bool WAVE>
+__device__ __forceinline__ void xf_lds_in(cx<T>* lds, int off, int es, const LineRt& rt, int t, cx<T>* u,
+                                          const cx<T>* twst, const cx<T>* __restrict__ twl) {
+  if constexpr (LC > 0) {
+    ct_fft_lds_in<T, E, INV, PAD, LC, WAVE>(lds, off, es, t, u, twst);
+  } else {
+    lds_fft<T, E, INV, PAD>(lds, off, es, rt.L, rt.sched, rt.nst, t, rt.pt, twl, rt.ntw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) u[e] = lds[off + padi<PAD>(t + rt.pt * e) * es];
+  }
+}
+// LDS entries of the per-stage twiddle table (compile-time path only).
+template <int E, int LC> __host__ __device__ constexpr int twst_size() { return LC > 0 ? ct_tw_total(E, LC) : 0; }
 
 // Forward split of a packed half-length transform: X_k = E_k + W_N^k O_k.
 template <typename T>
@@ -157,68 +170,6 @@ __device__ __forceinline__ cx<T> c2r_split(const cx<T>* line, int k, int nh, con
   return mk<T>(e.x - o.y, e.y + o.x);  // e + i o
 }
 
-// ------------------------------------------------------------------------------------------
-// z pass, forward (real -> half complex)
-// ------------------------------------------------------------------------------------------
-constexpr int ZMAX_THREADS = 256;
-constexpr int XMAX_THREADS = 512;
-
-template <typename T, int E>
-__global__ void __launch_bounds__(ZMAX_THREADS) k_zfwd(int n, int G, uint32_t sched, int nst, const T* __restrict__ in0, const T* __restrict__ in1,
-                       void* __restrict__ out0, void* __restrict__ out1, const cx<T>* __restrict__ tw) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
-  const int nh = n >> 1;
-  const int lp = zpitch(nh);
-  const int pt = nh / E;
-  const T* in = blockIdx.y ? in1 : in0;
-  void* out = blockIdx.y ? out1 : out0;
-  const size_t line0 = (size_t)blockIdx.x * G;
-  const int tid = threadIdx.x;
-  cx<T>* twl = stage_twiddles<T>(lds + (size_t)G * lp, tw, n);
-  lines_to_lds<T, E>(lds, reinterpret_cast<const cx<T>*>(in) + line0 * nh, nh, lp);
-  __syncthreads();
-  const int t = tid % pt, g = tid / pt;
-  cx<T>* line = lds + g * lp;
-  lds_fft<T, E, false, ZPAD>(lds, g * lp, 1, nh, sched, nst, t, pt, twl, n);
-  const size_t ob = (line0 + g) * nh;
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int k = t + pt * e;
-    st<T>(out, ob + k, r2c_split<T>(line, k, nh, twl));
-  }
-}
-
-// ------------------------------------------------------------------------------------------
-// column pass (length N along y or x), in place
-// ------------------------------------------------------------------------------------------
-template <typename T, int E, bool INV>
-__global__ void __launch_bounds__(XMAX_THREADS) k_col(int n, int tile, uint32_t sched, int nst, void* const* __restrict__ bufs, size_t row_stride,
-                      size_t outer_stride, const cx<T>* __restrict__ tw) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
-  const int nh = n >> 1;
-  const int tiles = nh / tile;
-  const int blk = xcd_tile(blockIdx.x, gridDim.x);
-  const int outer = blk / tiles;
-  const int kz0 = (blk % tiles) * tile;
-  cx<T>* buf = reinterpret_cast<cx<T>*>(bufs[blockIdx.y]);
-  const size_t base = (size_t)outer * outer_stride + kz0;
-  const int pitch = tile + 1;
-  const int tid = threadIdx.x;
-  cx<T>* twl = stage_twiddles<T>(lds + (size_t)n * pitch, tw, n);
-  {
-    cx<T> v[E];
-    tile_load<T, E>(v, buf, base, row_stride, tile);
-    tile_to_lds<T, E>(lds, v, tile, pitch);
-  }
-  __syncthreads();
-  const int pt = n / E;
-  const int c = tid % tile, t = tid / tile;
-  lds_fft<T, E, INV>(lds, c, pitch, n, sched, nst, t, pt, twl, n);
-  tile_store<T, E>(buf, lds, base, row_stride, tile, pitch);
-}
-
 __device__ __forceinline__ int sfreq(int j, int n) { return j < (n >> 1) ? j : j - n; }
 
 // Histogram in LDS: `copies` copies of nvals doubles; wave w uses copy w % copies.
@@ -234,16 +185,107 @@ __device__ __forceinline__ void hist_flush(const double* h, int copies, int nval
 }
 
 // ------------------------------------------------------------------------------------------
-// x pass of the painted meshes + combine + l=0 bin + inverse x of C
+// z pass, forward (real -> half complex)
 // ------------------------------------------------------------------------------------------
-template <typename T, int E>
-__global__ void __launch_bounds__(XMAX_THREADS) k_xcombine(int n, int tile, uint32_t sched, int nst, const cx<T>* __restrict__ s1,
-                           const cx<T>* __restrict__ s2, cx<T>* __restrict__ cout, cx<T>* __restrict__ gout,
-                           int interlaced, int compensated, const T* __restrict__ invw,
-                           const cx<T>* __restrict__ phase, const cx<T>* __restrict__ tw) {
+// LDS of the z passes: G padded lines, the W_N^j table (N entries; the splits read the
+// first N/2), and on the compile-time path the per-stage table of the length-N/2 transform.
+template <typename T, int E, int NC, int TC>
+__global__ void __launch_bounds__(ZMAX_THREADS) k_zfwd(int n_rt, int g_rt, uint32_t sched, int nst,
+                                                        const T* __restrict__ in0, const T* __restrict__ in1,
+                                                        void* __restrict__ out0, void* __restrict__ out1,
+                                                        const cx<T>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+  const int n = NC > 0 ? NC : n_rt;
+  const int G = TC > 0 ? TC : g_rt;
+  const int nh = n >> 1;
+  const int lp = zpitch(nh);
+  const int pt = nh / E;
+  const int bs = pt * G;
+  constexpr bool WAVE = NC > 0 && NC / 2 / E <= 64;
+  const T* in = blockIdx.y ? in1 : in0;
+  void* out = blockIdx.y ? out1 : out0;
+  const size_t line0 = (size_t)blockIdx.x * G;
+  const int tid = threadIdx.x;
+  cx<T>* twl = stage_twiddles<T>(lds + (size_t)G * lp, tw, n);
+  cx<T>* twst = twl + n;
+  if constexpr (NC > 0) ct_twiddles<T, E, NC / 2, NC>(twst, tw);
+  lines_to_lds<T, E>(lds, reinterpret_cast<const cx<T>*>(in) + line0 * nh, nh, lp, bs);
+  __syncthreads();
+  const int t = tid % pt, g = tid / pt;
+  cx<T>* line = lds + g * lp;
+  if constexpr (NC > 0) {
+    cx<T> u[E];
+    ct_fft_lds_in<T, E, false, ZPAD, NC / 2, WAVE>(lds, g * lp, 1, t, u, twst);
+#pragma unroll
+    for (int e = 0; e < E; ++e) line[padi<ZPAD>(t + pt * e)] = u[e];
+    ct_sync<WAVE>();
+  } else {
+    lds_fft<T, E, false, ZPAD>(lds, g * lp, 1, nh, sched, nst, t, pt, twl, n);
+  }
+  const size_t ob = (line0 + g) * nh;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = t + pt * e;
+    gstore<T>((cx<T>*)out, ob + k, r2c_split<T>(line, k, nh, twl));
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// column pass (length N along y or x), in place.  Lane c = tid % tile, t = tid / tile: the
+// tile load leaves rows t + pt*e of column c in the thread's registers, which is the
+// transform's own register layout, so LDS is used only between radix stages.
+// ------------------------------------------------------------------------------------------
+template <typename T, int E, bool INV, int NC, int TC>
+__global__ void __launch_bounds__(XMAX_THREADS) k_col(int n_rt, int tile_rt, uint32_t sched, int nst,
+                                                       void* const* __restrict__ bufs, size_t row_stride,
+                                                       size_t outer_stride, const cx<T>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+  const int n = NC > 0 ? NC : n_rt;
+  const int tile = TC > 0 ? TC : tile_rt;
+  const int nh = n >> 1;
+  const int pt = n / E;
+  const int bs = pt * tile;
+  const int tiles = nh / tile;
+  const int blk = xcd_tile(blockIdx.x, gridDim.x);
+  const int outer = blk / tiles;
+  const int kz0 = (blk % tiles) * tile;
+  cx<T>* buf = reinterpret_cast<cx<T>*>(bufs[blockIdx.y]);
+  const size_t base = (size_t)outer * outer_stride + kz0;
+  const int pitch = tile + 1;
+  const int tid = threadIdx.x;
+  const int c = tid % tile, t = tid / tile;
+  cx<T> u[E];
+  tile_load<T, E>(u, buf, base, row_stride, tile, bs);
+  // generic path: the W_N^j table; compile-time path: the per-stage table only
+  cx<T>* twl = lds + (size_t)n * pitch;
+  cx<T>* twst = twl;
+  if constexpr (NC > 0) ct_twiddles<T, E, NC, NC>(twst, tw); else stage_twiddles<T>(twl, tw, n);
+  const LineRt rt{n, sched, nst, pt, n};
+  xf_regs<T, E, INV, 0, NC, false>(lds, c, pitch, rt, t, u, twst, twl);
+#pragma unroll
+  for (int e = 0; e < E; ++e) gstore<T>(buf, base + (size_t)(t + pt * e) * row_stride + c, u[e]);
+}
+
+// ------------------------------------------------------------------------------------------
+// x pass of the painted meshes + combine + inverse x of C (same lane layout as k_col)
+// ------------------------------------------------------------------------------------------
+template <typename T, int E, int NC, int TC>
+__global__ void __launch_bounds__(XMAX_THREADS) k_xcombine(int n_rt, int tile_rt, uint32_t sched, int nst,
+                                                            const cx<T>* __restrict__ s1, const cx<T>* __restrict__ s2,
+                                                            cx<T>* __restrict__ cout, cx<T>* __restrict__ gout,
+                                                            int interlaced, int compensated,
+                                                            const T* __restrict__ invw,
+                                                            const cx<T>* __restrict__ phase,
+                                                            const cx<T>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = NC > 0 ? NC : n_rt;
+  const int tile = TC > 0 ? TC : tile_rt;
   const int nh = n >> 1;
   const int pitch = tile + 1;
+  const int pt = n / E;
+  const int bs = pt * tile;
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
   const int tiles = nh / tile;
   const int blk = xcd_tile(blockIdx.x, gridDim.x);
@@ -252,32 +294,25 @@ __global__ void __launch_bounds__(XMAX_THREADS) k_xcombine(int n, int tile, uint
   const size_t rs = (size_t)n * nh;
   const size_t base = (size_t)y * nh + kz0;
   const int tid = threadIdx.x;
-  const int pt = n / E;
   const int c = tid % tile, t = tid / tile;
   const int kz = kz0 + c;
   cx<T> a1[E];
-  cx<T> v2[E];
-  cx<T>* twl = stage_twiddles<T>(lds + (size_t)n * pitch, tw, n);
-  {
-    cx<T> v[E];
-    tile_load<T, E>(v, s1, base, rs, tile);
-    if (interlaced) tile_load<T, E>(v2, s2, base, rs, tile);
-    tile_to_lds<T, E>(lds, v, tile, pitch);
-  }
-  __syncthreads();
-  lds_fft<T, E, false>(lds, c, pitch, n, sched, nst, t, pt, twl, n);
-#pragma unroll
-  for (int e = 0; e < E; ++e) a1[e] = lds[(t + pt * e) * pitch + c];
+  cx<T> a2[E];
+  tile_load<T, E>(a1, s1, base, rs, tile, bs);
+  if (interlaced) tile_load<T, E>(a2, s2, base, rs, tile, bs);
+  // generic path: the W_N^j table; compile-time path: the per-stage table only
+  cx<T>* twl = lds + (size_t)n * pitch;
+  cx<T>* twst = twl;
+  if constexpr (NC > 0) ct_twiddles<T, E, NC, NC>(twst, tw); else stage_twiddles<T>(twl, tw, n);
+  const LineRt rt{n, sched, nst, pt, n};
+  xf_regs<T, E, false, 0, NC, false>(lds, c, pitch, rt, t, a1, twst, twl);
   if (interlaced) {
-    __syncthreads();
-    tile_to_lds<T, E>(lds, v2, tile, pitch);
-    __syncthreads();
-    lds_fft<T, E, false>(lds, c, pitch, n, sched, nst, t, pt, twl, n);
+    xf_regs<T, E, false, 0, NC, false>(lds, c, pitch, rt, t, a2, twst, twl);
     const cx<T> pyz = cmul<T>(phase[y], phase[kz]);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int x = t + pt * e;
-      const cx<T> b = cmul<T>(lds[x * pitch + c], cmul<T>(phase[x], pyz));
+      const cx<T> b = cmul<T>(a2[e], cmul<T>(phase[x], pyz));
       a1[e] = mk<T>(T(0.5) * (a1[e].x + b.x), T(0.5) * (a1[e].y + b.y));
     }
   }
@@ -292,146 +327,153 @@ __global__ void __launch_bounds__(XMAX_THREADS) k_xcombine(int n, int tile, uint
     gstore<T>(cout, base + c + (size_t)x * rs, v);
   }
   if (gout == nullptr) return;
-  __syncthreads();
+  xf_regs<T, E, true, 0, NC, false>(lds, c, pitch, rt, t, a1, twst, twl);
 #pragma unroll
-  for (int e = 0; e < E; ++e) lds[(t + pt * e) * pitch + c] = a1[e];
-  __syncthreads();
-  lds_fft<T, E, true>(lds, c, pitch, n, sched, nst, t, pt, twl, n);
-  tile_store<T, E>(gout, lds, base, rs, tile, pitch);
+  for (int e = 0; e < E; ++e) gstore<T>(gout, base + (size_t)(t + pt * e) * rs + c, a1[e]);
 }
 
 // ------------------------------------------------------------------------------------------
-// z pre-pass: D_c from G (inverse z), then weighted forward z for every field of the group
+// z pre-pass: D_c from G (inverse z), then weighted forward z for every field of the group.
+// Fields come |m|-major (the table order) so the harmonic recurrence continues across them.
+// Each line is handled by the threads of one wavefront (compile-time path), so the field
+// loop needs no block barrier.
 // ------------------------------------------------------------------------------------------
-template <typename T, int E>
-__global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n, int G, uint32_t sched, int nst, const cx<T>* __restrict__ gin,
-                       const T* __restrict__ real_in, T* __restrict__ real_out, void* const* __restrict__ bufs,
-                       int nf, const int* __restrict__ fields, T scale, double off0, double off1, double off2,
-                       double h, const T* __restrict__ ytab, const cx<T>* __restrict__ tw) {
+template <typename T, int E, int NC, int TC>
+__global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n_rt, int g_rt, uint32_t sched, int nst,
+                                                        const cx<T>* __restrict__ gin, const T* __restrict__ real_in,
+                                                        T* __restrict__ real_out, void* const* __restrict__ bufs,
+                                                        int nf, const int* __restrict__ fields, T scale, double off0,
+                                                        double off1, double off2, double h,
+                                                        const T* __restrict__ ytab, const cx<T>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+  const int n = NC > 0 ? NC : n_rt;
+  const int G = TC > 0 ? TC : g_rt;
   const int nh = n >> 1;
   const int lp = zpitch(nh);
   const int pt = nh / E;
+  const int bs = pt * G;
+  constexpr bool WAVE = NC > 0 && NC / 2 / E <= 64;
   const size_t line0 = (size_t)blockIdx.x * G;
   const int tid = threadIdx.x;
   const int t = tid % pt, g = tid / pt;
   const size_t lineg = line0 + g;
   cx<T>* line = lds + g * lp;
   cx<T>* twl = stage_twiddles<T>(lds + (size_t)G * lp, tw, n);
+  cx<T>* twst = twl + n;
+  if constexpr (NC > 0) ct_twiddles<T, E, NC / 2, NC>(twst, tw);
+  const LineRt rt{nh, sched, nst, pt, n};
   T r[2 * E];
   if (real_in) {
     const cx<T>* src = reinterpret_cast<const cx<T>*>(real_in) + lineg * nh;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const cx<T> v = src[t + pt * e];
+      const cx<T> v = gload<T>(src, t + pt * e);
       r[2 * e] = v.x;
       r[2 * e + 1] = v.y;
     }
+    __syncthreads();
   } else {
-    lines_to_lds<T, E>(lds, gin + line0 * nh, nh, lp);
+    lines_to_lds<T, E>(lds, gin + line0 * nh, nh, lp, bs);
     __syncthreads();
     cx<T> z[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) z[e] = c2r_split<T>(line, t + pt * e, nh, twl);
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < E; ++e) line[padi<ZPAD>(t + pt * e)] = z[e];
-    __syncthreads();
-    lds_fft<T, E, true, ZPAD>(lds, g * lp, 1, nh, sched, nst, t, pt, twl, n);
+    xf_regs<T, E, true, ZPAD, NC / 2, WAVE>(lds, g * lp, 1, rt, t, z, twst, twl);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const cx<T> v = line[padi<ZPAD>(t + pt * e)];
-      r[2 * e] = v.x * scale;
-      r[2 * e + 1] = v.y * scale;
+      r[2 * e] = z[e].x * scale;
+      r[2 * e + 1] = z[e].y * scale;
     }
     if (real_out) {
       cx<T>* dst = reinterpret_cast<cx<T>*>(real_out) + lineg * nh;
 #pragma unroll
-      for (int e = 0; e < E; ++e) dst[t + pt * e] = mk<T>(r[2 * e], r[2 * e + 1]);
+      for (int e = 0; e < E; ++e) gstore<T>(dst, t + pt * e, mk<T>(r[2 * e], r[2 * e + 1]));
     }
-    __syncthreads();
   }
   if (nf == 0) return;
-  // distance from the observer to this thread's nodes (x, y fixed by the line)
+  // unit vectors from the observer to this thread's nodes (x, y fixed by the line)
   const int ix = (int)(lineg / n), iy = (int)(lineg % n);
   const T px = (T)(off0 + ix * h), py = (T)(off1 + iy * h);
   const T pxy2 = px * px + py * py;
-  T inv[2 * E];
-#pragma unroll
-  for (int q = 0; q < 2 * E; ++q) {
-    const int iz = 2 * (t + pt * (q >> 1)) + (q & 1);
-    const T pz = (T)(off2 + iz * h);
-    const T rr = sqrt(pxy2 + pz * pz);
-    inv[q] = rr > T(0) ? T(1) / rr : T(0);
-  }
   T ux[2 * E], uy[2 * E], uz[2 * E];
+  bool zero[2 * E];
 #pragma unroll
   for (int q = 0; q < 2 * E; ++q) {
     const T pz = (T)(off2 + (2 * (t + pt * (q >> 1)) + (q & 1)) * h);
-    ux[q] = px * inv[q];
-    uy[q] = py * inv[q];
-    uz[q] = pz * inv[q];
+    const T rr = sqrt(pxy2 + pz * pz);
+    zero[q] = !(rr > T(0));
+    const T inv = zero[q] ? T(0) : T(1) / rr;
+    ux[q] = px * inv;
+    uy[q] = py * inv;
+    uz[q] = pz * inv;
   }
   YRun<T, 2 * E> yr;
   yrun_init(yr);
   for (int f = 0; f < nf; ++f) {
     T yv[2 * E];
     yrun_eval<T, 2 * E>(yr, fields[4 * f + 1], fields[4 * f + 2], ux, uy, uz, yv, ytab);
+    cx<T> u[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const T y0 = inv[2 * e] > T(0) ? yv[2 * e] : T(0);
-      const T y1 = inv[2 * e + 1] > T(0) ? yv[2 * e + 1] : T(0);
-      line[padi<ZPAD>(t + pt * e)] = mk<T>(r[2 * e] * y0, r[2 * e + 1] * y1);
+      const T y0 = zero[2 * e] ? T(0) : yv[2 * e];
+      const T y1 = zero[2 * e + 1] ? T(0) : yv[2 * e + 1];
+      u[e] = mk<T>(r[2 * e] * y0, r[2 * e + 1] * y1);
     }
-    __syncthreads();
-    lds_fft<T, E, false, ZPAD>(lds, g * lp, 1, nh, sched, nst, t, pt, twl, n);
-    void* out = bufs[fields[4 * f]];
+    xf_regs<T, E, false, ZPAD, NC / 2, WAVE>(lds, g * lp, 1, rt, t, u, twst, twl);
+    // the split needs X_k and X_{nh-k}: park the line in LDS (own slots), then read
+#pragma unroll
+    for (int e = 0; e < E; ++e) line[padi<ZPAD>(t + pt * e)] = u[e];
+    if constexpr (NC > 0) ct_sync<WAVE>(); else __syncthreads();
+    cx<T>* out = reinterpret_cast<cx<T>*>(bufs[fields[4 * f]]);
     const size_t ob = lineg * nh;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int k = t + pt * e;
-      st<T>(out, ob + k, r2c_split<T>(line, k, nh, twl));
+      gstore<T>(out, ob + k, r2c_split<T>(line, k, nh, twl));
     }
-    __syncthreads();
   }
 }
 
 // ------------------------------------------------------------------------------------------
-// x post-pass: forward x of each field, sum_m Y_lm(khat) B, product with C, binning
+// x post-pass: forward x of each field, sum_m Y_lm(khat) B, product with C, binning.
+// Fields come l-major (slots contiguous).  One complex accumulator per element holds
+// sum_m Y_lm(khat) B_lm of the current slot; at the last field of a slot it is folded
+// against C (held in registers for the whole block) into the FP64 bin histogram.  Two tile
+// buffers alternate between fields, so one block barrier per field suffices; the transform
+// itself runs within one wavefront per column on the compile-time path.
 // ------------------------------------------------------------------------------------------
-// Fields arrive ordered by slot (one slot per multipole l of the group).  One complex
-// accumulator per element holds sum_m Y_lm(khat) B_lm of the current slot.  After each
-// field's transform the thread scales its own LDS entries by Y_lm (a rolled loop, to keep
-// register pressure low) and adds them to the accumulator; at the last field of a slot the
-// accumulator is parked in the thread's own LDS entries and folded against C into the FP64
-// bin histogram.
-template <typename T>
-__device__ __forceinline__ void bin_fold(const cx<T>* a_lds, const cx<T>* __restrict__ cin, size_t gidx, int n2,
-                                         const long long* __restrict__ thr, int nb, double omega, double* h) {
-  const int bin = kbin_of(n2, thr, nb);
-  if (bin < 0) return;
-  const cx<T> a = *a_lds;
-  const cx<T> cv = gload<T>(cin, gidx);
-  lds_atomic_add<double>(&h[bin], omega * FOUR_PI * ((double)cv.x * (double)a.x + (double)cv.y * (double)a.y));
+template <typename T, int E, int NC>
+__host__ __device__ constexpr size_t xpost_elems(int n, int tile) {
+  return 2 * (size_t)xrows(n) * (tile + 1) + (NC > 0 ? twst_size<E, NC>() : n);
 }
 
-constexpr int XPOST_THREADS = 256;
-
-template <typename T, int E>
-__global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n, int tile, uint32_t sched, int nst, void* const* __restrict__ bufs, int nf,
-                        const int* __restrict__ fields, int nslots, int with_l0, double kf,
-                        const cx<T>* __restrict__ cin, const T* __restrict__ ytab,
-                        const long long* __restrict__ thr, int nb, int copies, double* __restrict__ partial,
-                        const cx<T>* __restrict__ tw) {
+template <typename T, int E, int NC, int TC>
+__global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, uint32_t sched, int nst,
+                                                          void* const* __restrict__ bufs, int nf,
+                                                          const int* __restrict__ fields, int nslots, int with_l0,
+                                                          double kf, const cx<T>* __restrict__ cin,
+                                                          const T* __restrict__ ytab,
+                                                          const long long* __restrict__ thr, int nb, int copies,
+                                                          double* __restrict__ partial,
+                                                          const cx<T>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem[];
+  const int n = NC > 0 ? NC : n_rt;
+  const int tile = TC > 0 ? TC : tile_rt;
   const int nh = n >> 1;
   const int pitch = tile + 1;
+  const int pt = n / E;
+  const int bs = pt * tile;
+  constexpr bool WAVE = NC > 0 && NC / E <= 64;
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
-  double* hist = reinterpret_cast<double*>(smem + sizeof(cx<T>) * ((size_t)xrows(n) * pitch + n));
+  const size_t tsz = (size_t)xrows(n) * pitch;
+  cx<T>* twl = lds + 2 * tsz;
+  cx<T>* twst = twl;
+  double* hist = reinterpret_cast<double*>(smem + sizeof(cx<T>) * xpost_elems<T, E, NC>(n, tile));
   const int l0rows = with_l0 ? 3 : 0;
   const int nvals = (l0rows + nslots) * nb;
   hist_zero(hist, copies * nvals);
+  if constexpr (NC > 0) ct_twiddles<T, E, NC, NC>(twst, tw); else stage_twiddles<T>(twl, tw, n);
   const int tiles = nh / tile;
   const int blk = xcd_tile(blockIdx.x, gridDim.x);
   const int y = blk / tiles;
@@ -439,84 +481,76 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n, int tile, uint32
   const size_t rs = (size_t)n * nh;
   const size_t base = (size_t)y * nh + kz0;
   const int tid = threadIdx.x;
-  const int pt = n / E;
-  // rows fastest across the lanes of a wave (with the padded rows this keeps the Stockham
-  // stages close to bank-conflict free)
+  // rows fastest across the lanes of a wave: a column's transform stays inside one wave
   const int t = tid % pt, c = tid / pt;
   const int kz = kz0 + c;
   const int fy = sfreq(y, n);
   const bool ynyq = (y == nh);
-  const double omega = (kz == 0) ? 1.0 : 2.0;
+  const double w4pi = ((kz == 0) ? 1.0 : 2.0) * FOUR_PI;
   double* h = hist + ((tid >> 6) % copies) * nvals;
-  cx<T>* twl = stage_twiddles<T>(lds + (size_t)xrows(n) * pitch, tw, n);
-  cx<T> acc[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) acc[e] = mk<T>(T(0), T(0));
-  // unit wave vectors of this thread's modes
+  const LineRt rt{n, sched, nst, pt, n};
+  __syncthreads();  // histogram zeroed, twiddles staged
+  cx<T> nxt[E];
+  if (nf > 0) tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[0]]), base, rs, tile, bs);
+  // per element: k bin (-1 when the mode is excluded), C, unit wave vector
+  int bin[E];
+  cx<T> cv[E];
   T ux[E], uy[E], uz[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const T fx = (T)sfreq(t + pt * e, n);
-    const T n2 = fx * fx + (T)fy * (T)fy + (T)kz * (T)kz;
-    const T ki = n2 > T(0) ? T(1) / sqrt(n2) : T(0);
-    ux[e] = fx * ki;
+    const int x = t + pt * e;
+    const int fx = sfreq(x, n);
+    const int n2 = fx * fx + fy * fy + kz * kz;
+    bin[e] = (ynyq || x == nh || n2 == 0) ? -1 : kbin_of(n2, thr, nb);
+    cv[e] = gload<T>(cin, base + c + (size_t)x * rs);
+    const T ki = n2 > 0 ? T(1) / sqrt((T)n2) : T(0);
+    ux[e] = (T)fx * ki;
     uy[e] = (T)fy * ki;
     uz[e] = (T)kz * ki;
   }
+  cx<T> acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = mk<T>(T(0), T(0));
   YRun<T, E> yr;
   yrun_init(yr);
-  cx<T> nxt[E];
-  if (nf > 0) tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[0]]), base, rs, tile);
-  __syncthreads();
   for (int f = 0; f < nf; ++f) {
-    tile_to_lds_padded<T, E>(lds, nxt, tile, pitch);
+    cx<T>* tb = lds + (f & 1) * tsz;
+    tile_to_lds<T, E, XPAD>(tb, nxt, tile, pitch, bs);
     // prefetch the next field's tile while this one is transformed
-    if (f + 1 < nf) tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[4 * (f + 1)]]), base, rs, tile);
+    if (f + 1 < nf)
+      tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[4 * (f + 1)]]), base, rs, tile, bs);
     __syncthreads();
-    lds_fft<T, E, false, XPAD>(lds, c, pitch, n, sched, nst, t, pt, twl, n);
+    cx<T> u[E];
+    xf_lds_in<T, E, false, XPAD, NC, WAVE>(tb, c, pitch, rt, t, u, twst, twl);
     const int slot = fields[4 * f + 3];
     {
       T yv[E];
       yrun_eval<T, E>(yr, fields[4 * f + 1], fields[4 * f + 2], ux, uy, uz, yv, ytab);
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const cx<T> b = lds[padi<XPAD>(t + pt * e) * pitch + c];
-        acc[e] = mk<T>(acc[e].x + yv[e] * b.x, acc[e].y + yv[e] * b.y);
-      }
+      for (int e = 0; e < E; ++e) acc[e] = mk<T>(acc[e].x + yv[e] * u[e].x, acc[e].y + yv[e] * u[e].y);
     }
     if (f + 1 == nf || fields[4 * (f + 1) + 3] != slot) {
+      double* hs = h + (l0rows + slot) * nb;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        lds[padi<XPAD>(t + pt * e) * pitch + c] = acc[e];
+        if (bin[e] >= 0)
+          lds_atomic_add<double>(&hs[bin[e]], w4pi * ((double)cv[e].x * (double)acc[e].x +
+                                                      (double)cv[e].y * (double)acc[e].y));
         acc[e] = mk<T>(T(0), T(0));
       }
-      if (!ynyq) {
-        double* hs = h + (l0rows + slot) * nb;
-#pragma unroll 1
-        for (int e = 0; e < E; ++e) {
-          const int x = t + pt * e;
-          const int fx = sfreq(x, n);
-          const int n2 = fx * fx + fy * fy + kz * kz;
-          if (x == nh || n2 == 0) continue;
-          bin_fold<T>(&lds[padi<XPAD>(x) * pitch + c], cin, base + c + (size_t)x * rs, n2, thr, nb, omega, hs);
-        }
-      }
     }
-    __syncthreads();
   }
-  if (with_l0 && !ynyq) {
-#pragma unroll 1
+  if (with_l0) {
+    const double w = (kz == 0) ? 1.0 : 2.0;
+#pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int x = t + pt * e;
-      const int fx = sfreq(x, n);
+      if (bin[e] < 0) continue;
+      const int fx = sfreq(t + pt * e, n);
       const int n2 = fx * fx + fy * fy + kz * kz;
-      if (x == nh || n2 == 0) continue;
-      const int bin = kbin_of(n2, thr, nb);
-      if (bin < 0) continue;
-      const cx<T> cv = gload<T>(cin, base + c + (size_t)x * rs);
-      lds_atomic_add<double>(&h[bin], omega);
-      lds_atomic_add<double>(&h[nb + bin], omega * kf * sqrt((double)n2));
-      lds_atomic_add<double>(&h[2 * nb + bin], omega * ((double)cv.x * (double)cv.x + (double)cv.y * (double)cv.y));
+      lds_atomic_add<double>(&h[bin[e]], w);
+      lds_atomic_add<double>(&h[nb + bin[e]], w * kf * sqrt((double)n2));
+      lds_atomic_add<double>(&h[2 * nb + bin[e]],
+                             w * ((double)cv[e].x * (double)cv[e].x + (double)cv[e].y * (double)cv[e].y));
     }
   }
   __syncthreads();
@@ -536,8 +570,8 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce(const double* __restrict
   for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) a += partial[(size_t)b * nvals + v];
   s[threadIdx.x] = a;
   __syncthreads();
-  for (int h = RED_THREADS / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+  for (int hh = RED_THREADS / 2; hh > 0; hh >>= 1) {
+    if ((int)threadIdx.x < hh) s[threadIdx.x] += s[threadIdx.x + hh];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -601,21 +635,64 @@ __global__ void k_kmu(int n, const cx<T>* __restrict__ cin, double l0, double l1
 // launchers
 // ------------------------------------------------------------------------------------------
 static int zthreads(const FftShape& fs) { return (fs.n / 2 / fs.e_z) * fs.zlines; }
-static size_t zsmem(const FftShape& fs, size_t cs) { return cs * ((size_t)fs.zlines * zpitch(fs.n / 2) + fs.n); }
+// LDS sizes.  Twiddles: the generic path stages the W_N^j table (N entries); the per-stage
+// table of the compile-time path has fewer than L entries for a length-L transform.
+static size_t zsmem(const FftShape& fs, size_t cs) {
+  return cs * ((size_t)fs.zlines * zpitch(fs.n / 2) + fs.n + fs.n / 2);
+}
 int xpass_threads(const FftShape& fs) { return (fs.n / fs.e_col) * fs.tile; }
 int xpass_blocks(const FftShape& fs) { return fs.n * ((fs.n / 2) / fs.tile); }
 int post_blocks(const FftShape& fs) { return fs.n * ((fs.n / 2) / fs.tile_post); }
-static size_t colsmem(const FftShape& fs, size_t cs) { return cs * (size_t)fs.n * (fs.tile + 2); }
+static size_t colsmem(const FftShape& fs, size_t cs) { return cs * ((size_t)fs.n * (fs.tile + 1) + fs.n); }
+size_t xpost_base_bytes(const FftShape& fs, bool fp64) {
+  const size_t cs = fp64 ? sizeof(double2) : sizeof(float2);
+  return cs * (2 * (size_t)xrows(fs.n) * (fs.tile_post + 1) + fs.n);
+}
 
-#define PKM_DISPATCH_E(EVAL, CALL)            \
-  switch (EVAL) {                             \
+#define PKM_DISPATCH_E(EVAL, CALL)                  \
+  switch (EVAL) {                                   \
     case 4: { constexpr int E = 4; CALL; break; }   \
     case 6: { constexpr int E = 6; CALL; break; }   \
     case 8: { constexpr int E = 8; CALL; break; }   \
     case 12: { constexpr int E = 12; CALL; break; } \
     case 16: { constexpr int E = 16; CALL; break; } \
-    default: return hipErrorInvalidValue;     \
+    default: return hipErrorInvalidValue;           \
   }
+
+// Compile-time instantiations for power-of-two meshes: (N, E, TC) triples matching the
+// plan's shape rules for FP32 and FP64; anything else runs the generic kernels.
+#define PKM_TRY(NV, EV, TV, EARG, TARG, CALL)      \
+  if (fs.n == NV && (EARG) == EV && (TARG) == TV) { \
+    constexpr int NC = NV, E = EV, TC = TV;         \
+    CALL;                                           \
+    return hipGetLastError();                       \
+  }
+
+#define PKM_TRY_Z(CALL)                        \
+  PKM_TRY(64, 8, 64, fs.e_z, fs.zlines, CALL)  \
+  PKM_TRY(128, 8, 32, fs.e_z, fs.zlines, CALL) \
+  PKM_TRY(256, 8, 16, fs.e_z, fs.zlines, CALL) \
+  PKM_TRY(512, 8, 8, fs.e_z, fs.zlines, CALL)  \
+  PKM_TRY(1024, 8, 4, fs.e_z, fs.zlines, CALL)
+
+#define PKM_TRY_COL(CALL)                         \
+  PKM_TRY(64, 8, 16, fs.e_col, fs.tile, CALL)     \
+  PKM_TRY(128, 8, 16, fs.e_col, fs.tile, CALL)    \
+  PKM_TRY(256, 16, 16, fs.e_col, fs.tile, CALL)   \
+  PKM_TRY(512, 16, 16, fs.e_col, fs.tile, CALL)   \
+  PKM_TRY(1024, 16, 8, fs.e_col, fs.tile, CALL)   \
+  PKM_TRY(64, 8, 8, fs.e_col, fs.tile, CALL)      \
+  PKM_TRY(128, 8, 8, fs.e_col, fs.tile, CALL)     \
+  PKM_TRY(256, 8, 8, fs.e_col, fs.tile, CALL)     \
+  PKM_TRY(512, 8, 8, fs.e_col, fs.tile, CALL)     \
+  PKM_TRY(1024, 8, 4, fs.e_col, fs.tile, CALL)
+
+#define PKM_TRY_POST(CALL)                           \
+  PKM_TRY(64, 8, 16, fs.e_post, fs.tile_post, CALL)  \
+  PKM_TRY(128, 8, 16, fs.e_post, fs.tile_post, CALL) \
+  PKM_TRY(256, 8, 8, fs.e_post, fs.tile_post, CALL)  \
+  PKM_TRY(512, 8, 4, fs.e_post, fs.tile_post, CALL)  \
+  PKM_TRY(1024, 8, 2, fs.e_post, fs.tile_post, CALL)
 
 template <typename T>
 hipError_t launch_zfwd(const FftShape& fs, const T* in0, const T* in1, void* out0, void* out1, int nbuf,
@@ -623,8 +700,10 @@ hipError_t launch_zfwd(const FftShape& fs, const T* in0, const T* in1, void* out
   const int lines = fs.n * fs.n;
   dim3 grid(lines / fs.zlines, nbuf);
   const size_t sm = zsmem(fs, sizeof(cx<T>));
-  PKM_DISPATCH_E(fs.e_z, (k_zfwd<T, E><<<grid, zthreads(fs), sm, s>>>(fs.n, fs.zlines, fs.sched_z, fs.nst_z, in0, in1,
-                                                                      out0, out1, (const cx<T>*)tw)));
+  PKM_TRY_Z((k_zfwd<T, E, NC, TC><<<grid, zthreads(fs), sm, s>>>(fs.n, fs.zlines, fs.sched_z, fs.nst_z, in0, in1,
+                                                                   out0, out1, (const cx<T>*)tw)));
+  PKM_DISPATCH_E(fs.e_z, (k_zfwd<T, E, 0, 0><<<grid, zthreads(fs), sm, s>>>(fs.n, fs.zlines, fs.sched_z, fs.nst_z, in0,
+                                                                          in1, out0, out1, (const cx<T>*)tw)));
   return hipGetLastError();
 }
 
@@ -637,11 +716,15 @@ hipError_t launch_col(const FftShape& fs, void* const* bufs_dev, int nbuf, int a
   dim3 grid(xpass_blocks(fs), nbuf);
   const size_t sm = colsmem(fs, sizeof(cx<T>));
   if (inverse) {
-    PKM_DISPATCH_E(fs.e_col, (k_col<T, E, true><<<grid, xpass_threads(fs), sm, s>>>(
+    PKM_TRY_COL((k_col<T, E, true, NC, TC><<<grid, xpass_threads(fs), sm, s>>>(
+        fs.n, fs.tile, fs.sched_col, fs.nst_col, bufs_dev, row_stride, outer_stride, (const cx<T>*)tw)));
+    PKM_DISPATCH_E(fs.e_col, (k_col<T, E, true, 0, 0><<<grid, xpass_threads(fs), sm, s>>>(
                                   fs.n, fs.tile, fs.sched_col, fs.nst_col, bufs_dev, row_stride, outer_stride,
                                   (const cx<T>*)tw)));
   } else {
-    PKM_DISPATCH_E(fs.e_col, (k_col<T, E, false><<<grid, xpass_threads(fs), sm, s>>>(
+    PKM_TRY_COL((k_col<T, E, false, NC, TC><<<grid, xpass_threads(fs), sm, s>>>(
+        fs.n, fs.tile, fs.sched_col, fs.nst_col, bufs_dev, row_stride, outer_stride, (const cx<T>*)tw)));
+    PKM_DISPATCH_E(fs.e_col, (k_col<T, E, false, 0, 0><<<grid, xpass_threads(fs), sm, s>>>(
                                   fs.n, fs.tile, fs.sched_col, fs.nst_col, bufs_dev, row_stride, outer_stride,
                                   (const cx<T>*)tw)));
   }
@@ -652,7 +735,10 @@ template <typename T>
 hipError_t launch_xcombine(const FftShape& fs, void* s1, void* s2, void* c_out, void* g_out, int interlaced,
                            int compensated, const void* invw, const void* phase, const void* tw, hipStream_t s) {
   const size_t sm = colsmem(fs, sizeof(cx<T>));
-  PKM_DISPATCH_E(fs.e_col, (k_xcombine<T, E><<<xpass_blocks(fs), xpass_threads(fs), sm, s>>>(
+  PKM_TRY_COL((k_xcombine<T, E, NC, TC><<<xpass_blocks(fs), xpass_threads(fs), sm, s>>>(
+      fs.n, fs.tile, fs.sched_col, fs.nst_col, (const cx<T>*)s1, (const cx<T>*)s2, (cx<T>*)c_out, (cx<T>*)g_out,
+      interlaced, compensated, (const T*)invw, (const cx<T>*)phase, (const cx<T>*)tw)));
+  PKM_DISPATCH_E(fs.e_col, (k_xcombine<T, E, 0, 0><<<xpass_blocks(fs), xpass_threads(fs), sm, s>>>(
                                fs.n, fs.tile, fs.sched_col, fs.nst_col, (const cx<T>*)s1, (const cx<T>*)s2,
                                (cx<T>*)c_out, (cx<T>*)g_out, interlaced, compensated, (const T*)invw,
                                (const cx<T>*)phase, (const cx<T>*)tw)));
@@ -665,7 +751,10 @@ hipError_t launch_zpre(const FftShape& fs, const void* g_in, const T* real_in, T
                        const void* tw, hipStream_t s) {
   const int lines = fs.n * fs.n;
   const size_t sm = zsmem(fs, sizeof(cx<T>));
-  PKM_DISPATCH_E(fs.e_z, (k_zpre<T, E><<<lines / fs.zlines, zthreads(fs), sm, s>>>(
+  PKM_TRY_Z((k_zpre<T, E, NC, TC><<<lines / fs.zlines, zthreads(fs), sm, s>>>(
+      fs.n, fs.zlines, fs.sched_z, fs.nst_z, (const cx<T>*)g_in, real_in, real_out, bufs_dev, nf, fields_dev,
+      (T)scale, off[0], off[1], off[2], h, (const T*)ytab, (const cx<T>*)tw)));
+  PKM_DISPATCH_E(fs.e_z, (k_zpre<T, E, 0, 0><<<lines / fs.zlines, zthreads(fs), sm, s>>>(
                              fs.n, fs.zlines, fs.sched_z, fs.nst_z, (const cx<T>*)g_in, real_in, real_out, bufs_dev,
                              nf, fields_dev, (T)scale, off[0], off[1], off[2], h, (const T*)ytab,
                              (const cx<T>*)tw)));
@@ -678,13 +767,15 @@ hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const
                         double* partial, int* nblocks_out, const void* tw, hipStream_t s) {
   if (nslots < 0) return hipErrorInvalidValue;
   const int rows = (with_l0 ? 3 : 0) + nslots;
-  const size_t sm = sizeof(cx<T>) * ((size_t)xrows(fs.n) * (fs.tile_post + 1) + fs.n) +
-                    sizeof(double) * (size_t)bs.hist_copies * rows * bs.nb;
+  const size_t sm = xpost_base_bytes(fs, sizeof(T) == 8) + sizeof(double) * (size_t)bs.hist_copies * rows * bs.nb;
   const int nblk = post_blocks(fs);
   const int nthr = (fs.n / fs.e_post) * fs.tile_post;
   if (nthr > XPOST_THREADS) return hipErrorInvalidValue;
   *nblocks_out = nblk;
-  PKM_DISPATCH_E(fs.e_post, (k_xpost<T, E><<<nblk, nthr, sm, s>>>(
+  PKM_TRY_POST((k_xpost<T, E, NC, TC><<<nblk, nthr, sm, s>>>(
+      fs.n, fs.tile_post, fs.sched_post, fs.nst_post, bufs_dev, nf, fields_dev, nslots, with_l0, kf,
+      (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies, partial, (const cx<T>*)tw)));
+  PKM_DISPATCH_E(fs.e_post, (k_xpost<T, E, 0, 0><<<nblk, nthr, sm, s>>>(
                                 fs.n, fs.tile_post, fs.sched_post, fs.nst_post, bufs_dev, nf, fields_dev, nslots,
                                 with_l0, kf, (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies,
                                 partial, (const cx<T>*)tw)));

@@ -468,7 +468,7 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
   }
   const int rows = 3 + ell_max / 2;  // count, ksum, Q0, Q2, ...
   {
-    const size_t col_lds_b = sizeof(T) * 2 * ((size_t)(n + n / 8 + 1) * (pl->fs.tile_post + 1) + n);
+    const size_t col_lds_b = xpost_base_bytes(pl->fs, sizeof(T) == 8);
     if (col_lds_b + sizeof(double) * 5 * (size_t)nb > 160 * 1024) {
       pl->err = "too many k bins for one pass";
       throw Fail{PKM_EINVAL};
@@ -533,8 +533,9 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
   }
   // histogram copies per block: one per wave when the LDS budget allows
   const int waves = ((n / pl->fs.e_post) * pl->fs.tile_post + 63) / 64;
-  const size_t col_lds = sizeof(T) * 2 * ((size_t)(n + n / 8 + 1) * (pl->fs.tile_post + 1) + n);
-  const size_t budget = 160 * 1024 - col_lds - 1024;
+  // two post-pass blocks per CU (the register budget allows no more)
+  const size_t col_lds = xpost_base_bytes(pl->fs, sizeof(T) == 8);
+  const size_t budget = col_lds + 1024 < 80 * 1024 ? 80 * 1024 - col_lds - 1024 : 0;
   check_hip(pl, launch_fill<double>(pl->out_dev, total_vals, 0.0, s), "zero out");
   check_hip(pl, hipEventRecord(pl->ev0, s), "event");
   const bool dc_real = !(pl->p.interlaced || pl->p.compensated);
