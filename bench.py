@@ -12,6 +12,9 @@ oracle on a bounded sample of the same estimate and scales it to estimates/s.
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import math
 import os
@@ -48,6 +51,68 @@ def stage_bytes(nmesh: int, es: int, n_part: int, nfields: int) -> dict:
     }
 
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+# Sources whose change invalidates stored HBM counter readings of the transform kernels.
+TRAFFIC_SOURCES = ["paper_1704_02357_amd/csrc/kernels_fft.hip", "paper_1704_02357_amd/csrc/device_common.hpp",
+                   "paper_1704_02357_amd/csrc/kernels.hpp", "paper_1704_02357_amd/csrc/plan.hip"]
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(stage: str):
+    """HBM bytes per launch of a stage from a committed counter summary (profiles/*_traffic.txt,
+    a line 'TRAFFIC {json}'), or None when there is none for the current kernel sources."""
+    digest = source_digest()
+    for path in sorted(glob.glob(os.path.join(HERE, "profiles", "*_traffic.txt"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("TRAFFIC "):
+                    continue
+                rec = json.loads(line[len("TRAFFIC "):])
+                if rec.get("stage") == stage and rec.get("source_digest") == digest and rec.get("nmesh") == NMESH:
+                    return rec["hbm_bytes_per_launch"]
+    return None
+
+
+def summarize_profile(directory: str) -> None:
+    """Print the per-kernel summary of a rocprofv3 CSV output directory: kernel statistics
+    (--kernel-trace --stats) and/or counter means per dispatch (--pmc)."""
+    def rows(pattern):
+        out = []
+        for path in sorted(glob.glob(os.path.join(directory, "**", pattern), recursive=True)):
+            with open(path, newline="") as f:
+                out.extend(csv.DictReader(f))
+        return out
+
+    def short(name):
+        name = name.replace("(anonymous namespace)::", "").replace("pkm::", "")
+        return name.split("(")[0].replace("void ", "")[:60]
+
+    stats = rows("*kernel_stats.csv")
+    if stats:
+        print(f"{'kernel':60s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}")
+        for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+            print(f"{short(r['Name']):60s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.1f} "
+                  f"{float(r['TotalDurationNs']) / 1e6:10.3f} {float(r['Percentage']):6.2f}")
+    pmc = rows("*counter_collection.csv")
+    if pmc:
+        acc = {}
+        for r in pmc:
+            key = (short(r["Kernel_Name"]), r["Counter_Name"])
+            a = acc.setdefault(key, [0.0, set()])
+            a[0] += float(r["Counter_Value"])
+            a[1].add(r["Dispatch_Id"])
+        print(f"{'kernel':60s} {'counter':>14s} {'dispatches':>10s} {'mean_per_dispatch':>18s}")
+        for (k, c), (v, d) in sorted(acc.items()):
+            print(f"{k:60s} {c:>14s} {len(d):10d} {v / len(d):18.6g}")
+
+
 def run_form(precision: int, data, rand, edges, steps: int, warmup: int):
     import torch
     from paper_1704_02357_amd import Plan
@@ -76,9 +141,11 @@ def run_form(precision: int, data, rand, edges, steps: int, warmup: int):
 def cpu_baseline(data, rand, edges, workers: int) -> dict:
     """FP64 oracle timed on a bounded sample of one estimate, scaled to estimates/s.
 
-    Sample: painting of 1/20 of the catalog (x20), one full-grid forward transform (x17
-    transforms), one harmonic field (Y_lm at every node and mode, product, accumulate; x14
-    fields) and one binning pass (x3 multipoles)."""
+    Sample: painting split into a per-cell part and a per-particle part, from two paints of
+    catalog subsamples (1/25 and 1/100) onto a 256^3 mesh (per-cell part x8 for 512^3, the
+    per-particle part extrapolated to the whole catalog); one full-grid forward transform (x17
+    transforms); the harmonic weighting of one field on 1/16 of the nodes and of the modes
+    (x16 x14 fields); one binning pass (x3 multipoles)."""
     import scipy.fft as sfft
     from oracle.estimator import default_params, k_thresholds, mode_bins, node_vectors, mode_vectors, binned_sums
     from oracle.mesh import fkp_meshes
@@ -86,35 +153,49 @@ def cpu_baseline(data, rand, edges, workers: int) -> dict:
     from oracle.ylm import real_ylm
     from synth import Catalog
     p = default_params(NMESH, BOX, observer=OBSERVER, window=3, interlaced=True, compensated=True)
-    frac = 20
-    sub_d = Catalog(data.pos[::frac], data.w[::frac], data.nbar[::frac])
-    sub_r = Catalog(rand.pos[::frac], rand.w[::frac], rand.nbar[::frac])
+    slab_div = 16
+    nfields = sum(2 * l + 1 for l in range(2, ELL_MAX + 1, 2))
     t = {}
-    t0 = time.perf_counter()
-    sc = catalog_scalars(sub_d, sub_r, BOX)
-    d1, d2 = fkp_meshes(sub_d, sub_r, sc["alpha"], NMESH, BOX, p["box_origin"], 3, True)
-    t["paint"] = (time.perf_counter() - t0) * frac
+
+    def paint_time(frac, nm):
+        sub_d = Catalog(data.pos[::frac], data.w[::frac], data.nbar[::frac])
+        sub_r = Catalog(rand.pos[::frac], rand.w[::frac], rand.nbar[::frac])
+        t0 = time.perf_counter()
+        sc = catalog_scalars(sub_d, sub_r, BOX)
+        meshes = fkp_meshes(sub_d, sub_r, sc["alpha"], nm, BOX, p["box_origin"], 3, True)
+        return time.perf_counter() - t0, meshes[0]
+
+    ta, m = paint_time(25, NMESH // 2)
+    tb, _ = paint_time(100, NMESH // 2)
+    per_catalog = max(0.0, (ta - tb) / (1 / 25 - 1 / 100))
+    per_mesh = max(0.0, ta - per_catalog / 25) * 8
+    t["paint"] = per_mesh + per_catalog
+    # a 512^3 density for the transform and field samples (the 256^3 mesh, each cell split in 8)
+    d1 = m.repeat(2, axis=0).repeat(2, axis=1).repeat(2, axis=2)
+    del m
     t0 = time.perf_counter()
     c = sfft.fftn(d1, workers=workers)
-    t["fft"] = (time.perf_counter() - t0) * 17
-    del d2
-    t0 = time.perf_counter()
+    t["fft"] = (time.perf_counter() - t0) * (nfields + 3)
     xv = node_vectors(NMESH, BOX, p["box_origin"], p["observer"])
     kv = mode_vectors(NMESH)
-    b = sfft.fftn(d1 * real_ylm(2, 1, xv), workers=workers)
-    a = real_ylm(2, 1, kv) * b
-    t["field"] = (time.perf_counter() - t0) * 14
-    del xv, kv, b
+    sl = NMESH // slab_div
+    t0 = time.perf_counter()
+    weighted = d1[:sl] * real_ylm(2, 1, xv[:sl])
+    a = real_ylm(2, 1, kv[:sl]) * c[:sl]
+    t["field"] = (time.perf_counter() - t0) * slab_div * nfields
+    del xv, kv, weighted
     t0 = time.perf_counter()
     bins = mode_bins(NMESH, k_thresholds(edges, BOX))
-    q = np.real(c * np.conj(a))
+    q = np.real(c * np.conj(c))
     binned_sums(q, bins, len(edges) - 1)
     t["bin"] = (time.perf_counter() - t0) * 3
     sec = sum(t.values())
     return {"value": 1.0 / sec, "unit": "estimates/s", "cores": workers, "kind": "oracle",
-            "sample": "FP64 numpy/scipy oracle: paint of 1/20 of the catalog (x20), one 512^3 complex FFT (x17), "
-                      "one Y_lm-weighted field incl. both harmonic evaluations (x14), one binning pass (x3); "
-                      f"seconds per estimate {sec:.1f} = " + ", ".join(f"{k} {v:.1f}" for k, v in t.items())}
+            "sample": f"FP64 numpy/scipy oracle: paint cost from 1/25 and 1/100 catalog subsamples on a 256^3 mesh "
+                      f"(per-cell part x8, per-particle part extrapolated to the catalog), one 512^3 complex "
+                      f"FFT (x{nfields + 3}), Y_lm(x) and Y_lm(k) weighting of one field on 1/{slab_div} of the "
+                      f"grid (x{slab_div} x{nfields}), one binning pass (x3); seconds per estimate {sec:.1f} = "
+                      + ", ".join(f"{k} {v:.1f}" for k, v in t.items())}
 
 
 def main():
@@ -129,7 +210,12 @@ def main():
     ap.add_argument("--fp32-only", action="store_true", help="skip the FP64 form (profiling runs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 1 GiB device copy (x3) first, to calibrate HBM byte counters")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="print the kernel summary of a rocprofv3 CSV output directory and exit")
     args = ap.parse_args()
+    if args.summarize_profile:
+        summarize_profile(args.summarize_profile)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).",
               file=sys.stderr)
@@ -182,7 +268,7 @@ def main():
     dom_bytes_per_launch = stage_bytes(NMESH, 4, n_part, nfields)[dom] * args.steps / stages[dom]["launches"]
     achieved = dom_bytes_per_launch / (stages[dom]["ms_per_launch"] * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(dom),
             "bytes_per_launch": dom_bytes_per_launch}
     total_model = sum(stage_bytes(NMESH, 4, n_part, nfields).values())
     out = {
