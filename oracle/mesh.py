@@ -64,6 +64,34 @@ def paint(u: np.ndarray, weight: np.ndarray, nmesh: int, window: int) -> np.ndar
     return out.reshape(n, n, n)
 
 
+def window_1d(d: np.ndarray, window: int) -> np.ndarray:
+    """Assignment weight of a particle at signed distance d (in cells) from a node, written
+    as the kernel itself rather than as taps: NGP 1 on [-1/2, 1/2); CIC max(0, 1 - |d|);
+    TSC 3/4 - d^2 for |d| <= 1/2, (3/2 - |d|)^2 / 2 for 1/2 < |d| < 3/2, else 0."""
+    a = np.abs(d)
+    if window == NGP:
+        return ((d >= -0.5) & (d < 0.5)).astype(np.float64)
+    if window == CIC:
+        return np.maximum(0.0, 1.0 - a)
+    if window == TSC:
+        return np.where(a <= 0.5, 0.75 - a * a, np.where(a < 1.5, 0.5 * (1.5 - a) ** 2, 0.0))
+    raise ValueError("window must be 1 (NGP), 2 (CIC) or 3 (TSC)")
+
+
+def paint_at(u: np.ndarray, weight: np.ndarray, nmesh: int, window: int, cells: np.ndarray) -> np.ndarray:
+    """Value of the painted mesh at the listed nodes (cells: (K, 3) ints): for each node c,
+    sum over particles of weight * prod_a W(u_a - c_a), the distance wrapped to [-N/2, N/2).
+    Same quantity as paint() at those nodes, evaluated from the kernel's definition."""
+    u = np.asarray(u, dtype=np.float64)
+    out = np.empty(len(cells))
+    for i, c in enumerate(np.asarray(cells)):
+        d = u - c[None, :]
+        d = d - nmesh * np.floor(d / nmesh + 0.5)
+        w = window_1d(d[:, 0], window) * window_1d(d[:, 1], window) * window_1d(d[:, 2], window)
+        out[i] = np.sum(weight * w)
+    return out
+
+
 def fkp_meshes(data, randoms, alpha: float, nmesh: int, box_len: float, origin, window: int,
                interlaced: bool):
     """D1 (and D2 when interlaced) = sum_d w W - alpha sum_r w W."""

@@ -15,3 +15,18 @@ from .lognormal import (  # noqa: F401
     config_c3,
     batch_mock,
 )
+
+
+def catalog_digest(*catalogs) -> str:
+    """Short SHA-256 of the positions, weights and densities of the given catalogs, used to
+    check that a regenerated seeded catalog is the one a stored result was computed for."""
+    import hashlib
+
+    import numpy as np
+
+    h = hashlib.sha256()
+    for c in catalogs:
+        for a in (c.pos, c.w, c.nbar):
+            if a is not None:
+                h.update(np.ascontiguousarray(a, dtype=np.float64).tobytes())
+    return h.hexdigest()[:16]

@@ -8,7 +8,7 @@ import scipy.fft as sfft
 from synth import Catalog
 from oracle.catalog import catalog_scalars
 from oracle.mesh import (CIC, NGP, TSC, axis_taps, combine, compensation_1d, fkp_meshes,
-                         int_freq, mesh_coords, nyquist_mask, paint)
+                         int_freq, mesh_coords, nyquist_mask, paint, paint_at, window_1d)
 
 
 def _cat(pos, w=None, nbar=None):
@@ -117,3 +117,27 @@ def test_jing_alias_sums(window, p):
         sinc = np.where(f == 0, 1.0, np.sin(x) / np.where(f == 0, 1.0, x))
     assert np.max(np.abs(compensation_1d(n, window, True) - sinc ** window)) < 1e-15
     assert np.all(compensation_1d(n, NGP, False) == 1.0)
+
+
+@pytest.mark.parametrize("window", [NGP, CIC, TSC])
+def test_paint_at_matches_tap_painting(window):
+    """The kernel-definition evaluation at chosen nodes equals the tap painter there,
+    including nodes reached through the periodic wrap."""
+    rng = np.random.default_rng(11 + window)
+    n = 12
+    u = rng.random((300, 3)) * n
+    u[:20] = rng.random((20, 3)) * 1.2 - 0.6          # straddling the wrap at 0
+    u[20:25] = np.floor(u[20:25]) + 0.5                # exactly on a cell edge
+    w = rng.normal(size=300)
+    full = paint(u, w, n, window)
+    cells = np.array([[i, j, k] for i in (0, 1, 5, 11) for j in (0, 6, 11) for k in (0, 3, 11)])
+    got = paint_at(u, w, n, window, cells)
+    ref = full[cells[:, 0], cells[:, 1], cells[:, 2]]
+    assert np.allclose(got, ref, rtol=0, atol=1e-13 * np.sum(np.abs(w)))
+
+
+def test_window_kernels_closed_form():
+    d = np.array([-1.6, -1.5, -1.0, -0.5, -0.25, 0.0, 0.25, 0.5, 1.0, 1.5])
+    assert np.array_equal(window_1d(d, NGP), [0, 0, 0, 1, 1, 1, 1, 0, 0, 0])
+    assert np.allclose(window_1d(d, CIC), [0, 0, 0, 0.5, 0.75, 1, 0.75, 0.5, 0, 0])
+    assert np.allclose(window_1d(d, TSC), [0, 0, 0.125, 0.5, 0.6875, 0.75, 0.6875, 0.5, 0.125, 0])
