@@ -45,7 +45,12 @@ def pole_errors(gpu: dict, orc: dict):
 def assert_pole_parity(gpu: dict, orc: dict, precision: int, label: str = ""):
     assert np.array_equal(np.asarray(gpu["n_modes"]), np.asarray(orc["n_modes"])), f"{label}: mode counts differ"
     km_ok = np.isfinite(orc["k_mean"])
-    assert np.allclose(gpu["k_mean"][km_ok], orc["k_mean"][km_ok], rtol=1e-13, atol=0), f"{label}: k_mean"
+    # k_mean is a sum of n_b positive FP64 terms on both sides, in different orders: the
+    # recursive-summation bound (n_b - 1) u, u = 2^-53, with a floor of 1e-13
+    cnt = np.asarray(orc["n_modes"], dtype=np.float64)[km_ok]
+    km_tol = np.maximum(1e-13, cnt * 2.0 ** -53)
+    km_err = np.abs(gpu["k_mean"][km_ok] - orc["k_mean"][km_ok]) / np.abs(orc["k_mean"][km_ok])
+    assert np.all(km_err <= km_tol), f"{label}: k_mean rel err {km_err.max():.2e}"
     for key in ("alpha", "norm_I", "shot_noise"):
         assert abs(gpu[key] - orc[key]) <= 1e-13 * abs(orc[key]) + 1e-300, f"{label}: {key}"
     scaled, plain = pole_errors(gpu, orc)
