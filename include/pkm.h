@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define PKM_ABI_VERSION 1
+#define PKM_ABI_VERSION 2
 
 typedef enum {
   PKM_OK = 0,
@@ -216,6 +216,110 @@ pkm_status pkm_fft3d_inverse(pkm_plan* plan, void* in_half_dev, void* out_real_d
  *           3: D_c, the field that is harmonically weighted (real N^3).
  * bytes must equal the buffer size (N^3 or N^3 complex/2 elements of the plan precision). */
 pkm_status pkm_plan_read_buffer(pkm_plan* plan, int32_t which, void* host_dst, size_t bytes);
+
+/* ---------------------------------------------------------------------------------------
+ * Asynchronous estimates.  The same computation as pkm_paint + pkm_compute_multipoles
+ * (Sec. 2.1 eq. FKP-density, eq. Pell-ours, eq. Fell; Sec. 2.3), split so that the device
+ * work can overlap with other plans' work or be recorded into a HIP graph.
+ *
+ * pkm_prepare     builds the request's host tables (k thresholds, field groups, reduce maps)
+ *                 and reserves device and pinned-host buffers for up to max_particles data +
+ *                 random objects.  Synchronous; may allocate.  Re-preparing with another
+ *                 ell_max or other edges replaces the tables.
+ * pkm_enqueue     enqueues one whole estimate (paint, transforms, multipoles, and the copy
+ *                 of the bin sums to the plan's pinned staging) on the plan's stream and
+ *                 returns without waiting.  Catalogs must be device-resident (on_device = 1)
+ *                 and stay valid and unmodified until pkm_finish returns.  Allocates nothing,
+ *                 issues no synchronous HIP call: the enqueue may be captured into a graph.
+ *                 PKM_EBUSY if a previous enqueue has not been finished; PKM_EORDER if the
+ *                 plan is not prepared; PKM_EINVAL above the reserved particle count.
+ * pkm_query       PKM_OK when the enqueued estimate has completed, PKM_EBUSY while it runs.
+ * pkm_finish      waits for it and normalises (FP64, host) into `out` as pkm_compute_multipoles
+ *                 does for the prepared ell_max and edges.  Afterwards the plan holds the
+ *                 painted field as after pkm_paint.
+ * pkm_paint / pkm_compute_multipoles return PKM_EBUSY between pkm_enqueue and pkm_finish.
+ * ------------------------------------------------------------------------------------- */
+pkm_status pkm_prepare(pkm_plan* plan, int32_t ell_max, const double* k_edges, int32_t n_edges,
+                       int64_t max_particles);
+pkm_status pkm_enqueue(pkm_plan* plan, const pkm_catalog* data, const pkm_catalog* randoms);
+pkm_status pkm_query(pkm_plan* plan);
+pkm_status pkm_finish(pkm_plan* plan, pkm_result* out);
+
+/* ---------------------------------------------------------------------------------------
+ * Batches: many estimates (e.g. a set of covariance mocks of uneven mesh size, Sec. 4.1's
+ * motivation) issued as one unit.  Each item is (prepared plan, device catalogs).  Items on
+ * distinct plans run concurrently on the plans' streams (each plan needs its own non-null
+ * stream); items sharing a plan run in the order added.  With use_graph = 1 the first run
+ * captures the whole issue sequence into a HIP graph (fork/join over the plans' streams) and
+ * later runs replay it with one launch; adding an item drops the graph.  The catalogs'
+ * device pointers and counts are recorded: their contents may change between runs, their
+ * addresses and sizes may not.  Plans in a batch must not be re-prepared or used directly
+ * while the batch holds them.
+ *   pkm_batch_run    issues (or replays) every item, waits, and reports the device time
+ *                    from the fork to the join in *ms_out (may be NULL).
+ *   pkm_batch_result normalises item `index` of the last run into `out` (FP64, host).
+ * ------------------------------------------------------------------------------------- */
+typedef struct pkm_batch pkm_batch;
+pkm_status pkm_batch_create(int32_t device_id, pkm_batch** out);
+pkm_status pkm_batch_add(pkm_batch* batch, pkm_plan* plan, const pkm_catalog* data, const pkm_catalog* randoms,
+                         int32_t* index_out);
+pkm_status pkm_batch_run(pkm_batch* batch, int32_t use_graph, double* ms_out);
+pkm_status pkm_batch_result(pkm_batch* batch, int32_t index, pkm_result* out);
+int32_t pkm_batch_size(const pkm_batch* batch);
+const char* pkm_batch_last_error(const pkm_batch* batch);
+void pkm_batch_destroy(pkm_batch* batch);
+
+/* ---------------------------------------------------------------------------------------
+ * Serving: a request loop on one device.  Requests (mesh parameters, ell_max, k edges and
+ * host catalogs, copied at submit) are admitted in arrival order as soon as fewer than
+ * max_inflight estimates run and the device bytes of resident plans plus the request's
+ * footprint fit hbm_budget_bytes (idle plans are evicted least recently used first; a
+ * request that cannot fit even alone fails with PKM_ENOMEM).  Admitted requests run on
+ * separate streams and overlap on the device; plans (meshes, tables, staging) stay resident
+ * and are reused by later requests with the same mesh, box, observer, window and precision.
+ * Results are computed exactly as by pkm_paint + pkm_compute_multipoles.
+ *   pkm_server_submit  queues a request and returns its ticket (PKM_EINVAL on bad input).
+ *   pkm_server_poll    PKM_EBUSY until the request has finished, then copies the result
+ *                      into `out` (arrays sized as for pkm_compute_multipoles) once.
+ *   pkm_server_wait    blocks until then.
+ *   pkm_server_stats   completed / failed / queued / in-flight counts, resident and peak
+ *                      device bytes, the largest number of concurrent estimates seen,
+ *                      latency percentiles (submit to completion, ms) and throughput.
+ *   pkm_server_destroy finishes the requests in flight, cancels queued ones, frees all.
+ * The server functions are thread safe.
+ * ------------------------------------------------------------------------------------- */
+typedef struct {
+  int32_t device_id;
+  int64_t hbm_budget_bytes;  /* admission budget; <= 0 selects 80% of the free memory */
+  int32_t max_inflight;      /* concurrent estimates, 1..32 */
+} pkm_server_config;
+
+typedef struct {
+  pkm_params params;         /* ell_max_hint and max_group are taken from here */
+  int32_t ell_max;
+  const double* k_edges;
+  int32_t n_edges;
+  pkm_catalog data;          /* host arrays (on_device = 0) */
+  pkm_catalog randoms;       /* host arrays, used when has_randoms = 1 (nbar required) */
+  int32_t has_randoms;
+} pkm_request;
+
+typedef struct {
+  int64_t completed, failed, queued, inflight;
+  int64_t resident_plans, resident_bytes, peak_bytes;
+  int32_t max_concurrent;
+  double latency_p50_ms, latency_p99_ms, latency_mean_ms;
+  double throughput_per_s;   /* completed requests / (last completion - first submit) */
+} pkm_server_stats_t;
+
+typedef struct pkm_server pkm_server;
+pkm_status pkm_server_create(const pkm_server_config* cfg, pkm_server** out);
+pkm_status pkm_server_submit(pkm_server* server, const pkm_request* request, int64_t* ticket);
+pkm_status pkm_server_poll(pkm_server* server, int64_t ticket, pkm_result* out);
+pkm_status pkm_server_wait(pkm_server* server, int64_t ticket, pkm_result* out);
+pkm_status pkm_server_stats(pkm_server* server, pkm_server_stats_t* out);
+const char* pkm_server_last_error(const pkm_server* server);
+void pkm_server_destroy(pkm_server* server);
 
 #ifdef __cplusplus
 }

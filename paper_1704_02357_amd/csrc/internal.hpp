@@ -1,0 +1,30 @@
+// Entry points of the plan (plan.hip) used by the batch and serving runtime (runtime.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/pkm.h"
+
+namespace pkm_internal {
+
+// Host tables of a multipole request and buffers for up to max_particles objects.
+pkm_status prepare(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, int64_t max_particles);
+// Doubles of a result slot of the prepared request (catalog sums + bin sums).
+size_t slot_doubles(const pkm_plan* pl);
+bool prepared(const pkm_plan* pl);
+hipStream_t stream_of(const pkm_plan* pl);
+int device_of(const pkm_plan* pl);
+int64_t device_bytes(const pkm_plan* pl);
+std::string& error_of(pkm_plan* pl);
+// One whole estimate of device catalogs, results to a pinned host slot; no allocation, no
+// host wait (capturable).
+pkm_status enqueue(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* randoms, double* slot);
+// Normalise a completed slot into `out` (the prepared ell_max and edges).
+void finish(pkm_plan* pl, const double* slot, int64_t nd, int64_t nr, pkm_result* out);
+// Device bytes a plan with these parameters would hold for one request (admission control).
+int64_t footprint(const pkm_params* p, int ell_max, int n_edges, int64_t n_particles);
+
+}  // namespace pkm_internal

@@ -25,8 +25,20 @@
 #include "../../include/pkm.h"
 #include "kernels.hpp"
 #include "device_common.hpp"
+#include "internal.hpp"
 
 using namespace pkm;
+
+// One field group of a multipole request: field-table offsets, reduce map, histogram shape.
+struct GroupCfg {
+  int nf = 0, fofs = 0, pofs = 0, mofs = 0, nv = 0, nslots = 0, copies = 1;
+};
+struct ComputeCfg {
+  int ell_max = -1;
+  std::vector<double> edges;
+  int nb = 0, total_vals = 0, nfields_total = 0;
+  std::vector<GroupCfg> groups;
+};
 
 struct pkm_plan {
   pkm_params p{};
@@ -46,6 +58,14 @@ struct pkm_plan {
   std::vector<void*> fields;
   void** ptrs_dev = nullptr;  // device array of buffer pointers (fields, then scratch slots)
   int ptr_cap = 0;
+  void** paint_ptrs = nullptr;  // device array {s1, s2, g} for the paint passes
+  ComputeCfg cc;              // tables of the last prepared multipole request
+  // asynchronous estimate (pkm_prepare / pkm_enqueue / pkm_finish)
+  double* slot = nullptr;     // pinned host staging, slot_cap doubles
+  size_t slot_cap = 0;
+  hipEvent_t done = nullptr;
+  int64_t pend_nd = 0, pend_nr = 0;
+  bool pending_async = false;
   int* ftab_dev = nullptr;    // (l, m, slot) per field, all groups
   int ftab_cap = 0;
   int* map_dev = nullptr;     // reduce map per value
@@ -283,37 +303,22 @@ void** scratch_ptrs(pkm_plan* pl, std::initializer_list<void*> ps) {
   return dst;
 }
 
-template <typename T> void run_paint(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* rand) {
+// ------------------------------------------------------------------------------------------
+// Estimate, split into a host-side preparation and a device-only enqueue.  The enqueue
+// functions allocate nothing and never wait on the device, so they may be recorded into a
+// HIP graph or overlap with other plans' work on other streams.
+// ------------------------------------------------------------------------------------------
+
+// Device catalog pointers and counts of one estimate.
+struct DevCats {
+  const double *dp = nullptr, *dw = nullptr, *dn = nullptr;
+  const double *rp = nullptr, *rw = nullptr, *rn = nullptr;
+  int64_t nd = 0, nr = 0;
+};
+
+// Copy host catalogs into the plan's staging buffer (device catalogs pass through).
+DevCats stage_catalogs(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* rand) {
   hipStream_t s = pl->stream;
-  const int n = pl->p.nmesh;
-  const size_t cells = (size_t)n * n * n;
-  // stage host catalogs
-  auto stage = [&](const pkm_catalog* cat, size_t offset, const double** pos, const double** w, const double** nbar) {
-    if (cat->on_device) {
-      *pos = cat->pos;
-      *w = cat->w;
-      *nbar = cat->nbar;
-      return offset;
-    }
-    const size_t nn = (size_t)cat->n;
-    double* base = pl->cat_dev + offset;
-    check_hip(pl, hipMemcpyAsync(base, cat->pos, nn * 3 * sizeof(double), hipMemcpyHostToDevice, s), "upload pos");
-    *pos = base;
-    offset += nn * 3;
-    if (cat->w) {
-      check_hip(pl, hipMemcpyAsync(pl->cat_dev + offset, cat->w, nn * sizeof(double), hipMemcpyHostToDevice, s),
-                "upload w");
-      *w = pl->cat_dev + offset;
-      offset += nn;
-    } else *w = nullptr;
-    if (cat->nbar) {
-      check_hip(pl, hipMemcpyAsync(pl->cat_dev + offset, cat->nbar, nn * sizeof(double), hipMemcpyHostToDevice, s),
-                "upload nbar");
-      *nbar = pl->cat_dev + offset;
-      offset += nn;
-    } else *nbar = nullptr;
-    return offset;
-  };
   size_t need = 0;
   for (const pkm_catalog* cat : {data, rand})
     if (cat && !cat->on_device) need += (size_t)cat->n * 3 + (cat->w ? cat->n : 0) + (cat->nbar ? cat->n : 0);
@@ -324,49 +329,92 @@ template <typename T> void run_paint(pkm_plan* pl, const pkm_catalog* data, cons
     pl->cat_dev = (double*)dalloc(pl, need * sizeof(double));
     pl->cat_cap = need;
   }
-  const double *dp, *dw, *dn, *rp = nullptr, *rw = nullptr, *rn = nullptr;
-  size_t off = stage(data, 0, &dp, &dw, &dn);
-  if (rand) stage(rand, off, &rp, &rw, &rn);
-  check_hip(pl, hipEventRecord(pl->ev0, s), "event");
-  // catalog scalars (FP64, fixed-order reductions)
-  double sums[4] = {0, 0, 0, 0};
+  size_t offset = 0;
+  auto one = [&](const pkm_catalog* cat, const double** pos, const double** w, const double** nbar) {
+    if (cat->on_device) {
+      *pos = cat->pos;
+      *w = cat->w;
+      *nbar = cat->nbar;
+      return;
+    }
+    const size_t nn = (size_t)cat->n;
+    auto up = [&](const double* src, size_t count, const char* what) {
+      double* dst = pl->cat_dev + offset;
+      check_hip(pl, hipMemcpyAsync(dst, src, count * sizeof(double), hipMemcpyHostToDevice, s), what);
+      offset += count;
+      return (const double*)dst;
+    };
+    *pos = up(cat->pos, nn * 3, "upload pos");
+    *w = cat->w ? up(cat->w, nn, "upload w") : nullptr;
+    *nbar = cat->nbar ? up(cat->nbar, nn, "upload nbar") : nullptr;
+  };
+  DevCats dc;
+  one(data, &dc.dp, &dc.dw, &dc.dn);
+  dc.nd = data->n;
+  if (rand) {
+    one(rand, &dc.rp, &dc.rw, &dc.rn);
+    dc.nr = rand->n;
+  }
+  return dc;
+}
+
+void reserve_particles(pkm_plan* pl, int64_t ntot) {
+  if ((size_t)ntot <= pl->sort_cap) return;
+  for (int** b : {&pl->tile_of, &pl->tile_rank}) {
+    dfree(pl, *b);
+    *b = nullptr;
+  }
+  dfree(pl, pl->payload);
+  pl->payload = nullptr;
+  pl->sort_cap = 0;
+  pl->tile_of = (int*)dalloc(pl, sizeof(int) * ntot);
+  pl->tile_rank = (int*)dalloc(pl, sizeof(int) * ntot);
+  pl->payload = dalloc(pl, 32 * (size_t)ntot);
+  pl->sort_cap = (size_t)ntot;
+}
+
+// alpha = N_d / N_r (unweighted counts); 0 for a periodic box.
+double alpha_of(int64_t nd, int64_t nr) { return nr > 0 ? (double)nd / (double)nr : 0.0; }
+
+// I and S from the catalog sums {sum_d w^2, -, sum_r w^2, sum_r w^2 nbar}.
+void scalars_of(const pkm_plan* pl, const double* sums, int64_t nd, int64_t nr, double* alpha, double* norm_I,
+                double* shot) {
+  const double sd2 = sums[0];
+  *alpha = alpha_of(nd, nr);
+  if (nr > 0) {
+    *norm_I = *alpha * sums[3];
+    *shot = (sd2 + *alpha * *alpha * sums[2]) / *norm_I;
+  } else {
+    const double L = pl->p.box_len;
+    const double nbar = (double)nd / (L * L * L);
+    *norm_I = nbar * sd2;
+    *shot = sd2 / *norm_I;
+  }
+}
+
+// Catalog sums, painting, forward transforms, combine and inverse of the combined field.
+// Leaves the sums in sums_dev[0..3], C and G resident.  Needs sort capacity >= nd + nr.
+template <typename T> void enqueue_paint(pkm_plan* pl, const DevCats& dc) {
+  hipStream_t s = pl->stream;
+  const int n = pl->p.nmesh;
+  const size_t cells = (size_t)n * n * n;
+  const bool has_r = dc.nr > 0;
   {
     StageScope ss(pl, PKM_STAGE_SUMS);
-    check_hip(pl, launch_catalog_sums(dw, nullptr, data->n, pl->sums_dev + 4, SUM_BLOCKS, pl->sums_dev, s), "sums");
-    if (rand)
-      check_hip(pl, launch_catalog_sums(rw, rn, rand->n, pl->sums_dev + 4, SUM_BLOCKS, pl->sums_dev + 2, s), "sums");
+    check_hip(pl, launch_catalog_sums(dc.dw, nullptr, dc.nd, pl->sums_dev + 4, SUM_BLOCKS, pl->sums_dev, s), "sums");
+    if (has_r)
+      check_hip(pl, launch_catalog_sums(dc.rw, dc.rn, dc.nr, pl->sums_dev + 4, SUM_BLOCKS, pl->sums_dev + 2, s),
+                "sums");
   }
-  check_hip(pl, hipMemcpyAsync(sums, pl->sums_dev, sizeof sums, hipMemcpyDeviceToHost, s), "download sums");
-  check_hip(pl, hipStreamSynchronize(s), "sync");
-  const double sd2 = sums[0];
-  if (rand) {
-    pl->alpha = (double)data->n / (double)rand->n;
-    pl->norm_I = pl->alpha * sums[3];
-    pl->shot = (sd2 + pl->alpha * pl->alpha * sums[2]) / pl->norm_I;
-  } else {
-    const double nbar = (double)data->n / (pl->p.box_len * pl->p.box_len * pl->p.box_len);
-    pl->alpha = 0.0;
-    pl->norm_I = nbar * sd2;
-    pl->shot = sd2 / pl->norm_I;
-  }
-  // paint: tile sort, then per-tile LDS accumulation
   T* d1 = (T*)pl->d1;
   T* d2 = pl->p.interlaced ? (T*)pl->d2 : nullptr;
   const double scale = (double)n / pl->p.box_len;
-  const int64_t nd = data->n, nr = rand ? rand->n : 0, ntot = nd + nr;
+  const int64_t ntot = dc.nd + dc.nr;
   if ((size_t)ntot > pl->sort_cap) {
-    for (int** b : {&pl->tile_of, &pl->tile_rank}) {
-      dfree(pl, *b);
-      *b = nullptr;
-    }
-    dfree(pl, pl->payload);
-    pl->payload = nullptr;
-    pl->sort_cap = 0;
-    pl->tile_of = (int*)dalloc(pl, sizeof(int) * ntot);
-    pl->tile_rank = (int*)dalloc(pl, sizeof(int) * ntot);
-    pl->payload = dalloc(pl, 32 * (size_t)ntot);
-    pl->sort_cap = (size_t)ntot;
+    pl->err = "particle count above the plan's reserved capacity";
+    throw Fail{PKM_EINVAL};
   }
+  const double alpha = alpha_of(dc.nd, dc.nr);
   {
     StageScope ss(pl, PKM_STAGE_FILL);
     check_hip(pl, launch_fill<int>(pl->tile_count, (size_t)pl->ntiles, 0, s), "fill");
@@ -375,23 +423,22 @@ template <typename T> void run_paint(pkm_plan* pl, const pkm_catalog* data, cons
   }
   {
     StageScope ss(pl, PKM_STAGE_PAINT);
-    check_hip(pl, launch_tile_sort(dp, nd, 0, pl->p.box_origin, scale, n, pl->ts, pl->tile_count, pl->tile_of,
+    check_hip(pl, launch_tile_sort(dc.dp, dc.nd, 0, pl->p.box_origin, scale, n, pl->ts, pl->tile_count, pl->tile_of,
                                    pl->tile_rank, s),
               "tile sort");
-    if (rand)
-      check_hip(pl, launch_tile_sort(rp, nr, nd, pl->p.box_origin, scale, n, pl->ts, pl->tile_count, pl->tile_of,
-                                     pl->tile_rank, s),
+    if (has_r)
+      check_hip(pl, launch_tile_sort(dc.rp, dc.nr, dc.nd, pl->p.box_origin, scale, n, pl->ts, pl->tile_count,
+                                     pl->tile_of, pl->tile_rank, s),
                 "tile sort");
-    check_hip(pl, launch_tile_offsets(pl->tile_count, pl->ntiles, pl->tile_off, pl->tile_of, pl->tile_rank, nd, ntot,
-                                      dp, dw, rp, rw, pl->alpha, pl->payload, pl->scan_sums, s),
+    check_hip(pl, launch_tile_offsets(pl->tile_count, pl->ntiles, pl->tile_off, pl->tile_of, pl->tile_rank, dc.nd,
+                                      ntot, dc.dp, dc.dw, dc.rp, dc.rw, alpha, pl->payload, pl->scan_sums, s),
               "tile offsets");
     check_hip(pl, launch_paint_tiles<T>(pl->tile_off, pl->payload, pl->ntiles, pl->p.box_origin, scale, n,
                                         pl->p.window, pl->ts, d1, d2, s),
               "paint");
   }
-  // forward transforms and combine
   const int nbuf = d2 ? 2 : 1;
-  void** sp = scratch_ptrs(pl, {pl->s1, pl->s2, pl->g});
+  void** sp = pl->paint_ptrs;  // {s1, s2, g}
   {
     StageScope ss(pl, PKM_STAGE_ZFWD);
     check_hip(pl, launch_zfwd<T>(pl->fs, d1, d2, pl->s1, pl->s2, nbuf, pl->tw, s), "zfwd");
@@ -411,24 +458,47 @@ template <typename T> void run_paint(pkm_plan* pl, const pkm_catalog* data, cons
     StageScope ss(pl, PKM_STAGE_IYCOL);
     check_hip(pl, launch_col<T>(pl->fs, sp + 2, 1, 1, true, pl->tw, s), "inverse y pass");
   }
+}
+
+template <typename T> void run_paint(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* rand) {
+  hipStream_t s = pl->stream;
+  DevCats dc = stage_catalogs(pl, data, rand);
+  reserve_particles(pl, dc.nd + dc.nr);
+  check_hip(pl, hipEventRecord(pl->ev0, s), "event");
+  enqueue_paint<T>(pl, dc);
+  double sums[4] = {0, 0, 0, 0};
+  check_hip(pl, hipMemcpyAsync(sums, pl->sums_dev, sizeof sums, hipMemcpyDeviceToHost, s), "download sums");
   check_hip(pl, hipEventRecord(pl->ev1, s), "event");
   check_hip(pl, hipStreamSynchronize(s), "sync");
+  scalars_of(pl, sums, dc.nd, dc.nr, &pl->alpha, &pl->norm_I, &pl->shot);
   resolve_stages(pl);
   float ms = 0;
   (void)hipEventElapsedTime(&ms, pl->ev0, pl->ev1);
   pl->stats.ms_paint = ms;
   const double R = (double)pl->mesh_bytes;
-  const double cat_bytes = 40.0 * (double)data->n + (rand ? 40.0 * (double)rand->n : 0.0);
+  const int nbuf = pl->p.interlaced ? 2 : 1;
+  const bool need_dc = pl->p.interlaced || pl->p.compensated;
+  const double cat_bytes = 40.0 * (double)(dc.nd + dc.nr);
   pl->stats.model_bytes_paint = cat_bytes + nbuf * (2 * R) /*zero + scatter*/ + nbuf * (2 * R) /*z*/ +
                                 nbuf * (2 * R) /*y*/ + nbuf * R + 2 * R /*x combine*/ + (need_dc ? 2 * R : 0);
   pl->painted = true;
 }
 
-template <typename T>
-void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, pkm_result* out) {
-  hipStream_t s = pl->stream;
+// Host tables of a multipole request (thresholds, field groups, reduce maps, partial sums),
+// cached until ell_max or the edges change.
+template <typename T> void prepare_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges) {
+  ComputeCfg& cc = pl->cc;
+  if (cc.ell_max == ell_max && cc.edges.size() == (size_t)n_edges &&
+      std::equal(cc.edges.begin(), cc.edges.end(), k_edges))
+    return;
+  cc = ComputeCfg{};
   const int n = pl->p.nmesh;
   const int nb = n_edges - 1;
+  {
+    const int need = fields_for(ell_max);
+    if ((int)pl->fields.size() < need && (pl->p.max_group <= 0 || (int)pl->fields.size() < pl->p.max_group))
+      ensure_fields(pl, pl->p.max_group > 0 ? std::min(need, pl->p.max_group) : need);
+  }
   // integer thresholds T_i = ceil(((e_i * L) / (2 pi))^2)
   std::vector<long long> thr(n_edges);
   const double twopi = 2.0 * M_PI;
@@ -467,12 +537,10 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
     if (groups.empty()) groups.push_back({});  // l = 0 only
   }
   const int rows = 3 + ell_max / 2;  // count, ksum, Q0, Q2, ...
-  {
-    const size_t col_lds_b = xpost_base_bytes(pl->fs, sizeof(T) == 8);
-    if (col_lds_b + sizeof(double) * 5 * (size_t)nb > 160 * 1024) {
-      pl->err = "too many k bins for one pass";
-      throw Fail{PKM_EINVAL};
-    }
+  const size_t col_lds = xpost_base_bytes(pl->fs, sizeof(T) == 8);
+  if (col_lds + sizeof(double) * 5 * (size_t)nb > 160 * 1024) {
+    pl->err = "too many k bins for one pass";
+    throw Fail{PKM_EINVAL};
   }
   const int total_vals = rows * nb;
   if (pl->out_cap < (size_t)total_vals) {
@@ -485,7 +553,6 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
   // continues from the previous one; the post-pass walks them l-major (slots contiguous),
   // |m| ascending with +m before -m.  Buffer b of a group holds its b-th field (l-major).
   std::vector<int> ftab, maps;
-  std::vector<int> fofs, pofs, mofs, nvals_g, nslots_g;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const auto& g = groups[gi];
     std::vector<int> idx(g.size());
@@ -495,20 +562,24 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
     std::vector<int> pre = idx, post = idx;
     std::stable_sort(pre.begin(), pre.end(), [&](int a, int b) { return key_pre(a) < key_pre(b); });
     std::stable_sort(post.begin(), post.end(), [&](int a, int b) { return key_post(a) < key_post(b); });
-    fofs.push_back((int)ftab.size() / 4);
+    GroupCfg gc;
+    gc.nf = (int)g.size();
+    gc.fofs = (int)ftab.size() / 4;
     for (int i : pre) { ftab.push_back(i); ftab.push_back(g[i].l); ftab.push_back(g[i].m); ftab.push_back(g[i].slot); }
-    pofs.push_back((int)ftab.size() / 4);
+    gc.pofs = (int)ftab.size() / 4;
     for (int i : post) { ftab.push_back(i); ftab.push_back(g[i].l); ftab.push_back(g[i].m); ftab.push_back(g[i].slot); }
     std::vector<int> slot_l;
     for (auto& f : g) if ((int)slot_l.size() <= f.slot) slot_l.push_back(f.l);
     const bool first = gi == 0;
-    mofs.push_back((int)maps.size());
+    gc.mofs = (int)maps.size();
     int nv = 0;
     if (first) for (int r = 0; r < 3; ++r) for (int b = 0; b < nb; ++b) { maps.push_back(r * nb + b); ++nv; }
     for (size_t si = 0; si < slot_l.size(); ++si)
       for (int b = 0; b < nb; ++b) { maps.push_back((2 + slot_l[si] / 2) * nb + b); ++nv; }
-    nvals_g.push_back(nv);
-    nslots_g.push_back((int)slot_l.size());
+    gc.nv = nv;
+    gc.nslots = (int)slot_l.size();
+    cc.groups.push_back(gc);
+    cc.nfields_total += gc.nf;
   }
   if (pl->ftab_cap < (int)ftab.size() + 4) {
     dfree(pl, pl->ftab_dev);
@@ -525,92 +596,136 @@ void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, 
   check_hip(pl, hipMemcpy(pl->map_dev, maps.data(), sizeof(int) * maps.size(), hipMemcpyHostToDevice), "maps");
   const int nblk = post_blocks(pl->fs);
   int max_nv = 0;
-  for (int v : nvals_g) max_nv = std::max(max_nv, v);
+  for (auto& gc : cc.groups) max_nv = std::max(max_nv, gc.nv);
   if (pl->partial_cap < (size_t)nblk * max_nv) {
     dfree(pl, pl->partial);
     pl->partial = (double*)dalloc(pl, sizeof(double) * (size_t)nblk * max_nv);
     pl->partial_cap = (size_t)nblk * max_nv;
   }
-  // histogram copies per block: one per wave when the LDS budget allows
+  // histogram copies per block: one per wave when the LDS budget of two post-pass blocks per
+  // CU allows (the register budget allows no more than two)
   const int waves = ((n / pl->fs.e_post) * pl->fs.tile_post + 63) / 64;
-  // two post-pass blocks per CU (the register budget allows no more)
-  const size_t col_lds = xpost_base_bytes(pl->fs, sizeof(T) == 8);
   const size_t budget = col_lds + 1024 < 80 * 1024 ? 80 * 1024 - col_lds - 1024 : 0;
-  check_hip(pl, launch_fill<double>(pl->out_dev, total_vals, 0.0, s), "zero out");
-  check_hip(pl, hipEventRecord(pl->ev0, s), "event");
+  for (auto& gc : cc.groups) {
+    const int copies = (int)std::min<size_t>((size_t)waves, budget / (sizeof(double) * (size_t)std::max(1, gc.nv)));
+    gc.copies = std::max(1, copies);
+  }
+  cc.ell_max = ell_max;
+  cc.nb = nb;
+  cc.total_vals = total_vals;
+  cc.edges.assign(k_edges, k_edges + n_edges);
+}
+
+// Every group's pre-pass, y pass, post-pass and reduction into out_dev (zeroed first).
+template <typename T> void enqueue_compute(pkm_plan* pl) {
+  hipStream_t s = pl->stream;
+  const ComputeCfg& cc = pl->cc;
+  const int n = pl->p.nmesh;
+  check_hip(pl, launch_fill<double>(pl->out_dev, cc.total_vals, 0.0, s), "zero out");
   const bool dc_real = !(pl->p.interlaced || pl->p.compensated);
   const double off[3] = {pl->p.box_origin[0] - pl->p.observer[0], pl->p.box_origin[1] - pl->p.observer[1],
                          pl->p.box_origin[2] - pl->p.observer[2]};
   const double h = pl->p.box_len / n;
   const double dc_scale = 2.0 / ((double)n * n * n);
-  int nfields_total = 0;
-  for (size_t gi = 0; gi < groups.size(); ++gi) {
-    const int nf = (int)groups[gi].size();
-    nfields_total += nf;
-    const int* ft = pl->ftab_dev + 4 * fofs[gi];
-    const int* ftp = pl->ftab_dev + 4 * pofs[gi];
-    if (nf > 0) {
+  for (size_t gi = 0; gi < cc.groups.size(); ++gi) {
+    const GroupCfg& gc = cc.groups[gi];
+    const int* ft = pl->ftab_dev + 4 * gc.fofs;
+    const int* ftp = pl->ftab_dev + 4 * gc.pofs;
+    if (gc.nf > 0) {
       {
         StageScope ss(pl, PKM_STAGE_ZPRE);
-        check_hip(pl, launch_zpre<T>(pl->fs, pl->g, dc_real ? (const T*)pl->d1 : nullptr, nullptr, pl->ptrs_dev, nf,
-                                     ft, dc_scale, off, h, pl->ytab, pl->tw, s),
+        check_hip(pl, launch_zpre<T>(pl->fs, pl->g, dc_real ? (const T*)pl->d1 : nullptr, nullptr, pl->ptrs_dev,
+                                     gc.nf, ft, dc_scale, off, h, pl->ytab, pl->tw, s),
                   "zpre");
       }
       StageScope ss(pl, PKM_STAGE_YCOL);
-      check_hip(pl, launch_col<T>(pl->fs, pl->ptrs_dev, nf, 1, false, pl->tw, s), "field y pass");
+      check_hip(pl, launch_col<T>(pl->fs, pl->ptrs_dev, gc.nf, 1, false, pl->tw, s), "field y pass");
     }
-    const int nv = nvals_g[gi];
-    int copies = (int)std::min<size_t>((size_t)waves, budget / (sizeof(double) * (size_t)std::max(1, nv)));
-    copies = std::max(1, copies);
     int nblocks = 0;
     {
-    StageScope ss(pl, PKM_STAGE_XPOST);
-    check_hip(pl, launch_xpost<T>(pl->fs, pl->ptrs_dev, nf, ftp, nslots_g[gi], gi == 0 ? 1 : 0, pl->c, pl->ytab,
-                                  BinSpec{pl->thr_dev, nb, copies}, (double)(2.0 * M_PI / pl->p.box_len), pl->partial,
-                                  &nblocks, pl->tw, s),
-              "xpost");
+      StageScope ss(pl, PKM_STAGE_XPOST);
+      check_hip(pl, launch_xpost<T>(pl->fs, pl->ptrs_dev, gc.nf, ftp, gc.nslots, gi == 0 ? 1 : 0, pl->c, pl->ytab,
+                                    BinSpec{pl->thr_dev, cc.nb, gc.copies}, (double)(2.0 * M_PI / pl->p.box_len),
+                                    pl->partial, &nblocks, pl->tw, s),
+                "xpost");
     }
     StageScope ss(pl, PKM_STAGE_REDUCE);
-    check_hip(pl, launch_reduce(pl->partial, nblocks, nv, pl->out_dev, pl->map_dev + mofs[gi], 1, s), "reduce");
+    check_hip(pl, launch_reduce(pl->partial, nblocks, gc.nv, pl->out_dev, pl->map_dev + gc.mofs, 1, s), "reduce");
   }
+}
+
+// P_l, k_mean and mode counts from the reduced bin sums (FP64, host).
+void normalize(const pkm_plan* pl, const double* res, double norm_I, double shot, pkm_result* out) {
+  const ComputeCfg& cc = pl->cc;
+  const int nb = cc.nb;
+  for (int b = 0; b < nb; ++b) {
+    const double cnt = res[b];
+    if (out->n_modes) out->n_modes[b] = (int64_t)llround(cnt);
+    if (out->k_mean) out->k_mean[b] = cnt > 0 ? res[nb + b] / cnt : NAN;
+    if (out->poles) {
+      for (int il = 0; il <= cc.ell_max / 2; ++il) {
+        const double q = res[(2 + il) * nb + b];
+        double v = cnt > 0 ? q / (norm_I * cnt) : NAN;
+        if (il == 0) v -= shot;
+        out->poles[(size_t)il * nb + b] = v;
+      }
+    }
+  }
+  const int n_fwd = pl->p.interlaced ? 2 : 1;
+  const int n_inv = (pl->p.interlaced || pl->p.compensated) ? 1 : 0;
+  out->n_transforms = cc.nfields_total + n_fwd + n_inv;
+}
+
+template <typename T>
+void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, pkm_result* out) {
+  hipStream_t s = pl->stream;
+  prepare_compute<T>(pl, ell_max, k_edges, n_edges);
+  const ComputeCfg& cc = pl->cc;
+  check_hip(pl, hipEventRecord(pl->ev0, s), "event");
+  enqueue_compute<T>(pl);
   check_hip(pl, hipEventRecord(pl->ev1, s), "event");
-  std::vector<double> res(total_vals);
-  check_hip(pl, hipMemcpyAsync(res.data(), pl->out_dev, sizeof(double) * total_vals, hipMemcpyDeviceToHost, s),
+  std::vector<double> res(cc.total_vals);
+  check_hip(pl, hipMemcpyAsync(res.data(), pl->out_dev, sizeof(double) * cc.total_vals, hipMemcpyDeviceToHost, s),
             "download");
   check_hip(pl, hipStreamSynchronize(s), "sync");
   resolve_stages(pl);
   float ms = 0;
   (void)hipEventElapsedTime(&ms, pl->ev0, pl->ev1);
   pl->stats.ms_compute = ms;
-  pl->stats.n_groups = (int)groups.size();
+  pl->stats.n_groups = (int)cc.groups.size();
   const double X = (double)pl->mesh_bytes;
   pl->stats.model_bytes_compute = 0;
-  for (size_t gi = 0; gi < groups.size(); ++gi) {
-    const double nf = (double)groups[gi].size();
+  for (const GroupCfg& gc : cc.groups) {
+    const double nf = (double)gc.nf;
     pl->stats.model_bytes_compute += (nf > 0 ? X + nf * X : 0) + 2 * nf * X + nf * X + X;
   }
-  const int n_fwd = pl->p.interlaced ? 2 : 1;
-  const int n_inv = (pl->p.interlaced || pl->p.compensated) ? 1 : 0;
-  pl->n_transforms = nfields_total + n_fwd + n_inv;
-  pl->stats.n_transforms = pl->n_transforms;
-  // normalise (FP64, host)
-  for (int b = 0; b < nb; ++b) {
-    const double cnt = res[b];
-    if (out->n_modes) out->n_modes[b] = (int64_t)llround(cnt);
-    if (out->k_mean) out->k_mean[b] = cnt > 0 ? res[nb + b] / cnt : NAN;
-    if (out->poles) {
-      for (int il = 0; il <= ell_max / 2; ++il) {
-        const double q = res[(2 + il) * nb + b];
-        double v = cnt > 0 ? q / (pl->norm_I * cnt) : NAN;
-        if (il == 0) v -= pl->shot;
-        out->poles[(size_t)il * nb + b] = v;
-      }
-    }
-  }
+  normalize(pl, res.data(), pl->norm_I, pl->shot, out);
   out->alpha = pl->alpha;
   out->norm_I = pl->norm_I;
   out->shot_noise = pl->shot;
-  out->n_transforms = pl->n_transforms;
+  pl->n_transforms = out->n_transforms;
+  pl->stats.n_transforms = pl->n_transforms;
+}
+
+// Whole estimate (paint + multipoles) on device catalogs, results copied to a pinned host
+// slot of (4 + total_vals) doubles: the catalog sums, then the reduced bin sums.  Requires
+// prepare_compute and reserve_particles beforehand; allocates nothing and does not wait.
+template <typename T> void enqueue_estimate(pkm_plan* pl, const DevCats& dc, double* slot) {
+  hipStream_t s = pl->stream;
+  enqueue_paint<T>(pl, dc);
+  enqueue_compute<T>(pl);
+  check_hip(pl, hipMemcpyAsync(slot, pl->sums_dev, 4 * sizeof(double), hipMemcpyDeviceToHost, s), "download sums");
+  check_hip(pl, hipMemcpyAsync(slot + 4, pl->out_dev, sizeof(double) * pl->cc.total_vals, hipMemcpyDeviceToHost, s),
+            "download bins");
+}
+
+void finish_from_slot(const pkm_plan* pl, const double* slot, int64_t nd, int64_t nr, pkm_result* out) {
+  double alpha, norm_I, shot;
+  scalars_of(pl, slot, nd, nr, &alpha, &norm_I, &shot);
+  normalize(pl, slot + 4, norm_I, shot, out);
+  out->alpha = alpha;
+  out->norm_I = norm_I;
+  out->shot_noise = shot;
 }
 
 template <typename T>
@@ -690,6 +805,49 @@ template <typename T> void read_dc(pkm_plan* pl, void* host, size_t bytes) {
   check_hip(pl, e, "read D_c");
 }
 
+// Launch shape of the transform passes for one mesh size and precision.
+bool make_shape(const pkm_params& p, FftShape* out) {
+  FftShape fs{};
+  const int n = p.nmesh;
+  const bool fp64 = p.precision == PKM_FP64;
+  fs.n = n;
+  fs.e_col = pick_e(n);
+  fs.e_z = pick_e(n / 2);
+  // register budget: FP64 column passes and all z-line passes use at most 8 (or 12 / 6
+  // for lengths with a factor 3) elements per thread
+  if (fp64 && fs.e_col == 16) fs.e_col = 8;
+  if (fs.e_z == 16) fs.e_z = 8;
+  if (!fs.e_col || !fs.e_z || !make_sched(n, fs.e_col, &fs.sched_col, &fs.nst_col) ||
+      !make_sched(n / 2, fs.e_z, &fs.sched_z, &fs.nst_z)) {
+    return false;
+  }
+  // tile columns: 128-byte rows, at most 512 threads per column-pass block
+  fs.tile = fp64 ? 8 : 16;
+  const int pt_col = n / fs.e_col;
+  while (fs.tile > 1 && (pt_col * fs.tile > 512 || (n / 2) % fs.tile)) fs.tile /= 2;
+  // post-pass: at most 8 elements per thread (register budget of the fused recurrence)
+  fs.e_post = fs.e_col > 8 && fs.e_col % 8 == 0 ? 8 : fs.e_col;
+  if (fs.e_post == 12) fs.e_post = 6;
+  if (!make_sched(n, fs.e_post, &fs.sched_post, &fs.nst_post)) {
+    return false;
+  }
+  // 256-thread post-pass blocks (several resident per CU); narrow tiles share 128-byte rows
+  // through L2 because consecutive tiles run on the same XCD
+  {
+    const int pt_post = n / fs.e_post;
+    int tp = std::max(1, 256 / pt_post);
+    tp = std::min(tp, 16);
+    while (tp > 1 && (n / 2) % tp) tp /= 2;
+    fs.tile_post = tp;
+  }
+  const int pt_z = (n / 2) / fs.e_z;
+  int zl = 1;
+  while (zl * 2 * pt_z <= 256 && ((size_t)n * n) % (zl * 2) == 0) zl *= 2;
+  fs.zlines = zl;
+  *out = fs;
+  return true;
+}
+
 pkm_status validate_params(const pkm_params* p, std::string* why) {
   if (!p) { *why = "params is NULL"; return PKM_EINVAL; }
   if (!is_smooth(p->nmesh)) { *why = "nmesh must be 2^a 3^b with a >= 2 and 16 <= N <= 1024"; return PKM_EINVAL; }
@@ -742,14 +900,117 @@ void free_all(pkm_plan* pl) {
                     (void*)pl->map_dev, pl->tw, pl->ytab, pl->invw, pl->phase, (void*)pl->thr_dev, (void*)pl->partial,
                     (void*)pl->out_dev, (void*)pl->sums_dev, (void*)pl->cat_dev, (void*)pl->tile_count,
                     (void*)pl->tile_off, (void*)pl->tile_of, (void*)pl->tile_rank, pl->payload,
-                    (void*)pl->scan_sums})
+                    (void*)pl->scan_sums, (void*)pl->paint_ptrs})
     dfree(pl, ptr);
+  if (pl->slot) (void)hipHostFree(pl->slot);
+  if (pl->done) (void)hipEventDestroy(pl->done);
   for (hipEvent_t e : pl->ev_pool) (void)hipEventDestroy(e);
   if (pl->ev0) (void)hipEventDestroy(pl->ev0);
   if (pl->ev1) (void)hipEventDestroy(pl->ev1);
 }
 
+pkm_status validate_request(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges) {
+  if (!k_edges || n_edges < 2) { pl->err = "need k_edges (n_edges >= 2)"; return PKM_EINVAL; }
+  if (ell_max < 0 || ell_max > 16 || ell_max % 2) { pl->err = "ell_max must be even and in 0..16"; return PKM_EINVAL; }
+  for (int i = 0; i < n_edges; ++i) {
+    if (!(k_edges[i] >= 0.0) || !std::isfinite(k_edges[i])) { pl->err = "k edges must be finite and >= 0"; return PKM_EINVAL; }
+    if (i > 0 && !(k_edges[i] > k_edges[i - 1])) { pl->err = "k edges must be strictly increasing"; return PKM_EINVAL; }
+  }
+  return PKM_OK;
+}
+
+pkm_status validate_pair(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* randoms) {
+  std::string why;
+  if (validate_catalog(data, false, &why) != PKM_OK || (randoms && validate_catalog(randoms, true, &why) != PKM_OK)) {
+    pl->err = why;
+    return PKM_EINVAL;
+  }
+  if (data->n == 0) { pl->err = "data catalog is empty"; return PKM_EINVAL; }
+  if (randoms && randoms->n == 0) { pl->err = "random catalog is empty (pass NULL for a periodic box)"; return PKM_EINVAL; }
+  return PKM_OK;
+}
+
 }  // namespace
+
+// Internal entry points shared with the batch and serving runtime (runtime.hip).
+namespace pkm_internal {
+
+pkm_status prepare(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, int64_t max_particles) {
+  if (validate_request(pl, ell_max, k_edges, n_edges) != PKM_OK) return PKM_EINVAL;
+  if (max_particles < 1) { pl->err = "max_particles must be positive"; return PKM_EINVAL; }
+  if (pl->pending_async) { pl->err = "an enqueued estimate has not been finished"; return PKM_EBUSY; }
+  return guarded(pl, [&] {
+    check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
+    if (pl->fp64) prepare_compute<double>(pl, ell_max, k_edges, n_edges);
+    else prepare_compute<float>(pl, ell_max, k_edges, n_edges);
+    reserve_particles(pl, max_particles);
+    const size_t want = 4 + (size_t)pl->cc.total_vals;
+    if (pl->slot_cap < want) {
+      if (pl->slot) check_hip(pl, hipHostFree(pl->slot), "hipHostFree");
+      pl->slot = nullptr;
+      pl->slot_cap = 0;
+      check_hip(pl, hipHostMalloc((void**)&pl->slot, want * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
+      pl->slot_cap = want;
+    }
+    pl->stats.device_bytes = pl->bytes;
+  });
+}
+
+// Doubles of a result slot (catalog sums + bin sums) of the prepared request.
+size_t slot_doubles(const pkm_plan* pl) { return 4 + (size_t)pl->cc.total_vals; }
+bool prepared(const pkm_plan* pl) { return pl->cc.ell_max >= 0 && pl->sort_cap > 0; }
+hipStream_t stream_of(const pkm_plan* pl) { return pl->stream; }
+int device_of(const pkm_plan* pl) { return pl->dev.device_id; }
+int64_t device_bytes(const pkm_plan* pl) { return pl->bytes; }
+std::string& error_of(pkm_plan* pl) { return pl->err; }
+
+// Enqueue one estimate of device catalogs with its results copied to `slot` (pinned host,
+// slot_doubles(pl) doubles).  No allocation, no host wait: safe inside stream capture.
+pkm_status enqueue(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* randoms, double* slot) {
+  if (validate_pair(pl, data, randoms) != PKM_OK) return PKM_EINVAL;
+  if (!data->on_device || (randoms && !randoms->on_device)) {
+    pl->err = "asynchronous estimates take device-resident catalogs";
+    return PKM_EINVAL;
+  }
+  if (!prepared(pl)) { pl->err = "plan not prepared (pkm_prepare)"; return PKM_EORDER; }
+  if ((size_t)(data->n + (randoms ? randoms->n : 0)) > pl->sort_cap) {
+    pl->err = "particle count above the prepared capacity";
+    return PKM_EINVAL;
+  }
+  const bool timing = pl->stage_timing;
+  pl->stage_timing = false;
+  pkm_status st = guarded(pl, [&] {
+    DevCats dc;
+    dc.dp = data->pos; dc.dw = data->w; dc.dn = data->nbar; dc.nd = data->n;
+    if (randoms) { dc.rp = randoms->pos; dc.rw = randoms->w; dc.rn = randoms->nbar; dc.nr = randoms->n; }
+    if (pl->fp64) enqueue_estimate<double>(pl, dc, slot); else enqueue_estimate<float>(pl, dc, slot);
+  });
+  pl->stage_timing = timing;
+  if (st == PKM_OK) pl->painted = false;  // the resident fields now belong to the enqueued estimate
+  return st;
+}
+
+void finish(pkm_plan* pl, const double* slot, int64_t nd, int64_t nr, pkm_result* out) {
+  finish_from_slot(pl, slot, nd, nr, out);
+}
+
+int64_t footprint(const pkm_params* p, int ell_max, int n_edges, int64_t n_particles) {
+  FftShape fs{};
+  if (!make_shape(*p, &fs)) return -1;
+  const int64_t n = p->nmesh;
+  const int64_t mesh = (p->precision == PKM_FP64 ? 8 : 4) * n * n * n;
+  int nf = fields_for(std::max(ell_max, p->ell_max_hint == 0 ? 4 : p->ell_max_hint));
+  if (p->max_group > 0) nf = std::min(nf, p->max_group);
+  nf = std::max(nf, 1);
+  const int64_t meshes = (p->interlaced ? 6 : 4) + nf;
+  const int64_t nb = std::max(1, n_edges - 1);
+  const int64_t partial = (int64_t)post_blocks(fs) * (3 + ell_max / 2) * nb * 8;
+  const int64_t ts = 8;
+  const int64_t ntiles = (n / ts) * (n / ts) * (n / ts);
+  return meshes * mesh + 80 * n_particles + partial + 8 * ntiles + (4 << 20);
+}
+
+}  // namespace pkm_internal
 
 // -------------------------------------------------------------------------------------------
 // C ABI
@@ -786,43 +1047,10 @@ pkm_status pkm_plan_create(const pkm_params* p, const pkm_device* dev, pkm_plan*
   pl->es = pl->fp64 ? 8 : 4;
   const int n = p->nmesh;
   pl->mesh_bytes = pl->es * (size_t)n * n * n;
-  FftShape& fs = pl->fs;
-  fs.n = n;
-  fs.e_col = pick_e(n);
-  fs.e_z = pick_e(n / 2);
-  // register budget: FP64 column passes and all z-line passes use at most 8 (or 12 / 6
-  // for lengths with a factor 3) elements per thread
-  if (pl->fp64 && fs.e_col == 16) fs.e_col = 8;
-  if (fs.e_z == 16) fs.e_z = 8;
-  if (!fs.e_col || !fs.e_z || !make_sched(n, fs.e_col, &fs.sched_col, &fs.nst_col) ||
-      !make_sched(n / 2, fs.e_z, &fs.sched_z, &fs.nst_z)) {
+  if (!make_shape(*p, &pl->fs)) {
     delete pl;
     return PKM_EINVAL;
   }
-  // tile columns: 128-byte rows, at most 512 threads per column-pass block
-  fs.tile = pl->fp64 ? 8 : 16;
-  const int pt_col = n / fs.e_col;
-  while (fs.tile > 1 && (pt_col * fs.tile > 512 || (n / 2) % fs.tile)) fs.tile /= 2;
-  // post-pass: at most 8 elements per thread (register budget of the fused recurrence)
-  fs.e_post = fs.e_col > 8 && fs.e_col % 8 == 0 ? 8 : fs.e_col;
-  if (fs.e_post == 12) fs.e_post = 6;
-  if (!make_sched(n, fs.e_post, &fs.sched_post, &fs.nst_post)) {
-    delete pl;
-    return PKM_EINVAL;
-  }
-  // 256-thread post-pass blocks (several resident per CU); narrow tiles share 128-byte rows
-  // through L2 because consecutive tiles run on the same XCD
-  {
-    const int pt_post = n / fs.e_post;
-    int tp = std::max(1, 256 / pt_post);
-    tp = std::min(tp, 16);
-    while (tp > 1 && (n / 2) % tp) tp /= 2;
-    fs.tile_post = tp;
-  }
-  const int pt_z = (n / 2) / fs.e_z;
-  int zl = 1;
-  while (zl * 2 * pt_z <= 256 && ((size_t)n * n) % (zl * 2) == 0) zl *= 2;
-  fs.zlines = zl;
   st = guarded(pl, [&] {
     check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
     check_hip(pl, hipEventCreate(&pl->ev0), "event");
@@ -853,6 +1081,10 @@ pkm_status pkm_plan_create(const pkm_params* p, const pkm_device* dev, pkm_plan*
     ensure_fields(pl, std::max(want, 1));
     pl->ftab_dev = (int*)dalloc(pl, sizeof(int) * 4 * 64);
     pl->ftab_cap = 4 * 64;
+    pl->paint_ptrs = (void**)dalloc(pl, sizeof(void*) * 3);
+    void* pp[3] = {pl->s1, pl->s2, pl->g};
+    check_hip(pl, hipMemcpy(pl->paint_ptrs, pp, sizeof pp, hipMemcpyHostToDevice), "upload paint pointers");
+    check_hip(pl, hipEventCreateWithFlags(&pl->done, hipEventDisableTiming), "event");
     if (pl->fp64) upload_tables<double>(pl); else upload_tables<float>(pl);
   });
   if (st != PKM_OK) {
@@ -880,6 +1112,7 @@ pkm_status pkm_paint(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* r
     pl->err = "random catalog is empty (pass NULL for a periodic box)";
     return PKM_EINVAL;
   }
+  if (pl->pending_async) { pl->err = "an enqueued estimate has not been finished"; return PKM_EBUSY; }
   pl->painted = false;
   pkm_status st = guarded(pl, [&] {
     check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
@@ -892,18 +1125,12 @@ pkm_status pkm_paint(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* r
 pkm_status pkm_compute_multipoles(pkm_plan* pl, int32_t ell_max, const double* k_edges, int32_t n_edges,
                                   pkm_result* out) {
   if (!pl) return PKM_EINVAL;
-  if (!out || !k_edges || n_edges < 2) { pl->err = "need k_edges (n_edges >= 2) and a result"; return PKM_EINVAL; }
-  if (ell_max < 0 || ell_max > 16 || ell_max % 2) { pl->err = "ell_max must be even and in 0..16"; return PKM_EINVAL; }
-  for (int i = 0; i < n_edges; ++i) {
-    if (!(k_edges[i] >= 0.0) || !std::isfinite(k_edges[i])) { pl->err = "k edges must be finite and >= 0"; return PKM_EINVAL; }
-    if (i > 0 && !(k_edges[i] > k_edges[i - 1])) { pl->err = "k edges must be strictly increasing"; return PKM_EINVAL; }
-  }
+  if (!out) { pl->err = "need a result"; return PKM_EINVAL; }
+  if (validate_request(pl, ell_max, k_edges, n_edges) != PKM_OK) return PKM_EINVAL;
+  if (pl->pending_async) { pl->err = "an enqueued estimate has not been finished"; return PKM_EBUSY; }
   if (!pl->painted) { pl->err = "pkm_paint must succeed before pkm_compute_multipoles"; return PKM_EORDER; }
   pkm_status st = guarded(pl, [&] {
     check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
-    const int need = fields_for(ell_max);
-    if ((int)pl->fields.size() < need && (pl->p.max_group <= 0 || (int)pl->fields.size() < pl->p.max_group))
-      ensure_fields(pl, pl->p.max_group > 0 ? std::min(need, pl->p.max_group) : need);
     if (pl->fp64) run_compute<double>(pl, ell_max, k_edges, n_edges, out);
     else run_compute<float>(pl, ell_max, k_edges, n_edges, out);
   });
@@ -998,6 +1225,54 @@ pkm_status pkm_plan_read_buffer(pkm_plan* pl, int32_t which, void* host, size_t 
     else if (pl->fp64) read_dc<double>(pl, host, bytes);
     else read_dc<float>(pl, host, bytes);
   });
+}
+
+pkm_status pkm_prepare(pkm_plan* pl, int32_t ell_max, const double* k_edges, int32_t n_edges,
+                       int64_t max_particles) {
+  if (!pl) return PKM_EINVAL;
+  return pkm_internal::prepare(pl, ell_max, k_edges, n_edges, max_particles);
+}
+
+pkm_status pkm_enqueue(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* randoms) {
+  if (!pl) return PKM_EINVAL;
+  if (pl->pending_async) { pl->err = "the previous enqueued estimate has not been finished"; return PKM_EBUSY; }
+  if (!data) { pl->err = "data catalog is NULL"; return PKM_EINVAL; }
+  pkm_status st = guarded(pl, [&] { check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice"); });
+  if (st != PKM_OK) return st;
+  st = pkm_internal::enqueue(pl, data, randoms, pl->slot);
+  if (st != PKM_OK) return st;
+  st = guarded(pl, [&] { check_hip(pl, hipEventRecord(pl->done, pl->stream), "event"); });
+  if (st != PKM_OK) return st;
+  pl->pend_nd = data->n;
+  pl->pend_nr = randoms ? randoms->n : 0;
+  pl->pending_async = true;
+  return PKM_OK;
+}
+
+pkm_status pkm_query(pkm_plan* pl) {
+  if (!pl) return PKM_EINVAL;
+  if (!pl->pending_async) { pl->err = "nothing enqueued"; return PKM_EORDER; }
+  const hipError_t e = hipEventQuery(pl->done);
+  if (e == hipSuccess) return PKM_OK;
+  if (e == hipErrorNotReady) return PKM_EBUSY;
+  pl->err = std::string("event query failed: ") + hipGetErrorString(e);
+  return PKM_EDEVICE;
+}
+
+pkm_status pkm_finish(pkm_plan* pl, pkm_result* out) {
+  if (!pl) return PKM_EINVAL;
+  if (!out) { pl->err = "need a result"; return PKM_EINVAL; }
+  if (!pl->pending_async) { pl->err = "nothing enqueued"; return PKM_EORDER; }
+  pkm_status st = guarded(pl, [&] { check_hip(pl, hipEventSynchronize(pl->done), "event synchronize"); });
+  pl->pending_async = false;
+  if (st != PKM_OK) return st;
+  finish_from_slot(pl, pl->slot, pl->pend_nd, pl->pend_nr, out);
+  pl->alpha = out->alpha;
+  pl->norm_I = out->norm_I;
+  pl->shot = out->shot_noise;
+  pl->n_transforms = out->n_transforms;
+  pl->painted = true;
+  return PKM_OK;
 }
 
 }  // extern "C"

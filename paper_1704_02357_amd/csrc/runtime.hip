@@ -1,0 +1,748 @@
+// Batching and serving runtime over the plan's asynchronous estimate (include/pkm.h).
+//
+// Batch: many estimates (mocks of uneven mesh size, each with all its (l, m) fields) issued
+// as one unit.  Estimates on distinct plans run on the plans' own streams and overlap on
+// the device; estimates sharing a plan run in order on its stream.  The whole issue sequence
+// can be captured once into a HIP graph (fork/join over the plans' streams) and replayed
+// with one launch.
+//
+// Server: a request loop that admits multipole requests of different sizes and l_max as
+// they arrive, by HBM footprint and a cap on concurrent estimates, keeps plans (meshes and
+// tables) resident for reuse, overlaps the admitted estimates on separate streams, and
+// records per-request latency.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/pkm.h"
+#include "internal.hpp"
+
+namespace {
+
+struct PinnedBuf {
+  double* p = nullptr;
+  size_t n = 0;
+  PinnedBuf() = default;
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  ~PinnedBuf() { release(); }
+  hipError_t resize(size_t count) {
+    if (count <= n) return hipSuccess;
+    release();
+    hipError_t e = hipHostMalloc((void**)&p, std::max<size_t>(count, 1) * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) n = count;
+    else p = nullptr;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+}  // namespace
+
+// ===========================================================================================
+// Batch
+// ===========================================================================================
+struct BatchItem {
+  pkm_plan* plan = nullptr;
+  pkm_catalog data{}, rand{};
+  bool has_rand = false;
+  std::unique_ptr<PinnedBuf> slot;
+};
+
+struct pkm_batch {
+  int device = 0;
+  hipStream_t origin = nullptr;
+  std::vector<BatchItem> items;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t fork = nullptr, t0 = nullptr, t1 = nullptr;
+  std::vector<hipEvent_t> joins;
+  bool ran = false;
+  std::string err;
+};
+
+namespace {
+
+pkm_status hip_fail(pkm_batch* b, hipError_t e, const char* what) {
+  b->err = std::string(what) + " failed: " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? PKM_ENOMEM : PKM_EDEVICE;
+}
+
+void drop_graph(pkm_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// Distinct plan streams of the batch, in first-use order.
+std::vector<hipStream_t> batch_streams(const pkm_batch* b) {
+  std::vector<hipStream_t> v;
+  for (const auto& it : b->items) {
+    hipStream_t s = pkm_internal::stream_of(it.plan);
+    if (std::find(v.begin(), v.end(), s) == v.end()) v.push_back(s);
+  }
+  return v;
+}
+
+// Fork from origin, every item on its plan's stream, join back on origin.
+pkm_status issue(pkm_batch* b) {
+  const auto streams = batch_streams(b);
+  hipError_t e = hipEventRecord(b->fork, b->origin);
+  if (e != hipSuccess) return hip_fail(b, e, "fork event");
+  for (hipStream_t s : streams)
+    if ((e = hipStreamWaitEvent(s, b->fork, 0)) != hipSuccess) return hip_fail(b, e, "stream wait");
+  for (size_t i = 0; i < b->items.size(); ++i) {
+    BatchItem& it = b->items[i];
+    const pkm_status st = pkm_internal::enqueue(it.plan, &it.data, it.has_rand ? &it.rand : nullptr, it.slot->p);
+    if (st != PKM_OK) {
+      b->err = "item " + std::to_string(i) + ": " + pkm_internal::error_of(it.plan);
+      return st;
+    }
+  }
+  while (b->joins.size() < streams.size()) {
+    hipEvent_t ev;
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return hip_fail(b, e, "event");
+    b->joins.push_back(ev);
+  }
+  for (size_t k = 0; k < streams.size(); ++k) {
+    if ((e = hipEventRecord(b->joins[k], streams[k])) != hipSuccess) return hip_fail(b, e, "join event");
+    if ((e = hipStreamWaitEvent(b->origin, b->joins[k], 0)) != hipSuccess) return hip_fail(b, e, "join wait");
+  }
+  return PKM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pkm_status pkm_batch_create(int32_t device_id, pkm_batch** out) {
+  if (!out) return PKM_EINVAL;
+  pkm_batch* b = new (std::nothrow) pkm_batch();
+  if (!b) return PKM_ENOMEM;
+  b->device = device_id;
+  hipError_t e = hipSetDevice(device_id);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreate(&b->t0);
+  if (e == hipSuccess) e = hipEventCreate(&b->t1);
+  if (e != hipSuccess) {
+    pkm_batch_destroy(b);
+    return e == hipErrorOutOfMemory ? PKM_ENOMEM : PKM_EDEVICE;
+  }
+  *out = b;
+  return PKM_OK;
+}
+
+pkm_status pkm_batch_add(pkm_batch* b, pkm_plan* plan, const pkm_catalog* data, const pkm_catalog* randoms,
+                         int32_t* index_out) {
+  if (!b) return PKM_EINVAL;
+  if (!plan || !data) { b->err = "need a plan and a data catalog"; return PKM_EINVAL; }
+  if (!pkm_internal::prepared(plan)) { b->err = "plan not prepared (pkm_prepare)"; return PKM_EORDER; }
+  if (pkm_internal::device_of(plan) != b->device) { b->err = "plan lives on another device"; return PKM_EINVAL; }
+  if (pkm_internal::stream_of(plan) == nullptr) {
+    b->err = "batched plans need their own stream (not the null stream)";
+    return PKM_EINVAL;
+  }
+  if (!data->on_device || (randoms && !randoms->on_device)) {
+    b->err = "batched estimates take device-resident catalogs";
+    return PKM_EINVAL;
+  }
+  BatchItem it;
+  it.plan = plan;
+  it.data = *data;
+  if (randoms) { it.rand = *randoms; it.has_rand = true; }
+  it.slot.reset(new (std::nothrow) PinnedBuf());
+  if (!it.slot) return PKM_ENOMEM;
+  (void)hipSetDevice(b->device);
+  hipError_t e = it.slot->resize(pkm_internal::slot_doubles(plan));
+  if (e != hipSuccess) return hip_fail(b, e, "hipHostMalloc");
+  b->items.push_back(std::move(it));
+  drop_graph(b);
+  b->ran = false;
+  if (index_out) *index_out = (int32_t)(b->items.size() - 1);
+  return PKM_OK;
+}
+
+pkm_status pkm_batch_run(pkm_batch* b, int32_t use_graph, double* ms_out) {
+  if (!b) return PKM_EINVAL;
+  if (b->items.empty()) { b->err = "empty batch"; return PKM_EINVAL; }
+  hipError_t e = hipSetDevice(b->device);
+  if (e != hipSuccess) return hip_fail(b, e, "hipSetDevice");
+  b->ran = false;
+  if (use_graph && !b->exec) {
+    if ((e = hipStreamBeginCapture(b->origin, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_fail(b, e, "begin capture");
+    const pkm_status st = issue(b);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(b->origin, &g);
+    if (st != PKM_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e2 != hipSuccess) return hip_fail(b, e2, "end capture");
+    b->graph = g;
+    if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) {
+      drop_graph(b);
+      return hip_fail(b, e, "graph instantiate");
+    }
+  }
+  if ((e = hipEventRecord(b->t0, b->origin)) != hipSuccess) return hip_fail(b, e, "event");
+  if (use_graph) {
+    if ((e = hipGraphLaunch(b->exec, b->origin)) != hipSuccess) return hip_fail(b, e, "graph launch");
+  } else {
+    const pkm_status st = issue(b);
+    if (st != PKM_OK) return st;
+  }
+  if ((e = hipEventRecord(b->t1, b->origin)) != hipSuccess) return hip_fail(b, e, "event");
+  if ((e = hipStreamSynchronize(b->origin)) != hipSuccess) return hip_fail(b, e, "synchronize");
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, b->t0, b->t1);
+  if (ms_out) *ms_out = ms;
+  b->ran = true;
+  return PKM_OK;
+}
+
+pkm_status pkm_batch_result(pkm_batch* b, int32_t index, pkm_result* out) {
+  if (!b) return PKM_EINVAL;
+  if (!out || index < 0 || (size_t)index >= b->items.size()) { b->err = "bad index or result"; return PKM_EINVAL; }
+  if (!b->ran) { b->err = "batch has not run since its last change"; return PKM_EORDER; }
+  BatchItem& it = b->items[index];
+  pkm_internal::finish(it.plan, it.slot->p, it.data.n, it.has_rand ? it.rand.n : 0, out);
+  return PKM_OK;
+}
+
+int32_t pkm_batch_size(const pkm_batch* b) { return b ? (int32_t)b->items.size() : 0; }
+
+const char* pkm_batch_last_error(const pkm_batch* b) { return b ? b->err.c_str() : "no batch"; }
+
+void pkm_batch_destroy(pkm_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  if (b->origin) (void)hipStreamSynchronize(b->origin);
+  drop_graph(b);
+  for (hipEvent_t ev : b->joins) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : {b->fork, b->t0, b->t1})
+    if (ev) (void)hipEventDestroy(ev);
+  b->items.clear();
+  if (b->origin) (void)hipStreamDestroy(b->origin);
+  delete b;
+}
+
+}  // extern "C"
+
+// ===========================================================================================
+// Server
+// ===========================================================================================
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// Plans are interchangeable when these parameters agree (l_max only sizes the buffers).
+struct PlanKey {
+  pkm_params p;
+  bool operator<(const PlanKey& o) const { return std::memcmp(&p, &o.p, sizeof(pkm_params)) < 0; }
+};
+
+PlanKey key_of(const pkm_params& p) {
+  PlanKey k;
+  std::memset(&k.p, 0, sizeof(k.p));
+  k.p.nmesh = p.nmesh;
+  k.p.box_len = p.box_len;
+  for (int a = 0; a < 3; ++a) {
+    k.p.box_origin[a] = p.box_origin[a];
+    k.p.observer[a] = p.observer[a];
+  }
+  k.p.window = p.window;
+  k.p.interlaced = p.interlaced;
+  k.p.compensated = p.compensated;
+  k.p.precision = p.precision;
+  k.p.max_group = p.max_group;
+  return k;  // ell_max_hint excluded: a slot serves any l_max up to its own hint
+}
+
+// One resident plan with its stream and grow-only staging buffers (device frees and pinned
+// host frees synchronise the device, so they are avoided on the request path).
+struct Slot {
+  pkm_plan* plan = nullptr;
+  hipStream_t stream = nullptr;
+  PlanKey key;
+  int hint = 0;            // largest l_max the plan's field buffers were sized for
+  int64_t bytes = 0;       // plan bytes + catalog buffer
+  bool busy = false;
+  Clock::time_point last_used;
+  PinnedBuf stage;         // host catalog staging
+  PinnedBuf result;        // bin sums of the estimate in flight
+  double* dev_cat = nullptr;
+  size_t dev_cap = 0;      // doubles
+};
+
+struct Request {
+  int64_t ticket = 0;
+  pkm_params params{};
+  int ell_max = 0;
+  std::vector<double> edges;
+  int64_t nd = 0, nr = 0;
+  bool has_rand = false;
+  std::vector<double> host_cat;  // pos, w, nbar of data then randoms (copied at submit)
+  bool dw = false, dn = false, rw = false;
+  int64_t need = 0;
+  Slot* slot_plan = nullptr;
+  hipEvent_t done = nullptr;
+  Clock::time_point t_submit, t_done;
+  // result
+  pkm_status status = PKM_OK;
+  std::string err;
+  std::vector<double> poles, kmean;
+  std::vector<int64_t> nmodes;
+  double alpha = 0, norm_I = 0, shot = 0;
+  int n_transforms = 0;
+};
+
+}  // namespace
+
+struct pkm_server {
+  pkm_server_config cfg{};
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::vector<std::shared_ptr<Request>> inflight;
+  std::unordered_map<int64_t, std::shared_ptr<Request>> finished;
+  std::vector<std::unique_ptr<Slot>> slots;
+  int64_t next_ticket = 1;
+  int64_t resident = 0, peak_resident = 0;
+  int max_concurrent = 0;
+  std::vector<double> latencies_ms;
+  int64_t completed = 0, failed = 0;
+  Clock::time_point t_first_submit, t_last_done;
+  bool any_submit = false;
+  bool stop = false;
+  std::thread worker;
+  std::string err;
+};
+
+namespace {
+
+void free_slot(pkm_server* sv, Slot* s) {
+  pkm_plan_destroy(s->plan);
+  if (s->dev_cat) (void)hipFree(s->dev_cat);
+  s->stage.release();
+  s->result.release();
+  (void)hipStreamDestroy(s->stream);
+  sv->resident -= s->bytes;
+}
+
+// Copy the request's catalog through the slot's pinned staging to its device buffer.
+pkm_status stage_request(Request* r, Slot* sl) {
+  const size_t total = r->host_cat.size();
+  if (sl->dev_cap < total) {
+    if (sl->dev_cat) (void)hipFree(sl->dev_cat);
+    sl->dev_cat = nullptr;
+    sl->dev_cap = 0;
+    if (hipMalloc((void**)&sl->dev_cat, total * sizeof(double)) != hipSuccess) {
+      sl->dev_cat = nullptr;
+      r->err = "catalog allocation failed";
+      return PKM_ENOMEM;
+    }
+    sl->dev_cap = total;
+  }
+  if (sl->stage.resize(total) != hipSuccess) { r->err = "pinned staging allocation failed"; return PKM_ENOMEM; }
+  std::memcpy(sl->stage.p, r->host_cat.data(), total * sizeof(double));
+  const hipError_t e = hipMemcpyAsync(sl->dev_cat, sl->stage.p, total * sizeof(double), hipMemcpyHostToDevice,
+                                      sl->stream);
+  if (e != hipSuccess) { r->err = hipGetErrorString(e); return PKM_EDEVICE; }
+  return PKM_OK;
+}
+
+void catalogs_of(const Request* r, const Slot* sl, pkm_catalog* d, pkm_catalog* rr) {
+  const double* p = sl->dev_cat;
+  d->pos = p; p += 3 * r->nd;
+  d->w = r->dw ? p : nullptr; if (r->dw) p += r->nd;
+  d->nbar = r->dn ? p : nullptr; if (r->dn) p += r->nd;
+  d->n = r->nd;
+  d->on_device = 1;
+  if (r->has_rand) {
+    rr->pos = p; p += 3 * r->nr;
+    rr->w = r->rw ? p : nullptr; if (r->rw) p += r->nr;
+    rr->nbar = p;
+    rr->n = r->nr;
+    rr->on_device = 1;
+  }
+}
+
+void complete(pkm_server* sv, std::shared_ptr<Request> r, pkm_status st) {
+  r->status = st;
+  r->t_done = Clock::now();
+  if (r->done) (void)hipEventDestroy(r->done);
+  r->done = nullptr;
+  std::vector<double>().swap(r->host_cat);
+  if (r->slot_plan) {
+    r->slot_plan->busy = false;
+    r->slot_plan->last_used = r->t_done;
+    r->slot_plan = nullptr;
+  }
+  if (st == PKM_OK) {
+    sv->latencies_ms.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
+    ++sv->completed;
+  } else {
+    ++sv->failed;
+  }
+  sv->t_last_done = r->t_done;
+  sv->finished[r->ticket] = r;
+}
+
+// Try to start the request at the head of the queue.  Returns false when it must wait.
+bool admit_head(pkm_server* sv, std::unique_lock<std::mutex>& lk) {
+  if (sv->queue.empty() || (int)sv->inflight.size() >= sv->cfg.max_inflight) return false;
+  std::shared_ptr<Request> r = sv->queue.front();
+  const PlanKey key = key_of(r->params);
+  Slot* use = nullptr;
+  const int hint = std::max(r->ell_max, r->params.ell_max_hint);
+  for (auto& s : sv->slots)
+    if (!s->busy && s->hint >= r->ell_max && !(s->key < key) && !(key < s->key)) { use = s.get(); break; }
+  const int64_t cat_bytes = (int64_t)r->host_cat.size() * 8;
+  int64_t need = use ? std::max<int64_t>(0, cat_bytes - (int64_t)use->dev_cap * 8) : r->need + cat_bytes;
+  // evict idle plans (least recently used first) until the request fits
+  while (sv->resident + need > sv->cfg.hbm_budget_bytes) {
+    Slot* victim = nullptr;
+    for (auto& s : sv->slots)
+      if (!s->busy && s.get() != use && (!victim || s->last_used < victim->last_used)) victim = s.get();
+    if (!victim) break;
+    free_slot(sv, victim);
+    sv->slots.erase(std::find_if(sv->slots.begin(), sv->slots.end(), [&](auto& p) { return p.get() == victim; }));
+  }
+  if (sv->resident + need > sv->cfg.hbm_budget_bytes) {
+    if (sv->inflight.empty()) {  // can never fit
+      sv->queue.pop_front();
+      r->err = "request footprint above the server's HBM budget";
+      complete(sv, r, PKM_ENOMEM);
+      sv->cv_done.notify_all();
+      return true;
+    }
+    return false;  // wait for a completion to free memory
+  }
+  sv->queue.pop_front();
+  lk.unlock();  // device work below; the client side only touches the queue and results
+  pkm_status st = PKM_OK;
+  if (!use) {
+    auto s = std::make_unique<Slot>();
+    s->key = key;
+    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) st = PKM_EDEVICE;
+    if (st == PKM_OK) {
+      pkm_device dev{};
+      dev.device_id = sv->cfg.device_id;
+      dev.hip_stream = s->stream;
+      pkm_params pp = key.p;
+      pp.ell_max_hint = hint;
+      s->hint = hint;
+      st = pkm_plan_create(&pp, &dev, &s->plan);
+      if (st != PKM_OK) {
+        r->err = "plan creation failed";
+        (void)hipStreamDestroy(s->stream);
+      }
+    }
+    if (st == PKM_OK) {
+      use = s.get();
+      lk.lock();
+      sv->slots.push_back(std::move(s));
+      lk.unlock();
+    }
+  }
+  if (st == PKM_OK) {
+    use->busy = true;
+    r->slot_plan = use;
+    st = pkm_internal::prepare(use->plan, r->ell_max, r->edges.data(), (int)r->edges.size(), r->nd + r->nr);
+    if (st != PKM_OK) r->err = pkm_internal::error_of(use->plan);
+  }
+  if (st == PKM_OK && use->result.resize(pkm_internal::slot_doubles(use->plan)) != hipSuccess) st = PKM_ENOMEM;
+  if (st == PKM_OK) st = stage_request(r.get(), use);
+  if (st == PKM_OK) {
+    pkm_catalog d{}, rr{};
+    catalogs_of(r.get(), use, &d, &rr);
+    st = pkm_internal::enqueue(use->plan, &d, r->has_rand ? &rr : nullptr, use->result.p);
+    if (st != PKM_OK) r->err = pkm_internal::error_of(use->plan);
+  }
+  if (st == PKM_OK && (hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess ||
+                       hipEventRecord(r->done, use->stream) != hipSuccess))
+    st = PKM_EDEVICE;
+  lk.lock();
+  if (use) {
+    const int64_t b = pkm_internal::device_bytes(use->plan) + (int64_t)use->dev_cap * 8;
+    sv->resident += b - use->bytes;
+    use->bytes = b;
+  }
+  sv->peak_resident = std::max(sv->peak_resident, sv->resident);
+  if (st != PKM_OK) {
+    complete(sv, r, st);
+    sv->cv_done.notify_all();
+    return true;
+  }
+  sv->inflight.push_back(r);
+  sv->max_concurrent = std::max(sv->max_concurrent, (int)sv->inflight.size());
+  return true;
+}
+
+void reap(pkm_server* sv, std::unique_lock<std::mutex>& lk) {
+  for (size_t i = 0; i < sv->inflight.size();) {
+    std::shared_ptr<Request> r = sv->inflight[i];
+    const hipError_t e = hipEventQuery(r->done);
+    if (e == hipErrorNotReady) { ++i; continue; }
+    sv->inflight.erase(sv->inflight.begin() + i);
+    pkm_status st = PKM_OK;
+    if (e != hipSuccess) {
+      r->err = hipGetErrorString(e);
+      st = PKM_EDEVICE;
+    } else {
+      const int nb = (int)r->edges.size() - 1;
+      r->poles.assign((size_t)(r->ell_max / 2 + 1) * nb, 0.0);
+      r->kmean.assign(nb, 0.0);
+      r->nmodes.assign(nb, 0);
+      pkm_result res{};
+      res.poles = r->poles.data();
+      res.k_mean = r->kmean.data();
+      res.n_modes = r->nmodes.data();
+      pkm_internal::finish(r->slot_plan->plan, r->slot_plan->result.p, r->nd, r->nr, &res);
+      r->alpha = res.alpha;
+      r->norm_I = res.norm_I;
+      r->shot = res.shot_noise;
+      r->n_transforms = res.n_transforms;
+    }
+    complete(sv, r, st);
+    sv->cv_done.notify_all();
+  }
+  (void)lk;
+}
+
+void worker_loop(pkm_server* sv) {
+  (void)hipSetDevice(sv->cfg.device_id);
+  std::unique_lock<std::mutex> lk(sv->mu);
+  while (true) {
+    if (sv->stop && sv->inflight.empty()) break;
+    reap(sv, lk);
+    bool progressed = false;
+    while (!sv->stop && admit_head(sv, lk)) progressed = true;
+    if (sv->inflight.empty() && sv->queue.empty()) {
+      if (sv->stop) break;
+      sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
+      continue;
+    }
+    if (!progressed) {
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(50));
+      lk.lock();
+    }
+  }
+  // cancel what never started
+  while (!sv->queue.empty()) {
+    auto r = sv->queue.front();
+    sv->queue.pop_front();
+    r->err = "server stopped";
+    complete(sv, r, PKM_ECANCELLED);
+  }
+  sv->cv_done.notify_all();
+}
+
+pkm_status copy_out(const Request& r, pkm_result* out) {
+  if (r.status != PKM_OK) return r.status;
+  if (out->poles) std::copy(r.poles.begin(), r.poles.end(), out->poles);
+  if (out->k_mean) std::copy(r.kmean.begin(), r.kmean.end(), out->k_mean);
+  if (out->n_modes) std::copy(r.nmodes.begin(), r.nmodes.end(), out->n_modes);
+  out->alpha = r.alpha;
+  out->norm_I = r.norm_I;
+  out->shot_noise = r.shot;
+  out->n_transforms = r.n_transforms;
+  return PKM_OK;
+}
+
+double percentile(std::vector<double> v, double q) {
+  if (v.empty()) return 0.0;
+  std::sort(v.begin(), v.end());
+  const double pos = q * (double)(v.size() - 1);
+  const size_t lo = (size_t)pos;
+  const size_t hi = std::min(lo + 1, v.size() - 1);
+  return v[lo] + (pos - (double)lo) * (v[hi] - v[lo]);
+}
+
+}  // namespace
+
+extern "C" {
+
+pkm_status pkm_server_create(const pkm_server_config* cfg, pkm_server** out) {
+  if (!cfg || !out) return PKM_EINVAL;
+  if (cfg->max_inflight < 1 || cfg->max_inflight > 32) return PKM_EINVAL;
+  pkm_server* sv = new (std::nothrow) pkm_server();
+  if (!sv) return PKM_ENOMEM;
+  sv->cfg = *cfg;
+  if (hipSetDevice(cfg->device_id) != hipSuccess) {
+    delete sv;
+    return PKM_EDEVICE;
+  }
+  if (sv->cfg.hbm_budget_bytes <= 0) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+      delete sv;
+      return PKM_EDEVICE;
+    }
+    sv->cfg.hbm_budget_bytes = (int64_t)(0.8 * (double)free_b);
+  }
+  try {
+    sv->worker = std::thread(worker_loop, sv);
+  } catch (...) {
+    delete sv;
+    return PKM_ENOMEM;
+  }
+  *out = sv;
+  return PKM_OK;
+}
+
+pkm_status pkm_server_submit(pkm_server* sv, const pkm_request* rq, int64_t* ticket) {
+  if (!sv || !rq || !ticket) return PKM_EINVAL;
+  // validate what can be checked on the host
+  if (!rq->data.pos || rq->data.n <= 0 || rq->data.on_device) {
+    sv->err = "requests take a non-empty host data catalog";
+    return PKM_EINVAL;
+  }
+  if (rq->has_randoms && (!rq->randoms.pos || !rq->randoms.nbar || rq->randoms.n <= 0 || rq->randoms.on_device)) {
+    sv->err = "randoms need host positions and nbar and n > 0";
+    return PKM_EINVAL;
+  }
+  if (!rq->k_edges || rq->n_edges < 2 || rq->ell_max < 0 || rq->ell_max > 16 || rq->ell_max % 2) {
+    sv->err = "need even ell_max in 0..16 and at least two k edges";
+    return PKM_EINVAL;
+  }
+  auto r = std::make_shared<Request>();
+  r->params = rq->params;
+  r->ell_max = rq->ell_max;
+  r->edges.assign(rq->k_edges, rq->k_edges + rq->n_edges);
+  r->nd = rq->data.n;
+  r->has_rand = rq->has_randoms != 0;
+  r->nr = r->has_rand ? rq->randoms.n : 0;
+  r->dw = rq->data.w != nullptr;
+  r->dn = rq->data.nbar != nullptr;
+  r->rw = r->has_rand && rq->randoms.w != nullptr;
+  const size_t total = (size_t)r->nd * (3 + r->dw + r->dn) + (size_t)r->nr * (3 + r->rw + (r->has_rand ? 1 : 0));
+  r->need = pkm_internal::footprint(&rq->params, rq->ell_max, rq->n_edges, r->nd + r->nr);
+  if (r->need < 0) { sv->err = "invalid mesh parameters"; return PKM_EINVAL; }
+  if (rq->params.max_group == 0 && r->need > sv->cfg.hbm_budget_bytes / 2) {
+    // keep fewer weighted fields resident at once (field groups run one after another)
+    for (int g = 64; g >= 1; g /= 2) {
+      r->params.max_group = g;
+      r->need = pkm_internal::footprint(&r->params, rq->ell_max, rq->n_edges, r->nd + r->nr);
+      if (r->need <= sv->cfg.hbm_budget_bytes / 2) break;
+    }
+  }
+  {
+    // host copy so the caller may release its arrays after submit
+    try {
+      r->host_cat.resize(total);
+    } catch (...) {
+      return PKM_ENOMEM;
+    }
+    double* p = r->host_cat.data();
+    auto put = [&](const double* src, size_t count) { std::memcpy(p, src, count * sizeof(double)); p += count; };
+    put(rq->data.pos, 3 * (size_t)r->nd);
+    if (r->dw) put(rq->data.w, r->nd);
+    if (r->dn) put(rq->data.nbar, r->nd);
+    if (r->has_rand) {
+      put(rq->randoms.pos, 3 * (size_t)r->nr);
+      if (r->rw) put(rq->randoms.w, r->nr);
+      put(rq->randoms.nbar, r->nr);
+    }
+  }
+  std::lock_guard<std::mutex> g(sv->mu);
+  if (sv->stop) return PKM_ECANCELLED;
+  r->ticket = sv->next_ticket++;
+  r->t_submit = Clock::now();
+  if (!sv->any_submit) { sv->t_first_submit = r->t_submit; sv->any_submit = true; }
+  sv->queue.push_back(r);
+  *ticket = r->ticket;
+  sv->cv_work.notify_one();
+  return PKM_OK;
+}
+
+pkm_status pkm_server_poll(pkm_server* sv, int64_t ticket, pkm_result* out) {
+  if (!sv || !out) return PKM_EINVAL;
+  std::lock_guard<std::mutex> g(sv->mu);
+  auto it = sv->finished.find(ticket);
+  if (it == sv->finished.end()) {
+    if (ticket <= 0 || ticket >= sv->next_ticket) { sv->err = "unknown ticket"; return PKM_EINVAL; }
+    return PKM_EBUSY;
+  }
+  std::shared_ptr<Request> r = it->second;
+  sv->finished.erase(it);
+  if (r->status != PKM_OK) sv->err = r->err;
+  return copy_out(*r, out);
+}
+
+pkm_status pkm_server_wait(pkm_server* sv, int64_t ticket, pkm_result* out) {
+  if (!sv || !out) return PKM_EINVAL;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  if (ticket <= 0 || ticket >= sv->next_ticket) { sv->err = "unknown ticket"; return PKM_EINVAL; }
+  sv->cv_done.wait(lk, [&] { return sv->finished.count(ticket) > 0 || (sv->stop && sv->inflight.empty() && sv->queue.empty()); });
+  auto it = sv->finished.find(ticket);
+  if (it == sv->finished.end()) { sv->err = "ticket already collected"; return PKM_EINVAL; }
+  std::shared_ptr<Request> r = it->second;
+  sv->finished.erase(it);
+  if (r->status != PKM_OK) sv->err = r->err;
+  return copy_out(*r, out);
+}
+
+pkm_status pkm_server_stats(pkm_server* sv, pkm_server_stats_t* out) {
+  if (!sv || !out) return PKM_EINVAL;
+  std::lock_guard<std::mutex> g(sv->mu);
+  std::memset(out, 0, sizeof(*out));
+  out->completed = sv->completed;
+  out->failed = sv->failed;
+  out->queued = (int64_t)sv->queue.size();
+  out->inflight = (int64_t)sv->inflight.size();
+  out->resident_plans = (int64_t)sv->slots.size();
+  out->resident_bytes = sv->resident;
+  out->peak_bytes = sv->peak_resident;
+  out->max_concurrent = sv->max_concurrent;
+  out->latency_p50_ms = percentile(sv->latencies_ms, 0.50);
+  out->latency_p99_ms = percentile(sv->latencies_ms, 0.99);
+  out->latency_mean_ms = 0.0;
+  for (double v : sv->latencies_ms) out->latency_mean_ms += v;
+  if (!sv->latencies_ms.empty()) out->latency_mean_ms /= (double)sv->latencies_ms.size();
+  if (sv->any_submit && sv->completed > 0) {
+    const double span = std::chrono::duration<double>(sv->t_last_done - sv->t_first_submit).count();
+    out->throughput_per_s = span > 0 ? (double)sv->completed / span : 0.0;
+  }
+  return PKM_OK;
+}
+
+const char* pkm_server_last_error(const pkm_server* sv) { return sv ? sv->err.c_str() : "no server"; }
+
+void pkm_server_destroy(pkm_server* sv) {
+  if (!sv) return;
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv_work.notify_all();
+  if (sv->worker.joinable()) sv->worker.join();
+  (void)hipSetDevice(sv->cfg.device_id);
+  for (auto& s : sv->slots) free_slot(sv, s.get());
+  sv->slots.clear();
+  delete sv;
+}
+
+}  // extern "C"

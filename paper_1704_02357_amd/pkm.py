@@ -12,6 +12,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+ABI_VERSION = 2
 NGP, CIC, TSC = 1, 2, 3
 FP32, FP64 = 0, 1
 LOS_LOCAL, LOS_GLOBAL = 0, 1
@@ -49,6 +50,22 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 class Device(C.Structure):
     _fields_ = [("device_id", C.c_int32), ("hip_stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
                 ("alloc_ctx", C.c_void_p)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("device_id", C.c_int32), ("hbm_budget_bytes", C.c_int64), ("max_inflight", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("params", Params), ("ell_max", C.c_int32), ("k_edges", C.c_void_p), ("n_edges", C.c_int32),
+                ("data", Catalog), ("randoms", Catalog), ("has_randoms", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("completed", C.c_int64), ("failed", C.c_int64), ("queued", C.c_int64), ("inflight", C.c_int64),
+                ("resident_plans", C.c_int64), ("resident_bytes", C.c_int64), ("peak_bytes", C.c_int64),
+                ("max_concurrent", C.c_int32), ("latency_p50_ms", C.c_double), ("latency_p99_ms", C.c_double),
+                ("latency_mean_ms", C.c_double), ("throughput_per_s", C.c_double)]
 
 
 STAGES = ["sums", "fill", "paint", "zfwd", "ycol", "xcombine", "iycol", "zpre", "xpost", "reduce"]
@@ -95,6 +112,24 @@ def load_library():
         "pkm_fft3d_forward": (C.c_int, [P, P, P]),
         "pkm_fft3d_inverse": (C.c_int, [P, P, P]),
         "pkm_plan_read_buffer": (C.c_int, [P, C.c_int32, P, C.c_size_t]),
+        "pkm_prepare": (C.c_int, [P, C.c_int32, P, C.c_int32, C.c_int64]),
+        "pkm_enqueue": (C.c_int, [P, C.POINTER(Catalog), C.POINTER(Catalog)]),
+        "pkm_query": (C.c_int, [P]),
+        "pkm_finish": (C.c_int, [P, C.POINTER(Result)]),
+        "pkm_batch_create": (C.c_int, [C.c_int32, C.POINTER(P)]),
+        "pkm_batch_add": (C.c_int, [P, P, C.POINTER(Catalog), C.POINTER(Catalog), C.POINTER(C.c_int32)]),
+        "pkm_batch_run": (C.c_int, [P, C.c_int32, C.POINTER(C.c_double)]),
+        "pkm_batch_result": (C.c_int, [P, C.c_int32, C.POINTER(Result)]),
+        "pkm_batch_size": (C.c_int32, [P]),
+        "pkm_batch_last_error": (C.c_char_p, [P]),
+        "pkm_batch_destroy": (None, [P]),
+        "pkm_server_create": (C.c_int, [C.POINTER(ServerConfig), C.POINTER(P)]),
+        "pkm_server_submit": (C.c_int, [P, C.POINTER(Request), C.POINTER(C.c_int64)]),
+        "pkm_server_poll": (C.c_int, [P, C.c_int64, C.POINTER(Result)]),
+        "pkm_server_wait": (C.c_int, [P, C.c_int64, C.POINTER(Result)]),
+        "pkm_server_stats": (C.c_int, [P, C.POINTER(ServerStats)]),
+        "pkm_server_last_error": (C.c_char_p, [P]),
+        "pkm_server_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -153,6 +188,38 @@ class _TorchAllocator:
             pass
 
 
+def make_params(nmesh, box_len, *, box_origin=None, observer=(0.0, 0.0, 0.0), window=TSC, interlaced=True,
+                compensated=True, precision=FP32, ell_max_hint=4, max_group=0, los=None) -> Params:
+    p = Params()
+    p.nmesh = int(nmesh)
+    p.box_len = float(box_len)
+    o = (-0.5 * box_len,) * 3 if box_origin is None else box_origin
+    for a in range(3):
+        p.box_origin[a] = float(o[a])
+        p.observer[a] = float(observer[a])
+    if los is not None:
+        p.los_mode = LOS_GLOBAL
+        for a in range(3):
+            p.los[a] = float(los[a])
+    p.window, p.interlaced, p.compensated = int(window), int(bool(interlaced)), int(bool(compensated))
+    p.precision, p.ell_max_hint, p.max_group = int(precision), int(ell_max_hint), int(max_group)
+    return p
+
+
+def _result_arrays(ell_max: int, nb: int):
+    poles = np.empty((ell_max // 2 + 1, nb))
+    kmean = np.empty(nb)
+    nmodes = np.empty(nb, dtype=np.int64)
+    r = Result()
+    r.poles, r.k_mean, r.n_modes = poles.ctypes.data, kmean.ctypes.data, nmodes.ctypes.data
+    return r, poles, kmean, nmodes
+
+
+def _result_dict(r, poles, kmean, nmodes, ell_max):
+    return dict(poles=poles, k_mean=kmean, n_modes=nmodes, alpha=r.alpha, norm_I=r.norm_I, shot_noise=r.shot_noise,
+                n_transforms=r.n_transforms, ells=list(range(0, ell_max + 1, 2)))
+
+
 class Plan:
     """One mesh configuration.  Inputs may be numpy arrays (host) or torch CUDA tensors."""
 
@@ -160,19 +227,9 @@ class Plan:
                  interlaced=True, compensated=True, precision=FP32, ell_max_hint=4, max_group=0, los=None,
                  device: int = 0, stream=None, torch_allocator: bool = True):
         self.lib = load_library()
-        p = Params()
-        p.nmesh = int(nmesh)
-        p.box_len = float(box_len)
-        o = (-0.5 * box_len,) * 3 if box_origin is None else box_origin
-        for a in range(3):
-            p.box_origin[a] = float(o[a])
-            p.observer[a] = float(observer[a])
-        if los is not None:
-            p.los_mode = LOS_GLOBAL
-            for a in range(3):
-                p.los[a] = float(los[a])
-        p.window, p.interlaced, p.compensated = int(window), int(bool(interlaced)), int(bool(compensated))
-        p.precision, p.ell_max_hint, p.max_group = int(precision), int(ell_max_hint), int(max_group)
+        p = make_params(nmesh, box_len, box_origin=box_origin, observer=observer, window=window,
+                        interlaced=interlaced, compensated=compensated, precision=precision,
+                        ell_max_hint=ell_max_hint, max_group=max_group, los=los)
         self.params = p
         self.nmesh = p.nmesh
         self.precision = p.precision
@@ -231,16 +288,37 @@ class Plan:
 
     def compute_multipoles(self, ell_max: int, k_edges) -> dict:
         e = np.ascontiguousarray(k_edges, dtype=np.float64)
-        nb = e.size - 1
-        poles = np.empty((ell_max // 2 + 1, nb))
-        kmean = np.empty(nb)
-        nmodes = np.empty(nb, dtype=np.int64)
-        r = Result()
-        r.poles, r.k_mean, r.n_modes = poles.ctypes.data, kmean.ctypes.data, nmodes.ctypes.data
+        r, poles, kmean, nmodes = _result_arrays(ell_max, e.size - 1)
         st = self.lib.pkm_compute_multipoles(self.h, int(ell_max), _ptr(e), e.size, C.byref(r))
         self._check(st, "pkm_compute_multipoles")
-        return dict(poles=poles, k_mean=kmean, n_modes=nmodes, alpha=r.alpha, norm_I=r.norm_I,
-                    shot_noise=r.shot_noise, n_transforms=r.n_transforms, ells=list(range(0, ell_max + 1, 2)))
+        return _result_dict(r, poles, kmean, nmodes, ell_max)
+
+    # -- asynchronous estimate -------------------------------------------------------------
+    def prepare(self, ell_max: int, k_edges, max_particles: int):
+        """Host tables and buffers for estimates of up to max_particles objects."""
+        e = np.ascontiguousarray(k_edges, dtype=np.float64)
+        self._check(self.lib.pkm_prepare(self.h, int(ell_max), _ptr(e), e.size, int(max_particles)), "pkm_prepare")
+        self._prep = (int(ell_max), e.size - 1)
+
+    def enqueue(self, data, randoms=None):
+        """Enqueue paint + multipoles of device-resident catalogs; returns at once."""
+        self._akeep = [self._catalog(data), self._catalog(randoms)]
+        d, r = self._akeep
+        self._check(self.lib.pkm_enqueue(self.h, C.byref(d), C.byref(r) if r is not None else None), "pkm_enqueue")
+
+    def query(self) -> bool:
+        st = self.lib.pkm_query(self.h)
+        if st == 5:
+            return False
+        self._check(st, "pkm_query")
+        return True
+
+    def finish(self) -> dict:
+        ell_max, nb = self._prep
+        r, poles, kmean, nmodes = _result_arrays(ell_max, nb)
+        self._check(self.lib.pkm_finish(self.h, C.byref(r)), "pkm_finish")
+        self._akeep = []
+        return _result_dict(r, poles, kmean, nmodes, ell_max)
 
     def kmu_global(self, k_edges, mu_edges):
         ke = np.ascontiguousarray(k_edges, dtype=np.float64)
@@ -299,3 +377,128 @@ class Plan:
 
     def __exit__(self, *a):
         self.close()
+
+
+class Batch:
+    """Many estimates issued as one unit (optionally one HIP graph launch)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        h = C.c_void_p()
+        st = self.lib.pkm_batch_create(int(device), C.byref(h))
+        if st:
+            raise PkmError(st, "pkm_batch_create failed")
+        self.h = h
+        self._items = []
+
+    def _check(self, st, what):
+        if st:
+            msg = self.lib.pkm_batch_last_error(self.h)
+            raise PkmError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def add(self, plan: "Plan", data, randoms=None) -> int:
+        d, r = plan._catalog(data), plan._catalog(randoms)
+        idx = C.c_int32()
+        self._check(self.lib.pkm_batch_add(self.h, plan.h, C.byref(d), C.byref(r) if r is not None else None,
+                                           C.byref(idx)), "pkm_batch_add")
+        self._items.append((plan, plan._prep, (data, randoms)))
+        return idx.value
+
+    def run(self, use_graph: bool = True) -> float:
+        ms = C.c_double()
+        self._check(self.lib.pkm_batch_run(self.h, int(bool(use_graph)), C.byref(ms)), "pkm_batch_run")
+        return ms.value
+
+    def result(self, index: int) -> dict:
+        ell_max, nb = self._items[index][1]
+        r, poles, kmean, nmodes = _result_arrays(ell_max, nb)
+        self._check(self.lib.pkm_batch_result(self.h, int(index), C.byref(r)), "pkm_batch_result")
+        return _result_dict(r, poles, kmean, nmodes, ell_max)
+
+    def __len__(self):
+        return int(self.lib.pkm_batch_size(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pkm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request loop on one device: admission by HBM footprint, overlapping estimates."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, max_inflight: int = 4):
+        self.lib = load_library()
+        cfg = ServerConfig()
+        cfg.device_id, cfg.hbm_budget_bytes, cfg.max_inflight = int(device), int(hbm_budget_bytes), int(max_inflight)
+        h = C.c_void_p()
+        st = self.lib.pkm_server_create(C.byref(cfg), C.byref(h))
+        if st:
+            raise PkmError(st, "pkm_server_create failed")
+        self.h = h
+        self._shape = {}
+
+    def _check(self, st, what):
+        if st:
+            msg = self.lib.pkm_server_last_error(self.h)
+            raise PkmError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def submit(self, nmesh, box_len, ell_max, k_edges, data, randoms=None, **params) -> int:
+        """Queue one estimate of host catalogs; keyword arguments as for Plan."""
+        rq = Request()
+        rq.params = make_params(nmesh, box_len, **params)
+        e = np.ascontiguousarray(k_edges, dtype=np.float64)
+        rq.ell_max, rq.k_edges, rq.n_edges = int(ell_max), e.ctypes.data, e.size
+        keep = [e]
+        for field, cat in (("data", data), ("randoms", randoms)):
+            if cat is None:
+                continue
+            arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+                    for a in (cat.pos, cat.w, getattr(cat, "nbar", None))]
+            keep.append(arrs)
+            c = getattr(rq, field)
+            c.pos, c.w, c.nbar = [None if a is None else a.ctypes.data for a in arrs]
+            c.n, c.on_device = int(arrs[0].shape[0]), 0
+        rq.has_randoms = int(randoms is not None)
+        t = C.c_int64()
+        self._check(self.lib.pkm_server_submit(self.h, C.byref(rq), C.byref(t)), "pkm_server_submit")
+        self._shape[t.value] = (int(ell_max), e.size - 1)
+        return t.value
+
+    def _collect(self, fn, ticket):
+        ell_max, nb = self._shape[ticket]
+        r, poles, kmean, nmodes = _result_arrays(ell_max, nb)
+        st = fn(self.h, int(ticket), C.byref(r))
+        if st == 5:
+            return None
+        self._shape.pop(ticket, None)
+        self._check(st, "server result")
+        return _result_dict(r, poles, kmean, nmodes, ell_max)
+
+    def poll(self, ticket: int):
+        return self._collect(self.lib.pkm_server_poll, ticket)
+
+    def wait(self, ticket: int) -> dict:
+        return self._collect(self.lib.pkm_server_wait, ticket)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        self._check(self.lib.pkm_server_stats(self.h, C.byref(s)), "pkm_server_stats")
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pkm_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -31,7 +31,8 @@ def test_exports_every_declared_symbol():
     assert len(syms) >= 14
     for s in syms:
         assert hasattr(lib, s), s
-    assert lib.pkm_abi_version() == 1
+    from paper_1704_02357_amd import ABI_VERSION
+    assert lib.pkm_abi_version() == ABI_VERSION
     assert lib.pkm_status_str(0) == b"ok"
     assert lib.pkm_status_str(2) == b"compute before paint"
 

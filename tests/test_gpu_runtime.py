@@ -1,0 +1,197 @@
+"""GPU tests of the asynchronous estimate, the batch runtime (uneven mock sizes, HIP graph
+capture and replay) and the serving loop (mixed requests admitted while others run).
+
+Every batched or served result is compared with the same estimate run alone through the
+synchronous calls, to the precision form's tolerance."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+from tests.parity_util import small_catalogs
+
+pytestmark = pytest.mark.gpu
+
+OBS = (30.0, -40.0, -700.0)
+L = 300.0
+
+
+def _edges(n):
+    return np.arange(0.0, math.pi * n / L, 0.04)
+
+
+def _scaled_err(a, b):
+    pa, pb = np.asarray(a["poles"]), np.asarray(b["poles"])
+    scale = np.maximum(np.abs(pb), np.abs(pb[0] + b["shot_noise"])[None, :])
+    ok = np.isfinite(pb)
+    assert np.array_equal(ok, np.isfinite(pa))
+    return float(np.max(np.abs(pa - pb)[ok] / scale[ok])) if ok.any() else 0.0
+
+
+# painting adds tile flushes with atomics, so two runs agree to rounding only
+RUN_TOL = {0: 2e-6, 1: 1e-12}
+
+
+def _same(a, b, prec, label):
+    assert np.array_equal(a["n_modes"], b["n_modes"]), label
+    for k in ("alpha", "norm_I", "shot_noise"):
+        assert abs(a[k] - b[k]) <= 1e-12 * abs(b[k]), (label, k)
+    err = _scaled_err(a, b)
+    print(f"[same] {label} scaled_err={err:.2e}", flush=True)
+    assert err <= RUN_TOL[prec], (label, err)
+
+
+def _plan(n, prec, lmax=4, stream=None, **kw):
+    from paper_1704_02357_amd import Plan
+    return Plan(n, L, observer=OBS, window=3, interlaced=True, compensated=True, precision=prec,
+                ell_max_hint=lmax, stream=stream, **kw)
+
+
+def _alone(n, prec, lmax, d, r, **kw):
+    p = _plan(n, prec, lmax, **kw)
+    p.paint(d, r)
+    out = p.compute_multipoles(lmax, _edges(n))
+    p.close()
+    return out
+
+
+def _dev(cat):
+    import torch
+    if cat is None:
+        return None
+    f = lambda a: None if a is None else torch.tensor(a, dtype=torch.float64, device="cuda")
+    return (f(cat.pos), f(cat.w), f(cat.nbar))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_async_estimate_matches_sync(gpu, prec):
+    import torch
+    from paper_1704_02357_amd import PkmError
+    n, lmax = 48, 4
+    d, r = small_catalogs(3000, 20000, L, seed=71)
+    ref = _alone(n, prec, lmax, d, r)
+    s = torch.cuda.Stream()
+    p = _plan(n, prec, lmax, stream=s)
+    dd, rr = _dev(d), _dev(r)
+    with pytest.raises(PkmError):          # not prepared
+        p.enqueue(dd, rr)
+    p.prepare(lmax, _edges(n), 30000)
+    with pytest.raises(PkmError):          # host catalogs are refused
+        p.enqueue(d, r)
+    p.enqueue(dd, rr)
+    with pytest.raises(PkmError):          # one estimate at a time
+        p.enqueue(dd, rr)
+    with pytest.raises(PkmError):          # the plan's buffers are in use
+        p.paint(d, r)
+    while not p.query():
+        pass
+    got = p.finish()
+    _same(got, ref, prec, f"async prec={prec}")
+    # the plan now holds the painted field: a synchronous compute agrees
+    again = p.compute_multipoles(lmax, _edges(n))
+    _same(again, ref, prec, f"after finish prec={prec}")
+    p.close()
+
+
+def test_batch_uneven_mocks_graph_replays(gpu):
+    """Six mocks on three mesh sizes (two plans per size, each on its own stream), issued
+    directly and as one captured graph; replays with eager work in between, and a replay
+    after a catalog's contents changed, all match the estimates run alone."""
+    import torch
+    from paper_1704_02357_amd import Batch
+    prec, lmax = 0, 4
+    sizes = [32, 48, 64, 32, 48, 64]
+    mocks = [small_catalogs(1500 + 300 * i, 9000 + 1000 * i, L, seed=100 + i) for i in range(6)]
+    plans = {}
+    for n in sorted(set(sizes)):
+        for k in range(2):
+            p = _plan(n, prec, lmax, stream=torch.cuda.Stream())
+            p.prepare(lmax, _edges(n), 20000)
+            plans[(n, k)] = p
+    b = Batch()
+    dev = []
+    for i, n in enumerate(sizes):
+        d, r = mocks[i]
+        dd, rr = _dev(d), _dev(r)
+        dev.append((dd, rr))
+        b.add(plans[(n, i % 2)], dd, rr)
+    refs = [_alone(n, prec, lmax, *mocks[i]) for i, n in enumerate(sizes)]
+    ms = b.run(use_graph=False)
+    print(f"[batch] direct {ms:.2f} ms", flush=True)
+    for i in range(6):
+        _same(b.result(i), refs[i], prec, f"direct item {i}")
+    for rep in range(3):
+        ms = b.run(use_graph=True)
+        print(f"[batch] graph replay {rep} {ms:.2f} ms", flush=True)
+        for i in range(6):
+            _same(b.result(i), refs[i], prec, f"graph replay {rep} item {i}")
+        # eager work and synchronisation between replays
+        x = torch.randn(1 << 20, device="cuda")
+        torch.cuda.synchronize()
+        assert torch.isfinite(x.sum()).item()
+        _alone(32, prec, 2, *mocks[0])
+    # new catalog contents at the same addresses and sizes: the graph reads them
+    from synth import Catalog
+    d2, r2 = small_catalogs(1500, 9000, L, seed=999)
+    dd, rr = dev[0]
+    dd[0].copy_(torch.tensor(d2.pos, device="cuda"))
+    rr[0].copy_(torch.tensor(r2.pos, device="cuda"))
+    torch.cuda.synchronize()
+    b.run(use_graph=True)
+    new_d = Catalog(d2.pos, mocks[0][0].w, mocks[0][0].nbar)
+    new_r = Catalog(r2.pos, mocks[0][1].w, mocks[0][1].nbar)
+    _same(b.result(0), _alone(32, prec, lmax, new_d, new_r), prec, "replay after new contents")
+    b.close()
+    for p in plans.values():
+        p.close()
+
+
+def test_server_mixed_stream_matches_alone(gpu):
+    """Requests of different sizes, l_max, precision and with or without randoms, submitted
+    at once: admitted while others run, overlapping on the device, each equal to its
+    estimate run alone."""
+    from paper_1704_02357_amd import Server
+    reqs = []
+    for i, (n, lmax, prec, with_r) in enumerate([(32, 4, 0, True), (48, 8, 0, True), (64, 2, 1, True),
+                                                 (32, 4, 1, False), (64, 4, 0, True), (48, 4, 0, True),
+                                                 (32, 6, 0, True), (64, 4, 0, True)]):
+        d, r = small_catalogs(2000 + 500 * i, 12000 if with_r else 0, L, seed=300 + i)
+        reqs.append((n, lmax, prec, d, r))
+    sv = Server(max_inflight=3)
+    tickets = [sv.submit(n, L, lmax, _edges(n), d, r, observer=OBS, window=3, interlaced=True, compensated=True,
+                         precision=prec, ell_max_hint=lmax) for n, lmax, prec, d, r in reqs]
+    got = [sv.wait(t) for t in tickets]
+    st = sv.stats()
+    print(f"[server] {st}", flush=True)
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["max_concurrent"] >= 2
+    assert st["resident_plans"] >= 3
+    for (n, lmax, prec, d, r), g in zip(reqs, got):
+        _same(g, _alone(n, prec, lmax, d, r), prec, f"server n={n} l={lmax} prec={prec} randoms={r is not None}")
+    sv.close()
+
+
+def test_server_budget_admission(gpu):
+    """Under a budget that holds one 64^3 plan, requests still complete (one at a time),
+    the resident bytes never exceed the budget, and a request that cannot fit fails."""
+    from paper_1704_02357_amd import PkmError, Server
+    d, r = small_catalogs(2000, 12000, L, seed=5)
+    probe = _plan(64, 0, 4, torch_allocator=False)
+    probe.prepare(4, _edges(64), 14000)
+    one = probe.stats()["device_bytes"]
+    probe.close()
+    budget = int(one * 1.6)
+    sv = Server(max_inflight=4, hbm_budget_bytes=budget)
+    ts = [sv.submit(64, L, 4, _edges(64), d, r, observer=OBS, precision=0, ell_max_hint=4,
+                    box_origin=(-150.0 + 0.1 * k, -150.0, -150.0)) for k in range(3)]
+    outs = [sv.wait(t) for t in ts]
+    st = sv.stats()
+    print(f"[server budget] budget={budget} {st}", flush=True)
+    assert st["completed"] == 3 and st["peak_bytes"] <= budget
+    assert all(np.isfinite(o["poles"][0]).any() for o in outs)
+    big = sv.submit(128, L, 16, _edges(128), d, r, observer=OBS, precision=1, ell_max_hint=16)
+    with pytest.raises(PkmError):
+        sv.wait(big)
+    sv.close()
