@@ -198,6 +198,135 @@ def cpu_baseline(data, rand, edges, workers: int) -> dict:
                       + ", ".join(f"{k} {v:.1f}" for k, v in t.items())}
 
 
+def batch_bench(args) -> dict:
+    """64 seeded lognormal covariance mocks of uneven size (Nmesh 128/256/384 in turn,
+    5e4-8e5 galaxies, 10x randoms), l <= 4, FP32: all mocks issued as one batch over
+    per-plan streams, replayed as one HIP graph; against the same mocks run one by one."""
+    import torch
+    from paper_1704_02357_amd import Batch, Plan
+    from synth import batch_mock
+    n_mocks, lmax, per_size = args.mocks, 4, 4
+    t0 = time.perf_counter()
+    mocks = [batch_mock(i) for i in range(n_mocks)]
+    log(f"[batch] {n_mocks} mocks generated in {time.perf_counter() - t0:.1f} s")
+    dev = lambda a: None if a is None else torch.tensor(a, dtype=torch.float64, device="cuda")
+    L = 2000.0
+    edges = {n: np.arange(int(math.floor(math.pi * n / L / 0.01)) + 1, dtype=np.float64) * 0.01
+             for n in (128, 256, 384)}
+    plans = {}
+    maxp = {}
+    for d, r, info, n in mocks:
+        maxp[n] = max(maxp.get(n, 0), len(d.pos) + len(r.pos))
+    for n in sorted(maxp):
+        for k in range(per_size):
+            p = Plan(n, L, observer=OBSERVER, window=3, interlaced=True, compensated=True, precision=0,
+                     ell_max_hint=lmax, stream=torch.cuda.Stream())
+            p.prepare(lmax, edges[n], maxp[n])
+            plans[(n, k)] = p
+    b = Batch()
+    cats = []
+    count = {}
+    for i, (d, r, info, n) in enumerate(mocks):
+        dd = (dev(d.pos), dev(d.w), dev(d.nbar))
+        rr = (dev(r.pos), dev(r.w), dev(r.nbar))
+        cats.append((dd, rr))
+        k = count.get(n, 0)
+        count[n] = k + 1
+        b.add(plans[(n, k % per_size)], dd, rr)
+    torch.cuda.synchronize()
+    b.run(use_graph=False)
+    t_direct = min(b.run(use_graph=False) for _ in range(2))
+    b.run(use_graph=True)   # capture + first replay
+    t_graph = [b.run(use_graph=True) for _ in range(args.steps)]
+    # the same mocks one after another through the synchronous calls (one plan per size)
+    seq = {n: Plan(n, L, observer=OBSERVER, window=3, interlaced=True, compensated=True, precision=0,
+                   ell_max_hint=lmax) for n in maxp}
+    errs = []
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    for i, (d, r, info, n) in enumerate(mocks):
+        seq[n].paint(cats[i][0], cats[i][1])
+        ref = seq[n].compute_multipoles(lmax, edges[n])
+        got = b.result(i)
+        scale = np.maximum(np.abs(ref["poles"]), np.abs(ref["poles"][0] + ref["shot_noise"])[None, :])
+        ok = np.isfinite(ref["poles"])
+        errs.append(float(np.max(np.abs(got["poles"] - ref["poles"])[ok] / scale[ok])))
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - s0) * 1e3
+    med = float(np.median(t_graph))
+    for p in list(plans.values()) + list(seq.values()):
+        p.close()
+    b.close()
+    return {"metric": "covariance-mock P_l(k) estimates/s (64 lognormal mocks, Nmesh 128/256/384, l<=4, FP32, "
+                      "one graph launch)",
+            "value": round(n_mocks / (med * 1e-3), 2), "unit": "estimates/s", "n_gpus": 1, "steps": args.steps,
+            "ms_per_batch_graph": round(med, 2), "ms_per_batch_direct": round(t_direct, 2),
+            "ms_per_batch_sequential_sync": round(t_seq, 2), "higher_is_better": True, "dtype": "f32",
+            "data": "synthetic (seeded lognormal mocks, resident in HBM)",
+            "config": {"workload": f"{n_mocks} mocks, Nmesh cycling 128/256/384, L=2000 Mpc/h, 5e4-8e5 galaxies, "
+                                   "10x randoms, TSC + interlacing + compensation, l<=4, 0.01 h/Mpc bins",
+                       "plans_per_size": per_size},
+            "max_scaled_err_vs_sequential": max(errs)}
+
+
+def serve_bench(args) -> dict:
+    """Poisson-arrival request stream mixing Nmesh 256-768, l_max 4/8/16, 1e5-3e6 galaxies
+    (2x randoms), FP32 and FP64, through the serving loop; throughput and latency."""
+    import threading
+    from paper_1704_02357_amd import Server
+    from synth import SurveyGeometry, lognormal_survey
+    rng = np.random.default_rng(2026)
+    L = 2500.0
+    geom = SurveyGeometry(box_len=L)
+    t0 = time.perf_counter()
+    pool = [lognormal_survey(geom, int(ng), 4000 + i, ng=128, random_factor=2.0)[:2]
+            for i, ng in enumerate(np.geomspace(1e5, 3e6, 5))]
+    log(f"[serve] catalog pool generated in {time.perf_counter() - t0:.1f} s")
+    sizes, lmaxes = [256, 384, 512, 768], [4, 8, 16]
+    reqs = []
+    for i in range(args.requests):
+        n = int(rng.choice(sizes))
+        lmax = int(rng.choice(lmaxes))
+        prec = int(rng.integers(0, 2))
+        d, r = pool[int(rng.integers(0, len(pool)))]
+        edges = np.arange(int(math.floor(math.pi * n / L / 0.01)) + 1, dtype=np.float64) * 0.01
+        reqs.append((n, lmax, prec, d, r, edges))
+    gaps = rng.exponential(1.0 / args.rate, size=len(reqs))
+    sv = Server(max_inflight=args.inflight)
+    tickets = [None] * len(reqs)
+
+    def submitter():
+        start = time.perf_counter()
+        due = 0.0
+        for i, (n, lmax, prec, d, r, edges) in enumerate(reqs):
+            due += gaps[i]
+            delay = start + due - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets[i] = sv.submit(n, L, lmax, edges, d, r, observer=OBSERVER, window=3, interlaced=True,
+                                   compensated=True, precision=prec, ell_max_hint=lmax)
+
+    s0 = time.perf_counter()
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    for t in tickets:
+        sv.wait(t)
+    wall = time.perf_counter() - s0
+    st = sv.stats()
+    sv.close()
+    return {"metric": "served P_l(k) requests/s (Poisson stream, Nmesh 256-768, l_max 4/8/16, FP32+FP64), "
+                      "p50/p99 latency",
+            "value": round(len(reqs) / wall, 3), "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
+            "latency_ms": {"p50": round(st["latency_p50_ms"], 2), "p99": round(st["latency_p99_ms"], 2),
+                           "mean": round(st["latency_mean_ms"], 2)},
+            "server": {k: st[k] for k in ("completed", "failed", "max_concurrent", "resident_plans", "peak_bytes")},
+            "dtype": "f32+f64", "data": "synthetic (seeded lognormal catalogs, 5 sizes 1e5-3e6 galaxies, 2x randoms)",
+            "config": {"workload": f"{len(reqs)} requests, Poisson arrivals at {args.rate}/s, Nmesh in {sizes}, "
+                                   f"l_max in {lmaxes}, half FP32 / half FP64, L=2500 Mpc/h",
+                       "max_inflight": args.inflight}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,6 +341,12 @@ def main():
                     help="run a plain 1 GiB device copy (x3) first, to calibrate HBM byte counters")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="print the kernel summary of a rocprofv3 CSV output directory and exit")
+    ap.add_argument("--mode", choices=["estimate", "batch", "serve"], default="estimate",
+                    help="estimate: the 512^3 l<=4 line (default); batch: covariance mocks; serve: request stream")
+    ap.add_argument("--mocks", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=48)
+    ap.add_argument("--rate", type=float, default=1.0, help="request arrivals per second (serve mode)")
+    ap.add_argument("--inflight", type=int, default=4)
     args = ap.parse_args()
     if args.summarize_profile:
         summarize_profile(args.summarize_profile)
@@ -224,6 +359,10 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.mode != "estimate":
+        out = batch_bench(args) if args.mode == "batch" else serve_bench(args)
+        print(json.dumps(out), flush=True)
+        return
     if args.calib_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)   # 1 GiB
         dst = torch.empty_like(src)
