@@ -21,6 +21,7 @@ struct FftShape {
   uint32_t sched_post;
   int nst_post;
   int tile_post;    // columns per post-pass tile
+  int cus;          // compute units of the device (0: unknown)
 };
 
 // LDS bytes of a post-pass block without its histograms.

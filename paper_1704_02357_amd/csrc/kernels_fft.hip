@@ -19,6 +19,8 @@
 // lines per block for the z passes).  For power-of-two meshes the launchers instantiate them
 // with the plan's values, so all index arithmetic and the radix schedule fold to constants;
 // NC = TC = 0 selects the runtime-generic path used for the other sizes.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "device_common.hpp"
 
@@ -448,6 +450,56 @@ __host__ __device__ constexpr size_t xpost_elems(int n, int tile) {
   return 2 * (size_t)xrows(n) * (tile + 1) + (NC > 0 ? twst_size<E, NC>() : n);
 }
 
+// Tiles of a persistent post-pass block.  When the tile count and the grid are multiples of
+// 8, block b (dispatched to XCD b mod 8) walks a contiguous eighth of the tiles, so the
+// blocks of one XCD work on neighbouring tiles (which share 128-byte rows) at the same time.
+struct TileWalk {
+  int ntiles, first, step, end, chunk0;
+  __device__ TileWalk(int nt) : ntiles(nt) {
+    const int G = gridDim.x, b = blockIdx.x;
+    if (nt % 8 == 0 && G % 8 == 0 && G <= nt) {
+      const int per = nt / 8;
+      chunk0 = (b % 8) * per;
+      first = b / 8;
+      step = G / 8;
+      end = per;
+    } else {
+      chunk0 = 0;
+      first = b;
+      step = G;
+      end = nt;
+    }
+  }
+  __device__ int tile(int j) const { return chunk0 + j; }
+};
+
+// k bins of E elements at once from thresholds in LDS: all searches step together, so the
+// LDS reads of the E elements overlap.  -1 for modes outside [thr[0], thr[nb]) or excluded.
+template <int E>
+__device__ __forceinline__ void kbins_lds(const long long* thr, int nb, const int* n2, const bool* excl, int* bin) {
+  int lo[E], hi[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    lo[e] = 0;
+    hi[e] = nb;
+  }
+  for (int w = nb; w > 1; w = (w + 1) >> 1) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int mid = (lo[e] + hi[e]) >> 1;
+      if (hi[e] - lo[e] > 1) {
+        if (thr[mid] <= (long long)n2[e]) lo[e] = mid;
+        else hi[e] = mid;
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const bool in = !excl[e] && (long long)n2[e] >= thr[0] && (long long)n2[e] < thr[nb];
+    bin[e] = in ? lo[e] : -1;
+  }
+}
+
 template <typename T, int E, int NC, int TC>
 __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, uint32_t sched, int nst,
                                                           void* const* __restrict__ bufs, int nf,
@@ -472,85 +524,102 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
   double* hist = reinterpret_cast<double*>(smem + sizeof(cx<T>) * xpost_elems<T, E, NC>(n, tile));
   const int l0rows = with_l0 ? 3 : 0;
   const int nvals = (l0rows + nslots) * nb;
+  long long* thr_l = reinterpret_cast<long long*>(hist + (size_t)copies * nvals);
   hist_zero(hist, copies * nvals);
+  for (int i = threadIdx.x; i <= nb; i += blockDim.x) thr_l[i] = thr[i];
   if constexpr (NC > 0) ct_twiddles<T, E, NC, NC>(twst, tw); else stage_twiddles<T>(twl, tw, n);
-  const int tiles = nh / tile;
-  const int blk = xcd_tile(blockIdx.x, gridDim.x);
-  const int y = blk / tiles;
-  const int kz0 = (blk % tiles) * tile;
+  const int tiles_x = nh / tile;
   const size_t rs = (size_t)n * nh;
-  const size_t base = (size_t)y * nh + kz0;
   const int tid = threadIdx.x;
   // rows fastest across the lanes of a wave: a column's transform stays inside one wave
   const int t = tid % pt, c = tid / pt;
-  const int kz = kz0 + c;
-  const int fy = sfreq(y, n);
-  const bool ynyq = (y == nh);
-  const double w4pi = ((kz == 0) ? 1.0 : 2.0) * FOUR_PI;
   double* h = hist + ((tid >> 6) % copies) * nvals;
   const LineRt rt{n, sched, nst, pt, n};
-  __syncthreads();  // histogram zeroed, twiddles staged
+  const TileWalk walk(n * tiles_x);
+  __syncthreads();  // histogram zeroed, thresholds and twiddles staged
+  auto base_of = [&](int tl) { return (size_t)(tl / tiles_x) * nh + (size_t)(tl % tiles_x) * tile; };
   cx<T> nxt[E];
-  if (nf > 0) tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[0]]), base, rs, tile, bs);
-  // per element: k bin (-1 when the mode is excluded), C, unit wave vector
-  int bin[E];
-  cx<T> cv[E];
-  T ux[E], uy[E], uz[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int x = t + pt * e;
-    const int fx = sfreq(x, n);
-    const int n2 = fx * fx + fy * fy + kz * kz;
-    bin[e] = (ynyq || x == nh || n2 == 0) ? -1 : kbin_of(n2, thr, nb);
-    cv[e] = gload<T>(cin, base + c + (size_t)x * rs);
-    const T ki = n2 > 0 ? T(1) / sqrt((T)n2) : T(0);
-    ux[e] = (T)fx * ki;
-    uy[e] = (T)fy * ki;
-    uz[e] = (T)kz * ki;
-  }
-  cx<T> acc[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) acc[e] = mk<T>(T(0), T(0));
-  YRun<T, E> yr;
-  yrun_init(yr);
-  for (int f = 0; f < nf; ++f) {
-    cx<T>* tb = lds + (f & 1) * tsz;
-    tile_to_lds<T, E, XPAD>(tb, nxt, tile, pitch, bs);
-    // prefetch the next field's tile while this one is transformed
-    if (f + 1 < nf)
-      tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[4 * (f + 1)]]), base, rs, tile, bs);
-    __syncthreads();
-    cx<T> u[E];
-    xf_lds_in<T, E, false, XPAD, NC, WAVE>(tb, c, pitch, rt, t, u, twst, twl);
-    const int slot = fields[4 * f + 3];
+  int j = walk.first;
+  if (j < walk.end && nf > 0)
+    tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[0]]), base_of(walk.tile(j)), rs, tile, bs);
+  int parity = 0;
+  for (; j < walk.end; j += walk.step) {
+    const int tl = walk.tile(j);
+    const int y = tl / tiles_x;
+    const int kz = (tl % tiles_x) * tile + c;
+    const size_t base = base_of(tl);
+    const int fy = sfreq(y, n);
+    const bool ynyq = (y == nh);
+    const double w4pi = ((kz == 0) ? 1.0 : 2.0) * FOUR_PI;
+    // per element: k bin (-1 when the mode is excluded), C, unit wave vector
+    int bin[E];
+    cx<T> cv[E];
+    T ux[E], uy[E], uz[E];
     {
-      T yv[E];
-      yrun_eval<T, E>(yr, fields[4 * f + 1], fields[4 * f + 2], ux, uy, uz, yv, ytab);
-#pragma unroll
-      for (int e = 0; e < E; ++e) acc[e] = mk<T>(acc[e].x + yv[e] * u[e].x, acc[e].y + yv[e] * u[e].y);
-    }
-    if (f + 1 == nf || fields[4 * (f + 1) + 3] != slot) {
-      double* hs = h + (l0rows + slot) * nb;
+      int n2[E];
+      bool excl[E];
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        if (bin[e] >= 0)
-          lds_atomic_add<double>(&hs[bin[e]], w4pi * ((double)cv[e].x * (double)acc[e].x +
-                                                      (double)cv[e].y * (double)acc[e].y));
-        acc[e] = mk<T>(T(0), T(0));
+        const int x = t + pt * e;
+        const int fx = sfreq(x, n);
+        n2[e] = fx * fx + fy * fy + kz * kz;
+        excl[e] = ynyq || x == nh || n2[e] == 0;
+        cv[e] = gload<T>(cin, base + c + (size_t)x * rs);
+        const T ki = n2[e] > 0 ? T(1) / sqrt((T)n2[e]) : T(0);
+        ux[e] = (T)fx * ki;
+        uy[e] = (T)fy * ki;
+        uz[e] = (T)kz * ki;
+      }
+      kbins_lds<E>(thr_l, nb, n2, excl, bin);
+    }
+    cx<T> acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = mk<T>(T(0), T(0));
+    YRun<T, E> yr;
+    yrun_init(yr);
+    for (int f = 0; f < nf; ++f) {
+      cx<T>* tb = lds + parity * tsz;
+      parity ^= 1;
+      tile_to_lds<T, E, XPAD>(tb, nxt, tile, pitch, bs);
+      // prefetch the next field's tile (or the next tile's first field) during this one
+      if (f + 1 < nf)
+        tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[4 * (f + 1)]]), base, rs, tile, bs);
+      else if (j + walk.step < walk.end)
+        tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[0]]), base_of(walk.tile(j + walk.step)), rs,
+                        tile, bs);
+      __syncthreads();
+      cx<T> u[E];
+      xf_lds_in<T, E, false, XPAD, NC, WAVE>(tb, c, pitch, rt, t, u, twst, twl);
+      const int slot = fields[4 * f + 3];
+      {
+        T yv[E];
+        yrun_eval<T, E>(yr, fields[4 * f + 1], fields[4 * f + 2], ux, uy, uz, yv, ytab);
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] = mk<T>(acc[e].x + yv[e] * u[e].x, acc[e].y + yv[e] * u[e].y);
+      }
+      if (f + 1 == nf || fields[4 * (f + 1) + 3] != slot) {
+        double* hs = h + (l0rows + slot) * nb;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          if (bin[e] >= 0)
+            lds_atomic_add<double>(&hs[bin[e]], w4pi * ((double)cv[e].x * (double)acc[e].x +
+                                                        (double)cv[e].y * (double)acc[e].y));
+          acc[e] = mk<T>(T(0), T(0));
+        }
       }
     }
-  }
-  if (with_l0) {
-    const double w = (kz == 0) ? 1.0 : 2.0;
+    if (with_l0) {
+      const double w = (kz == 0) ? 1.0 : 2.0;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      if (bin[e] < 0) continue;
-      const int fx = sfreq(t + pt * e, n);
-      const int n2 = fx * fx + fy * fy + kz * kz;
-      lds_atomic_add<double>(&h[bin[e]], w);
-      lds_atomic_add<double>(&h[nb + bin[e]], w * kf * sqrt((double)n2));
-      lds_atomic_add<double>(&h[2 * nb + bin[e]],
-                             w * ((double)cv[e].x * (double)cv[e].x + (double)cv[e].y * (double)cv[e].y));
+      for (int e = 0; e < E; ++e) {
+        if (bin[e] < 0) continue;
+        const int fx = sfreq(t + pt * e, n);
+        const int n2 = fx * fx + fy * fy + kz * kz;
+        lds_atomic_add<double>(&h[bin[e]], w);
+        lds_atomic_add<double>(&h[nb + bin[e]], w * kf * sqrt((double)n2));
+        lds_atomic_add<double>(&h[2 * nb + bin[e]],
+                               w * ((double)cv[e].x * (double)cv[e].x + (double)cv[e].y * (double)cv[e].y));
+      }
     }
   }
   __syncthreads();
@@ -642,7 +711,13 @@ static size_t zsmem(const FftShape& fs, size_t cs) {
 }
 int xpass_threads(const FftShape& fs) { return (fs.n / fs.e_col) * fs.tile; }
 int xpass_blocks(const FftShape& fs) { return fs.n * ((fs.n / 2) / fs.tile); }
-int post_blocks(const FftShape& fs) { return fs.n * ((fs.n / 2) / fs.tile_post); }
+// Persistent post-pass grid: two blocks per compute unit (the register budget allows no
+// more), at most one block per tile.
+int post_blocks(const FftShape& fs) {
+  const int tiles = fs.n * ((fs.n / 2) / fs.tile_post);
+  const int cus = fs.cus > 0 ? fs.cus : 256;
+  return std::min(tiles, 2 * cus);
+}
 static size_t colsmem(const FftShape& fs, size_t cs) { return cs * ((size_t)fs.n * (fs.tile + 1) + fs.n); }
 size_t xpost_base_bytes(const FftShape& fs, bool fp64) {
   const size_t cs = fp64 ? sizeof(double2) : sizeof(float2);
@@ -767,7 +842,8 @@ hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const
                         double* partial, int* nblocks_out, const void* tw, hipStream_t s) {
   if (nslots < 0) return hipErrorInvalidValue;
   const int rows = (with_l0 ? 3 : 0) + nslots;
-  const size_t sm = xpost_base_bytes(fs, sizeof(T) == 8) + sizeof(double) * (size_t)bs.hist_copies * rows * bs.nb;
+  const size_t sm = xpost_base_bytes(fs, sizeof(T) == 8) + sizeof(double) * (size_t)bs.hist_copies * rows * bs.nb +
+                    sizeof(long long) * (size_t)(bs.nb + 1);
   const int nblk = post_blocks(fs);
   const int nthr = (fs.n / fs.e_post) * fs.tile_post;
   if (nthr > XPOST_THREADS) return hipErrorInvalidValue;

@@ -537,7 +537,7 @@ template <typename T> void prepare_compute(pkm_plan* pl, int ell_max, const doub
     if (groups.empty()) groups.push_back({});  // l = 0 only
   }
   const int rows = 3 + ell_max / 2;  // count, ksum, Q0, Q2, ...
-  const size_t col_lds = xpost_base_bytes(pl->fs, sizeof(T) == 8);
+  const size_t col_lds = xpost_base_bytes(pl->fs, sizeof(T) == 8) + sizeof(long long) * (size_t)n_edges;
   if (col_lds + sizeof(double) * 5 * (size_t)nb > 160 * 1024) {
     pl->err = "too many k bins for one pass";
     throw Fail{PKM_EINVAL};
@@ -1050,6 +1050,11 @@ pkm_status pkm_plan_create(const pkm_params* p, const pkm_device* dev, pkm_plan*
   if (!make_shape(*p, &pl->fs)) {
     delete pl;
     return PKM_EINVAL;
+  }
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->dev.device_id) == hipSuccess)
+      pl->fs.cus = cus;
   }
   st = guarded(pl, [&] {
     check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
