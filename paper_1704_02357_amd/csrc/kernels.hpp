@@ -41,13 +41,16 @@ template <typename T> hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s)
 
 // Counting sort of particles by tile of their base node (tile side ts): per particle the
 // tile id and its rank within the tile (atomic counter), for catalog entries [base, base+n).
+// `count` holds TILE_COUNT_COPIES zeroed copies of ntiles + 1 counters (a block uses one copy);
+// launch_tile_offsets turns them in place into per-copy start offsets.
 hipError_t launch_tile_sort(const double* pos, int64_t n, int64_t base, const double* origin, double scale,
                             int nmesh, int ts, int* count, int* tile_of, int* rank, hipStream_t s);
 // Exclusive scan of the tile counts (off has ntiles + 1 entries), then the particle payload
 // (x, y, z, w for data / -alpha w for randoms; 32 bytes each) written in tile order.
-hipError_t launch_tile_offsets(const int* count, int ntiles, int* off, const int* tile_of, const int* rank,
+hipError_t launch_tile_offsets(int* count, int ntiles, int* off, const int* tile_of, const int* rank,
                                int64_t nd, int64_t ntot, const double* dpos, const double* dw, const double* rpos,
                                const double* rw, double alpha, void* payload, int* bsum, hipStream_t s);
+constexpr int TILE_COUNT_COPIES = 8;
 // Scratch entries needed by the tile scan (block sums).
 inline int tile_scan_scratch(int ntiles) { return (ntiles + 1023) / 1024 + 1; }
 // Tile-wise painting from the sorted payload.

@@ -89,11 +89,21 @@ __device__ __forceinline__ void mesh_u(const double* __restrict__ pos, int64_t i
   u[2] = __dmul_rn(__dsub_rn(pos[3 * i + 2], o2), scale);
 }
 
+// Tile counters come in NCOPY copies of ntiles + 1: a block counts into copy blockIdx mod
+// NCOPY.  Workgroups are dispatched round-robin over the 8 XCDs, so each copy is then updated
+// from one XCD only and its cache lines stay in that XCD's L2 instead of moving between XCDs
+// on every atomic.  (Any copy assignment is correct; this one is only faster.)  The rank
+// returned carries the copy in its top bits.
+constexpr int NCOPY = TILE_COUNT_COPIES;
+constexpr int RANK_BITS = 28;
+
 __global__ void k_tile_count(const double* __restrict__ pos, int64_t n, int64_t base, double o0, double o1,
-                             double o2, double scale, int nmesh, int ts, int* __restrict__ count,
+                             double o2, double scale, int nmesh, int ts, int ntiles, int* __restrict__ count,
                              int* __restrict__ tile_of, int* __restrict__ rank) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int tpa = nmesh / ts;
+  const int copy = blockIdx.x % NCOPY;
+  int* cnt = count + (size_t)copy * (ntiles + 1);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     double u[3];
     mesh_u(pos, i, o0, o1, o2, scale, u);
@@ -101,7 +111,7 @@ __global__ void k_tile_count(const double* __restrict__ pos, int64_t n, int64_t 
     for (int a = 0; a < 3; ++a) tc[a] = wrap((long long)floor(u[a]), nmesh) / ts;
     const int tile = (tc[0] * tpa + tc[1]) * tpa + tc[2];
     tile_of[base + i] = tile;
-    rank[base + i] = atomicAdd(&count[tile], 1);
+    rank[base + i] = atomicAdd(&cnt[tile], 1) | (copy << RANK_BITS);
   }
 }
 
@@ -124,7 +134,9 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_blocks(const int* __restr
                                                               int* __restrict__ off, int* __restrict__ bsum) {
   __shared__ int part[SCAN_THREADS];
   const int i = blockIdx.x * SCAN_THREADS + threadIdx.x;
-  const int v = i < n ? count[i] : 0;
+  int v = 0;
+  if (i < n)
+    for (int c = 0; c < NCOPY; ++c) v += count[(size_t)c * (n + 1) + i];
   const int ex = block_scan_excl(v, part);
   if (i < n) off[i] = ex;
   if (threadIdx.x == SCAN_THREADS - 1) bsum[blockIdx.x] = ex + v;
@@ -148,15 +160,25 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_sums(int* __restrict__ bs
   if (threadIdx.x == 0) off[n] = carry;
 }
 
+// Final tile offsets, and the counters turned in place into per-copy start offsets:
+// count[c][i] <- off[i] + sum over c' < c of count[c'][i].
 __global__ void __launch_bounds__(SCAN_THREADS) k_scan_add(const int* __restrict__ bsum, int n,
-                                                           int* __restrict__ off) {
+                                                           int* __restrict__ off, int* __restrict__ count) {
   const int i = blockIdx.x * SCAN_THREADS + threadIdx.x;
-  if (i < n) off[i] += bsum[blockIdx.x];
+  if (i >= n) return;
+  int start = off[i] + bsum[blockIdx.x];
+  off[i] = start;
+  for (int c = 0; c < NCOPY; ++c) {
+    int* p = count + (size_t)c * (n + 1) + i;
+    const int v = *p;
+    *p = start;
+    start += v;
+  }
 }
 
 // Scatter each particle's payload (x, y, z, signed weight) to its slot in tile order.
 __global__ void k_tile_scatter(const int* __restrict__ tile_of, const int* __restrict__ rank, int64_t nd, int64_t n,
-                               const int* __restrict__ off, const double* __restrict__ dpos,
+                               int ntiles, const int* __restrict__ start, const double* __restrict__ dpos,
                                const double* __restrict__ dw, const double* __restrict__ rpos,
                                const double* __restrict__ rw, double alpha, double4* __restrict__ payload) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -170,7 +192,9 @@ __global__ void k_tile_scatter(const int* __restrict__ tile_of, const int* __res
     p.y = pos[3 * k + 1];
     p.z = pos[3 * k + 2];
     p.w = (wp ? wp[k] : 1.0) * (isd ? 1.0 : -alpha);
-    payload[off[tile_of[i]] + rank[i]] = p;
+    const int r = rank[i];
+    const int copy = (int)((unsigned)r >> RANK_BITS);
+    payload[start[(size_t)copy * (ntiles + 1) + tile_of[i]] + (r & ((1 << RANK_BITS) - 1))] = p;
   }
 }
 
@@ -243,7 +267,10 @@ __global__ void __launch_bounds__(256) k_paint_tiles(const int* __restrict__ off
                                                      double o0, double o1, double o2, double scale, int nmesh, int ts,
                                                      T* __restrict__ d1, T* __restrict__ d2) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int tile = blockIdx.x;
+  // XCD-aware order: each XCD paints a contiguous run of tiles (a slab of the mesh), so the
+  // halo cells that neighbouring tiles both flush are updated within one L2
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int tile = nb % 8 ? b : (b % 8) * (nb / 8) + b / 8;
   const int start = off[tile], end = off[tile + 1];
   if (start == end) return;
   const int rsz = ts + 4;
@@ -316,24 +343,25 @@ hipError_t launch_tile_sort(const double* pos, int64_t n, int64_t base, const do
   if (n <= 0) return hipSuccess;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 16384) blocks = 16384;
+  const int tpa = nmesh / ts;
   k_tile_count<<<(unsigned)blocks, 256, 0, s>>>(pos, n, base, origin[0], origin[1], origin[2], scale, nmesh, ts,
-                                                count, tile_of, rank);
+                                                tpa * tpa * tpa, count, tile_of, rank);
   return hipGetLastError();
 }
 
-hipError_t launch_tile_offsets(const int* count, int ntiles, int* off, const int* tile_of, const int* rank,
+hipError_t launch_tile_offsets(int* count, int ntiles, int* off, const int* tile_of, const int* rank,
                                int64_t nd, int64_t ntot, const double* dpos, const double* dw, const double* rpos,
                                const double* rw, double alpha, void* payload, int* bsum, hipStream_t s) {
   const int nblk = (ntiles + SCAN_THREADS - 1) / SCAN_THREADS;
   k_scan_blocks<<<nblk, SCAN_THREADS, 0, s>>>(count, ntiles, off, bsum);
   k_scan_sums<<<1, SCAN_THREADS, 0, s>>>(bsum, nblk, off, ntiles);
-  k_scan_add<<<nblk, SCAN_THREADS, 0, s>>>(bsum, ntiles, off);
+  k_scan_add<<<nblk, SCAN_THREADS, 0, s>>>(bsum, ntiles, off, count);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ntot == 0) return e;
   int64_t blocks = (ntot + 255) / 256;
   if (blocks > 16384) blocks = 16384;
-  k_tile_scatter<<<(unsigned)blocks, 256, 0, s>>>(tile_of, rank, nd, ntot, off, dpos, dw, rpos, rw, alpha,
-                                                  (double4*)payload);
+  k_tile_scatter<<<(unsigned)blocks, 256, 0, s>>>(tile_of, rank, nd, ntot, ntiles, count, dpos, dw, rpos, rw,
+                                                  alpha, (double4*)payload);
   return hipGetLastError();
 }
 

@@ -417,7 +417,7 @@ template <typename T> void enqueue_paint(pkm_plan* pl, const DevCats& dc) {
   const double alpha = alpha_of(dc.nd, dc.nr);
   {
     StageScope ss(pl, PKM_STAGE_FILL);
-    check_hip(pl, launch_fill<int>(pl->tile_count, (size_t)pl->ntiles, 0, s), "fill");
+    check_hip(pl, launch_fill<int>(pl->tile_count, (size_t)TILE_COUNT_COPIES * (pl->ntiles + 1), 0, s), "fill");
     check_hip(pl, launch_fill<T>(d1, cells, T(0), s), "fill");
     if (d2) check_hip(pl, launch_fill<T>(d2, cells, T(0), s), "fill");
   }
@@ -1078,7 +1078,7 @@ pkm_status pkm_plan_create(const pkm_params* p, const pkm_device* dev, pkm_plan*
     }
     while (n % pl->ts) pl->ts /= 2;
     pl->ntiles = (n / pl->ts) * (n / pl->ts) * (n / pl->ts);
-    pl->tile_count = (int*)dalloc(pl, sizeof(int) * (pl->ntiles + 1));
+    pl->tile_count = (int*)dalloc(pl, sizeof(int) * (size_t)TILE_COUNT_COPIES * (pl->ntiles + 1));
     pl->tile_off = (int*)dalloc(pl, sizeof(int) * (pl->ntiles + 1));
     pl->scan_sums = (int*)dalloc(pl, sizeof(int) * tile_scan_scratch(pl->ntiles));
     int want = fields_for(pl->p.ell_max_hint);
