@@ -262,19 +262,19 @@ __device__ __forceinline__ void tile_scatter(double* __restrict__ reg, T* __rest
   }
 }
 
-template <typename T, int W>
+template <typename T, int W, int TS>
 __global__ void __launch_bounds__(256) k_paint_tiles(const int* __restrict__ off, const double4* __restrict__ payload,
-                                                     double o0, double o1, double o2, double scale, int nmesh, int ts,
+                                                     double o0, double o1, double o2, double scale, int nmesh,
                                                      T* __restrict__ d1, T* __restrict__ d2) {
+  constexpr int ts = TS;
   extern __shared__ __align__(16) unsigned char smem[];
-  // XCD-aware order: each XCD paints a contiguous run of tiles (a slab of the mesh), so the
-  // halo cells that neighbouring tiles both flush are updated within one L2
-  const int nb = gridDim.x, b = blockIdx.x;
-  const int tile = nb % 8 ? b : (b % 8) * (nb / 8) + b / 8;
+  // natural tile order: consecutive tiles land on different XCDs, which spreads the dense
+  // survey region evenly (measured faster than XCD-local orders that keep halos in one L2)
+  const int tile = blockIdx.x;
   const int start = off[tile], end = off[tile + 1];
   if (start == end) return;
-  const int rsz = ts + 4;
-  const int rcells = rsz * rsz * rsz;
+  constexpr int rsz = ts + 4;
+  constexpr int rcells = rsz * rsz * rsz;
   double* r1 = reinterpret_cast<double*>(smem);   // FP64 accumulation for both precisions
   double* r2 = r1 + rcells;
   const int nreg = d2 ? 2 : 1;
@@ -311,10 +311,13 @@ __global__ void __launch_bounds__(256) k_paint_tiles(const int* __restrict__ off
     for (int i = threadIdx.x; i < rcells; i += blockDim.x) {
       const T v = (T)reg[i];
       if (v == T(0)) continue;
+      // region node (ra, rb, rc) is mesh node t0 - 1 + (ra, rb, rc), wrapped once at most
       const int rc = i % rsz, rb = (i / rsz) % rsz, ra = i / (rsz * rsz);
-      const size_t g = ((size_t)wrap(t0[0] - 1 + ra, nmesh) * nmesh + wrap(t0[1] - 1 + rb, nmesh)) * nmesh +
-                       wrap(t0[2] - 1 + rc, nmesh);
-      unsafeAtomicAdd(&mesh[g], v);
+      int gx = t0[0] - 1 + ra, gy = t0[1] - 1 + rb, gz = t0[2] - 1 + rc;
+      gx += gx < 0 ? nmesh : (gx >= nmesh ? -nmesh : 0);
+      gy += gy < 0 ? nmesh : (gy >= nmesh ? -nmesh : 0);
+      gz += gz < 0 ? nmesh : (gz >= nmesh ? -nmesh : 0);
+      unsafeAtomicAdd(&mesh[((size_t)gx * nmesh + gy) * nmesh + gz], v);
     }
   }
 }
@@ -368,20 +371,19 @@ hipError_t launch_tile_offsets(int* count, int ntiles, int* off, const int* tile
 template <typename T>
 hipError_t launch_paint_tiles(const int* off, const void* payload, int ntiles, const double* origin, double scale,
                               int nmesh, int window, int ts, T* d1, T* d2, hipStream_t s) {
-  const int rsz = ts + 4;
-  const size_t sm = sizeof(double) * (size_t)rsz * rsz * rsz * (d2 ? 2 : 1);
-  if (window == 1)
-    k_paint_tiles<T, 1><<<ntiles, 256, sm, s>>>(off, (const double4*)payload, origin[0], origin[1], origin[2],
-                                                scale, nmesh, ts, d1, d2);
-  else if (window == 2)
-    k_paint_tiles<T, 2><<<ntiles, 256, sm, s>>>(off, (const double4*)payload, origin[0], origin[1], origin[2],
-                                                scale, nmesh, ts, d1, d2);
-  else if (window == 3)
-    k_paint_tiles<T, 3><<<ntiles, 256, sm, s>>>(off, (const double4*)payload, origin[0], origin[1], origin[2],
-                                                scale, nmesh, ts, d1, d2);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  const size_t sm = sizeof(double) * (size_t)(ts + 4) * (ts + 4) * (ts + 4) * (d2 ? 2 : 1);
+  const double4* pl = (const double4*)payload;
+#define PKM_PAINT(WV, TV)                                                                                    \
+  if (window == WV && ts == TV) {                                                                            \
+    k_paint_tiles<T, WV, TV><<<ntiles, 256, sm, s>>>(off, pl, origin[0], origin[1], origin[2], scale, nmesh, d1, \
+                                                    d2);                                                     \
+    return hipGetLastError();                                                                                \
+  }
+  PKM_PAINT(1, 4) PKM_PAINT(2, 4) PKM_PAINT(3, 4)
+  PKM_PAINT(1, 8) PKM_PAINT(2, 8) PKM_PAINT(3, 8)
+  PKM_PAINT(1, 16) PKM_PAINT(2, 16) PKM_PAINT(3, 16)
+#undef PKM_PAINT
+  return hipErrorInvalidValue;
 }
 
 template hipError_t launch_paint_tiles<float>(const int*, const void*, int, const double*, double, int, int, int,
