@@ -360,7 +360,9 @@ template <typename T, int NV> __device__ __forceinline__ void yrun_init(YRun<T, 
   s.l = -1;
 }
 
-template <typename T, int NV>
+// PAIRS: advance the recurrence two degrees per iteration (fewer register copies, more
+// registers live); off for register-bound callers.
+template <typename T, int NV, bool PAIRS = true>
 __device__ __forceinline__ void yrun_eval(YRun<T, NV>& s, int ell, int m, const T* ux, const T* uy, const T* uz,
                                           T* out, const T* __restrict__ tab) {
   const int am = m < 0 ? -m : m;
@@ -385,9 +387,21 @@ __device__ __forceinline__ void yrun_eval(YRun<T, NV>& s, int ell, int m, const 
     s.l = am;
   }
   const T* c = tab + am * YLM_STRIDE;
-  for (int l = s.l + 1; l <= ell; ++l) {
+  int l = s.l + 1;
+  // two degrees per iteration with the pair's roles swapped in between (no register copies)
+  for (; PAIRS && l + 1 <= ell; l += 2) {
     const int j = l - am;
-    const T a = c[2 * j - 1], b = c[2 * j];  // b = 0 for j = 1
+    const T a1 = c[2 * j - 1], b1 = c[2 * j];  // b = 0 for j = 1
+    const T a2 = c[2 * j + 1], b2 = c[2 * j + 2];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      s.q0[v] = a1 * uz[v] * s.q1[v] - b1 * s.q0[v];  // q_l
+      s.q1[v] = a2 * uz[v] * s.q0[v] - b2 * s.q1[v];  // q_{l+1}
+    }
+  }
+  for (; l <= ell; ++l) {
+    const int j = l - am;
+    const T a = c[2 * j - 1], b = c[2 * j];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const T q2 = a * uz[v] * s.q1[v] - b * s.q0[v];
@@ -396,8 +410,13 @@ __device__ __forceinline__ void yrun_eval(YRun<T, NV>& s, int ell, int m, const 
     }
   }
   s.l = ell;
+  if (m < 0) {  // m is the same for the whole wave
 #pragma unroll
-  for (int v = 0; v < NV; ++v) out[v] = s.q1[v] * (m < 0 ? s.ci[v] : s.cr[v]);
+    for (int v = 0; v < NV; ++v) out[v] = s.q1[v] * s.ci[v];
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] = s.q1[v] * s.cr[v];
+  }
 }
 
 // Atomic add to an LDS location (native ds_add_f32 / ds_add_f64; a plain atomicAdd through a

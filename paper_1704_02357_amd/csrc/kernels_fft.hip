@@ -398,17 +398,18 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n_rt, int g_rt, uint3
   const int ix = (int)(lineg / n), iy = (int)(lineg % n);
   const T px = (T)(off0 + ix * h), py = (T)(off1 + iy * h);
   const T pxy2 = px * px + py * py;
+  // a node at the observer has no direction: its weighted value is zero for every field
   T ux[2 * E], uy[2 * E], uz[2 * E];
-  bool zero[2 * E];
 #pragma unroll
   for (int q = 0; q < 2 * E; ++q) {
     const T pz = (T)(off2 + (2 * (t + pt * (q >> 1)) + (q & 1)) * h);
     const T rr = sqrt(pxy2 + pz * pz);
-    zero[q] = !(rr > T(0));
-    const T inv = zero[q] ? T(0) : T(1) / rr;
+    const bool zero = !(rr > T(0));
+    const T inv = zero ? T(0) : T(1) / rr;
     ux[q] = px * inv;
     uy[q] = py * inv;
     uz[q] = pz * inv;
+    if (zero) r[q] = T(0);
   }
   YRun<T, 2 * E> yr;
   yrun_init(yr);
@@ -417,11 +418,7 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n_rt, int g_rt, uint3
     yrun_eval<T, 2 * E>(yr, fields[4 * f + 1], fields[4 * f + 2], ux, uy, uz, yv, ytab);
     cx<T> u[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const T y0 = zero[2 * e] ? T(0) : yv[2 * e];
-      const T y1 = zero[2 * e + 1] ? T(0) : yv[2 * e + 1];
-      u[e] = mk<T>(r[2 * e] * y0, r[2 * e + 1] * y1);
-    }
+    for (int e = 0; e < E; ++e) u[e] = mk<T>(r[2 * e] * yv[2 * e], r[2 * e + 1] * yv[2 * e + 1]);
     xf_regs<T, E, false, ZPAD, NC / 2, WAVE>(lds, g * lp, 1, rt, t, u, twst, twl);
     // the split needs X_k and X_{nh-k}: park the line in LDS (own slots), then read
 #pragma unroll
@@ -593,7 +590,7 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
       const int slot = fields[4 * f + 3];
       {
         T yv[E];
-        yrun_eval<T, E>(yr, fields[4 * f + 1], fields[4 * f + 2], ux, uy, uz, yv, ytab);
+        yrun_eval<T, E, false>(yr, fields[4 * f + 1], fields[4 * f + 2], ux, uy, uz, yv, ytab);
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[e] = mk<T>(acc[e].x + yv[e] * u[e].x, acc[e].y + yv[e] * u[e].y);
       }
