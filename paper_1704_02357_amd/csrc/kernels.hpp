@@ -84,13 +84,13 @@ hipError_t launch_zpre(const FftShape& fs, const void* g_in, const T* real_in, T
                        int nf, const int* fields_dev, double scale, const double* off, double h, const void* ytab,
                        const void* tw, hipStream_t s);
 
-// x-pass of every field of the group, sum over m of Y_lm(khat) B_lm per multipole slot,
-// product with C and binning.  Per block the partial sums are rows of nb bins:
+// Last transform pass of every field of the group (along x for axis 0, along y for axis 1),
+// sum over m of Y_lm(khat) B_lm per multipole slot, product with C and binning.  Per block the partial sums are rows of nb bins:
 // [count, sum |k|, sum |C|^2] when with_l0, then one row of sum 4 pi Y Re[C conj B] per slot.
 template <typename T>
 hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const int* fields_dev, int nslots,
                         int with_l0, const void* c_in, const void* ytab, const BinSpec& bs, double kf,
-                        double* partial, int* nblocks_out, const void* tw, hipStream_t s);
+                        double* partial, int* nblocks_out, const void* tw, int axis, hipStream_t s);
 
 // out[map[v]] (+)= sum_b partial[b*nvals + v] (map null -> identity), fixed order.
 hipError_t launch_reduce(const double* partial, int nblocks, int nvals, double* out, const int* map, int accumulate,

@@ -505,7 +505,7 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
                                                           const T* __restrict__ ytab,
                                                           const long long* __restrict__ thr, int nb, int copies,
                                                           double* __restrict__ partial,
-                                                          const cx<T>* __restrict__ tw) {
+                                                          const cx<T>* __restrict__ tw, int axis) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = NC > 0 ? NC : n_rt;
   const int tile = TC > 0 ? TC : tile_rt;
@@ -525,8 +525,11 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
   hist_zero(hist, copies * nvals);
   for (int i = threadIdx.x; i <= nb; i += blockDim.x) thr_l[i] = thr[i];
   if constexpr (NC > 0) ct_twiddles<T, E, NC, NC>(twst, tw); else stage_twiddles<T>(twl, tw, n);
+  // axis 0: the transform runs along x (rows x, tiles over y); axis 1: along y (rows y, tiles
+  // over x).  Rows are n*nh (axis 0) or nh (axis 1) elements apart.
   const int tiles_x = nh / tile;
-  const size_t rs = (size_t)n * nh;
+  const size_t rs = axis ? (size_t)nh : (size_t)n * nh;
+  const size_t os = axis ? (size_t)n * nh : (size_t)nh;
   const int tid = threadIdx.x;
   // rows fastest across the lanes of a wave: a column's transform stays inside one wave
   const int t = tid % pt, c = tid / pt;
@@ -534,7 +537,7 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
   const LineRt rt{n, sched, nst, pt, n};
   const TileWalk walk(n * tiles_x);
   __syncthreads();  // histogram zeroed, thresholds and twiddles staged
-  auto base_of = [&](int tl) { return (size_t)(tl / tiles_x) * nh + (size_t)(tl % tiles_x) * tile; };
+  auto base_of = [&](int tl) { return (size_t)(tl / tiles_x) * os + (size_t)(tl % tiles_x) * tile; };
   cx<T> nxt[E];
   int j = walk.first;
   if (j < walk.end && nf > 0)
@@ -542,11 +545,11 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
   int parity = 0;
   for (; j < walk.end; j += walk.step) {
     const int tl = walk.tile(j);
-    const int y = tl / tiles_x;
+    const int o = tl / tiles_x;  // the tile's fixed x (axis 1) or y (axis 0) index
     const int kz = (tl % tiles_x) * tile + c;
     const size_t base = base_of(tl);
-    const int fy = sfreq(y, n);
-    const bool ynyq = (y == nh);
+    const int fo = sfreq(o, n);
+    const bool onyq = (o == nh);
     const double w4pi = ((kz == 0) ? 1.0 : 2.0) * FOUR_PI;
     // per element: k bin (-1 when the mode is excluded), C, unit wave vector
     int bin[E];
@@ -557,14 +560,14 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
       bool excl[E];
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const int x = t + pt * e;
-        const int fx = sfreq(x, n);
-        n2[e] = fx * fx + fy * fy + kz * kz;
-        excl[e] = ynyq || x == nh || n2[e] == 0;
+        const int x = t + pt * e;  // row index along the transform axis
+        const int fr = sfreq(x, n);
+        n2[e] = fr * fr + fo * fo + kz * kz;
+        excl[e] = onyq || x == nh || n2[e] == 0;
         cv[e] = gload<T>(cin, base + c + (size_t)x * rs);
         const T ki = n2[e] > 0 ? T(1) / sqrt((T)n2[e]) : T(0);
-        ux[e] = (T)fx * ki;
-        uy[e] = (T)fy * ki;
+        ux[e] = (T)(axis ? fo : fr) * ki;
+        uy[e] = (T)(axis ? fr : fo) * ki;
         uz[e] = (T)kz * ki;
       }
       kbins_lds<E>(thr_l, nb, n2, excl, bin);
@@ -610,8 +613,8 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         if (bin[e] < 0) continue;
-        const int fx = sfreq(t + pt * e, n);
-        const int n2 = fx * fx + fy * fy + kz * kz;
+        const int fr = sfreq(t + pt * e, n);
+        const int n2 = fr * fr + fo * fo + kz * kz;
         lds_atomic_add<double>(&h[bin[e]], w);
         lds_atomic_add<double>(&h[nb + bin[e]], w * kf * sqrt((double)n2));
         lds_atomic_add<double>(&h[2 * nb + bin[e]],
@@ -836,7 +839,7 @@ hipError_t launch_zpre(const FftShape& fs, const void* g_in, const T* real_in, T
 template <typename T>
 hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const int* fields_dev, int nslots,
                         int with_l0, const void* c_in, const void* ytab, const BinSpec& bs, double kf,
-                        double* partial, int* nblocks_out, const void* tw, hipStream_t s) {
+                        double* partial, int* nblocks_out, const void* tw, int axis, hipStream_t s) {
   if (nslots < 0) return hipErrorInvalidValue;
   const int rows = (with_l0 ? 3 : 0) + nslots;
   const size_t sm = xpost_base_bytes(fs, sizeof(T) == 8) + sizeof(double) * (size_t)bs.hist_copies * rows * bs.nb +
@@ -847,11 +850,11 @@ hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const
   *nblocks_out = nblk;
   PKM_TRY_POST((k_xpost<T, E, NC, TC><<<nblk, nthr, sm, s>>>(
       fs.n, fs.tile_post, fs.sched_post, fs.nst_post, bufs_dev, nf, fields_dev, nslots, with_l0, kf,
-      (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies, partial, (const cx<T>*)tw)));
+      (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies, partial, (const cx<T>*)tw, axis)));
   PKM_DISPATCH_E(fs.e_post, (k_xpost<T, E, 0, 0><<<nblk, nthr, sm, s>>>(
                                 fs.n, fs.tile_post, fs.sched_post, fs.nst_post, bufs_dev, nf, fields_dev, nslots,
                                 with_l0, kf, (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies,
-                                partial, (const cx<T>*)tw)));
+                                partial, (const cx<T>*)tw, axis)));
   return hipGetLastError();
 }
 
@@ -880,7 +883,7 @@ hipError_t launch_kmu(const FftShape& fs, const void* c_in, const double* los, c
   template hipError_t launch_zpre<T>(const FftShape&, const void*, const T*, T*, void* const*, int, const int*,   \
                                      double, const double*, double, const void*, const void*, hipStream_t);       \
   template hipError_t launch_xpost<T>(const FftShape&, void* const*, int, const int*, int, int, const void*,     \
-                                      const void*, const BinSpec&, double, double*, int*, const void*,           \
+                                      const void*, const BinSpec&, double, double*, int*, const void*, int,      \
                                       hipStream_t);                                                              \
   template hipError_t launch_kmu<T>(const FftShape&, const void*, const double*, const BinSpec&, const double*,   \
                                     int, double*, int, hipStream_t);

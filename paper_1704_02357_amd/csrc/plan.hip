@@ -627,6 +627,7 @@ template <typename T> void enqueue_compute(pkm_plan* pl) {
                          pl->p.box_origin[2] - pl->p.observer[2]};
   const double h = pl->p.box_len / n;
   const double dc_scale = 2.0 / ((double)n * n * n);
+  const int post_axis = pl->fp64 ? 1 : 0;
   for (size_t gi = 0; gi < cc.groups.size(); ++gi) {
     const GroupCfg& gc = cc.groups[gi];
     const int* ft = pl->ftab_dev + 4 * gc.fofs;
@@ -638,16 +639,20 @@ template <typename T> void enqueue_compute(pkm_plan* pl) {
                                      gc.nf, ft, dc_scale, off, h, pl->ytab, pl->tw, s),
                   "zpre");
       }
+      // the column pass takes the axis the post-pass does not: FP64 fields take their x pass
+      // here and their y pass in the post-pass (whose rows are then nh, not n nh, elements
+      // apart: measured faster for FP64, slower for FP32)
       StageScope ss(pl, PKM_STAGE_YCOL);
-      check_hip(pl, launch_col<T>(pl->fs, pl->ptrs_dev, gc.nf, 1, false, pl->tw, s), "field y pass");
+      check_hip(pl, launch_col<T>(pl->fs, pl->ptrs_dev, gc.nf, post_axis == 1 ? 0 : 1, false, pl->tw, s),
+                "field column pass");
     }
     int nblocks = 0;
     {
       StageScope ss(pl, PKM_STAGE_XPOST);
       check_hip(pl, launch_xpost<T>(pl->fs, pl->ptrs_dev, gc.nf, ftp, gc.nslots, gi == 0 ? 1 : 0, pl->c, pl->ytab,
                                     BinSpec{pl->thr_dev, cc.nb, gc.copies}, (double)(2.0 * M_PI / pl->p.box_len),
-                                    pl->partial, &nblocks, pl->tw, s),
-                "xpost");
+                                    pl->partial, &nblocks, pl->tw, post_axis, s),
+                "post-pass");
     }
     StageScope ss(pl, PKM_STAGE_REDUCE);
     check_hip(pl, launch_reduce(pl->partial, nblocks, gc.nv, pl->out_dev, pl->map_dev + gc.mofs, 1, s), "reduce");
