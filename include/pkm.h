@@ -160,12 +160,39 @@ typedef struct {
 
 typedef struct pkm_plan pkm_plan;
 
+/* Launch shape of the passes.  A zero field keeps the built-in choice for the mesh size and
+ * precision.  e_col / e_z / e_post are elements per thread of the length-N column passes,
+ * the length-N/2 z passes and the post-pass (4, 6, 8, 12 or 16 with a radix schedule for
+ * the length); tile / tile_post are kz columns per block of the column passes and the
+ * post-pass; zlines is z lines per block; paint_tile is the painting tile side (4, 8, 16);
+ * post_axis chooses the last transform axis of the weighted fields (1: along x, 2: along y,
+ * i.e. the stored value is the axis + 1 so that zero keeps the default).  A shape that breaks
+ * a kernel limit (threads per block, LDS bytes, divisibility) is rejected with PKM_EINVAL.  */
+typedef struct {
+  int32_t e_col, tile, e_z, zlines, e_post, tile_post, paint_tile, post_axis;
+} pkm_shape;
+
 int pkm_abi_version(void);
 const char* pkm_status_str(pkm_status s);
 
 /* Validate the parameters, build twiddle / harmonic / compensation tables and allocate the
  * plan's device buffers.  *out is set only on success.                                     */
 pkm_status pkm_plan_create(const pkm_params* p, const pkm_device* dev, pkm_plan** out);
+
+/* pkm_plan_create with a launch shape (NULL = built-in); pkm_plan_shape reports the shape a
+ * plan runs with (every field filled in).                                                   */
+pkm_status pkm_plan_create_shaped(const pkm_params* p, const pkm_device* dev, const pkm_shape* shape,
+                                  pkm_plan** out);
+pkm_status pkm_plan_shape(const pkm_plan* plan, pkm_shape* out);
+
+/* Autotuner: times candidate launch shapes on a seeded synthetic catalog of n_particles
+ * objects (1/21 data, 20/21 randoms, uniform in the box) for estimates up to ell_max, one
+ * group of passes at a time (painting tile, z passes, column passes, post-pass and its
+ * axis), each candidate `reps` times after one warm-up, keeping the fastest per group.
+ * Writes the chosen shape, the device time of one estimate with it and with the built-in
+ * shape (ms; either pointer may be NULL).  Synchronous; creates and frees its own plans.   */
+pkm_status pkm_autotune(const pkm_params* p, const pkm_device* dev, int32_t ell_max, int64_t n_particles,
+                        int32_t reps, pkm_shape* best, double* best_ms, double* default_ms);
 
 /* Sec. 2.1 (eq. FKP-density) and Sec. 2.3: catalog scalars, painting of data minus
  * alpha x randoms (randoms NULL -> periodic box), forward transforms, interlace combine,

@@ -22,7 +22,12 @@ struct FftShape {
   int nst_post;
   int tile_post;    // columns per post-pass tile
   int cus;          // compute units of the device (0: unknown)
+  int post_axis;    // last transform axis of the weighted fields: 0 = x, 1 = y
 };
+
+// Bytes of LDS of the z-pass and column-pass blocks of a shape.
+size_t zpass_smem_bytes(const FftShape& fs, bool fp64);
+size_t colpass_smem_bytes(const FftShape& fs, bool fp64);
 
 // LDS bytes of a post-pass block without its histograms.
 size_t xpost_base_bytes(const FftShape& fs, bool fp64);

@@ -719,6 +719,10 @@ int post_blocks(const FftShape& fs) {
   return std::min(tiles, 2 * cus);
 }
 static size_t colsmem(const FftShape& fs, size_t cs) { return cs * ((size_t)fs.n * (fs.tile + 1) + fs.n); }
+size_t zpass_smem_bytes(const FftShape& fs, bool fp64) { return zsmem(fs, fp64 ? sizeof(double2) : sizeof(float2)); }
+size_t colpass_smem_bytes(const FftShape& fs, bool fp64) {
+  return colsmem(fs, fp64 ? sizeof(double2) : sizeof(float2));
+}
 size_t xpost_base_bytes(const FftShape& fs, bool fp64) {
   const size_t cs = fp64 ? sizeof(double2) : sizeof(float2);
   return cs * (2 * (size_t)xrows(fs.n) * (fs.tile_post + 1) + fs.n);

@@ -627,7 +627,7 @@ template <typename T> void enqueue_compute(pkm_plan* pl) {
                          pl->p.box_origin[2] - pl->p.observer[2]};
   const double h = pl->p.box_len / n;
   const double dc_scale = 2.0 / ((double)n * n * n);
-  const int post_axis = pl->fp64 ? 1 : 0;
+  const int post_axis = pl->fs.post_axis;
   for (size_t gi = 0; gi < cc.groups.size(); ++gi) {
     const GroupCfg& gc = cc.groups[gi];
     const int* ft = pl->ftab_dev + 4 * gc.fofs;
@@ -849,8 +849,67 @@ bool make_shape(const pkm_params& p, FftShape* out) {
   int zl = 1;
   while (zl * 2 * pt_z <= 256 && ((size_t)n * n) % (zl * 2) == 0) zl *= 2;
   fs.zlines = zl;
+  // FP64 fields finish along y (rows nh apart): measured faster; FP32 along x
+  fs.post_axis = fp64 ? 1 : 0;
   *out = fs;
   return true;
+}
+
+bool is_elem(int e) { return e == 4 || e == 6 || e == 8 || e == 12 || e == 16; }
+
+// Override the built-in shape with the non-zero fields of `sh`, checking every kernel limit.
+bool apply_shape(const pkm_params& p, const pkm_shape& sh, FftShape* fs, int* ts, std::string* why) {
+  const int n = p.nmesh, nh = n / 2;
+  const bool fp64 = p.precision == PKM_FP64;
+  FftShape f = *fs;
+  auto fail = [&](const char* m) { *why = m; return false; };
+  if (sh.e_col) {
+    if (!is_elem(sh.e_col) || !make_sched(n, sh.e_col, &f.sched_col, &f.nst_col)) return fail("bad e_col");
+    f.e_col = sh.e_col;
+  }
+  if (sh.tile) f.tile = sh.tile;
+  if (f.tile < 1 || nh % f.tile || (n / f.e_col) * f.tile > 512 || colpass_smem_bytes(f, fp64) > 160 * 1024)
+    return fail("column-pass tile breaks a kernel limit");
+  if (sh.e_z) {
+    if (!is_elem(sh.e_z) || !make_sched(nh, sh.e_z, &f.sched_z, &f.nst_z)) return fail("bad e_z");
+    f.e_z = sh.e_z;
+  }
+  if (sh.zlines) f.zlines = sh.zlines;
+  if (f.zlines < 1 || ((size_t)n * n) % f.zlines || (nh / f.e_z) * f.zlines > 256 ||
+      zpass_smem_bytes(f, fp64) > 160 * 1024)
+    return fail("z-pass lines break a kernel limit");
+  if (sh.e_post) {
+    if (!is_elem(sh.e_post) || !make_sched(n, sh.e_post, &f.sched_post, &f.nst_post)) return fail("bad e_post");
+    f.e_post = sh.e_post;
+  }
+  if (sh.tile_post) f.tile_post = sh.tile_post;
+  if (f.tile_post < 1 || nh % f.tile_post || (n / f.e_post) * f.tile_post > 256 ||
+      xpost_base_bytes(f, fp64) > 150 * 1024)
+    return fail("post-pass tile breaks a kernel limit");
+  if (sh.post_axis) {
+    if (sh.post_axis != 1 && sh.post_axis != 2) return fail("post_axis must be 1 (x) or 2 (y)");
+    f.post_axis = sh.post_axis - 1;
+  }
+  if (sh.paint_tile) {
+    if ((sh.paint_tile != 4 && sh.paint_tile != 8 && sh.paint_tile != 16) || n % sh.paint_tile)
+      return fail("paint_tile must be 4, 8 or 16 and divide nmesh");
+    *ts = sh.paint_tile;
+  }
+  *fs = f;
+  return true;
+}
+
+pkm_shape shape_of(const FftShape& fs, int ts) {
+  pkm_shape sh{};
+  sh.e_col = fs.e_col;
+  sh.tile = fs.tile;
+  sh.e_z = fs.e_z;
+  sh.zlines = fs.zlines;
+  sh.e_post = fs.e_post;
+  sh.tile_post = fs.tile_post;
+  sh.paint_tile = ts;
+  sh.post_axis = fs.post_axis + 1;
+  return sh;
 }
 
 pkm_status validate_params(const pkm_params* p, std::string* why) {
@@ -1038,10 +1097,20 @@ const char* pkm_status_str(pkm_status s) {
 }
 
 pkm_status pkm_plan_create(const pkm_params* p, const pkm_device* dev, pkm_plan** out) {
+  return pkm_plan_create_shaped(p, dev, nullptr, out);
+}
+
+pkm_status pkm_plan_create_shaped(const pkm_params* p, const pkm_device* dev, const pkm_shape* shape,
+                                  pkm_plan** out) {
   if (!out) return PKM_EINVAL;
   std::string why;
   pkm_status st = validate_params(p, &why);
   if (st != PKM_OK) return st;
+  FftShape fs0{};
+  int ts0 = 8;
+  if (!make_shape(*p, &fs0)) return PKM_EINVAL;
+  while (p->nmesh % ts0) ts0 /= 2;
+  if (shape && !apply_shape(*p, *shape, &fs0, &ts0, &why)) return PKM_EINVAL;
   pkm_plan* pl = new (std::nothrow) pkm_plan();
   if (!pl) return PKM_ENOMEM;
   pl->p = *p;
@@ -1052,10 +1121,7 @@ pkm_status pkm_plan_create(const pkm_params* p, const pkm_device* dev, pkm_plan*
   pl->es = pl->fp64 ? 8 : 4;
   const int n = p->nmesh;
   pl->mesh_bytes = pl->es * (size_t)n * n * n;
-  if (!make_shape(*p, &pl->fs)) {
-    delete pl;
-    return PKM_EINVAL;
-  }
+  pl->fs = fs0;
   {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->dev.device_id) == hipSuccess)
@@ -1076,12 +1142,7 @@ pkm_status pkm_plan_create(const pkm_params* p, const pkm_device* dev, pkm_plan*
     pl->phase = dalloc(pl, 2 * pl->es * n);
     pl->ytab = dalloc(pl, pl->es * (YLM_LMAX + 1) * YLM_STRIDE);
     pl->sums_dev = (double*)dalloc(pl, sizeof(double) * (4 + 2 * SUM_BLOCKS));
-    pl->ts = 8;
-    if (const char* e = std::getenv("PKM_PAINT_TILE")) {  // tuning override: 4, 8 or 16
-      const int v = std::atoi(e);
-      if (v == 4 || v == 8 || v == 16) pl->ts = v;
-    }
-    while (n % pl->ts) pl->ts /= 2;
+    pl->ts = ts0;
     pl->ntiles = (n / pl->ts) * (n / pl->ts) * (n / pl->ts);
     pl->tile_count = (int*)dalloc(pl, sizeof(int) * (size_t)TILE_COUNT_COPIES * (pl->ntiles + 1));
     pl->tile_off = (int*)dalloc(pl, sizeof(int) * (pl->ntiles + 1));
@@ -1235,6 +1296,145 @@ pkm_status pkm_plan_read_buffer(pkm_plan* pl, int32_t which, void* host, size_t 
     else if (pl->fp64) read_dc<double>(pl, host, bytes);
     else read_dc<float>(pl, host, bytes);
   });
+}
+
+pkm_status pkm_plan_shape(const pkm_plan* pl, pkm_shape* out) {
+  if (!pl || !out) return PKM_EINVAL;
+  *out = shape_of(pl->fs, pl->ts);
+  return PKM_OK;
+}
+
+pkm_status pkm_autotune(const pkm_params* p, const pkm_device* dev, int32_t ell_max, int64_t n_particles,
+                        int32_t reps, pkm_shape* best, double* best_ms, double* default_ms) {
+  std::string why;
+  if (validate_params(p, &why) != PKM_OK) return PKM_EINVAL;
+  if (ell_max < 0 || ell_max > 16 || ell_max % 2 || n_particles < 22 || reps < 1) return PKM_EINVAL;
+  const int n = p->nmesh, nh = n / 2;
+  const double L = p->box_len;
+  pkm_device d{};
+  if (dev) d = *dev;
+  if (hipSetDevice(d.device_id) != hipSuccess) return PKM_EDEVICE;
+  // synthetic catalog: uniform in the box, 1/21 data and 20/21 randoms (seeded)
+  const int64_t nd = std::max<int64_t>(1, n_particles / 21), nr = n_particles - nd;
+  std::vector<double> hpos(3 * (size_t)n_particles), hw((size_t)n_particles, 1.0),
+      hn((size_t)n_particles, (double)nd / (L * L * L));
+  uint64_t state = 0x9E3779B97F4A7C15ull;
+  for (double& v : hpos) {  // splitmix64 -> uniform [0, 1)
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    v = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+  }
+  for (int64_t i = 0; i < n_particles; ++i)
+    for (int a = 0; a < 3; ++a) hpos[3 * i + a] = p->box_origin[a] + hpos[3 * i + a] * L;
+  pkm_catalog dc{hpos.data(), hw.data(), hn.data(), nd, 0};
+  pkm_catalog rc{hpos.data() + 3 * nd, hw.data() + nd, hn.data() + nd, nr, 0};
+  std::vector<double> edges;
+  const double kf = 2.0 * M_PI / L;
+  for (double k = 0.0; k < M_PI * n / L; k += 4.0 * kf) edges.push_back(k);
+  if (edges.size() < 2) edges.push_back(M_PI * n / L);
+  const int nb = (int)edges.size() - 1;
+  std::vector<double> poles((size_t)(ell_max / 2 + 1) * nb), kmean(nb);
+  std::vector<int64_t> nmodes(nb);
+  // device ms per stage of one estimate with a shape (negative: shape rejected or failed)
+  auto time_shape = [&](const pkm_shape& sh, double* stage_ms) -> double {
+    pkm_plan* pl = nullptr;
+    pkm_params pp = *p;
+    if (pp.ell_max_hint < ell_max) pp.ell_max_hint = ell_max;
+    if (pkm_plan_create_shaped(&pp, &d, &sh, &pl) != PKM_OK) return -1.0;
+    pkm_result r{poles.data(), kmean.data(), nmodes.data(), 0, 0, 0, 0};
+    double total = -1.0;
+    if (pkm_paint(pl, &dc, &rc) == PKM_OK && pkm_compute_multipoles(pl, ell_max, edges.data(), nb + 1, &r) == PKM_OK) {
+      pkm_set_stage_timing(pl, 1);
+      pkm_reset_stats(pl);
+      bool ok = true;
+      for (int k = 0; k < reps && ok; ++k)
+        ok = pkm_paint(pl, &dc, &rc) == PKM_OK && pkm_compute_multipoles(pl, ell_max, edges.data(), nb + 1, &r) == PKM_OK;
+      if (ok) {
+        total = 0.0;
+        for (int st = 0; st < PKM_NSTAGES; ++st) {
+          stage_ms[st] = pl->stats.stage_ms[st] / reps;
+          total += stage_ms[st];
+        }
+      }
+    }
+    pkm_plan_destroy(pl);
+    return total;
+  };
+  double ms[PKM_NSTAGES];
+  pkm_shape cur{};
+  const double base = time_shape(cur, ms);
+  if (base < 0) return PKM_EDEVICE;
+  auto group_ms = [&](const double* m, std::initializer_list<int> st) {
+    double t = 0;
+    for (int i : st) t += m[i];
+    return t;
+  };
+  // one group at a time: keep the candidate with the smallest time over the group's stages
+  auto tune = [&](std::vector<pkm_shape> cands, std::initializer_list<int> stages) {
+    double best_t = -1.0;
+    pkm_shape keep = cur;
+    for (const pkm_shape& c : cands) {
+      double m[PKM_NSTAGES];
+      if (time_shape(c, m) < 0) continue;
+      const double t = group_ms(m, stages);
+      if (best_t < 0 || t < best_t) { best_t = t; keep = c; }
+    }
+    cur = keep;
+  };
+  {
+    std::vector<pkm_shape> c;
+    for (int ts : {4, 8, 16}) { pkm_shape s2 = cur; s2.paint_tile = ts; c.push_back(s2); }
+    tune(c, {PKM_STAGE_PAINT});
+  }
+  {
+    std::vector<pkm_shape> c;
+    for (int e : {4, 8, 16})
+      for (int zl = 1; zl <= 64; zl *= 2) {
+        if ((nh / e) * zl > 256 || (nh / e) * zl < 64) continue;
+        pkm_shape s2 = cur; s2.e_z = e; s2.zlines = zl; c.push_back(s2);
+      }
+    tune(c, {PKM_STAGE_ZFWD, PKM_STAGE_ZPRE});
+  }
+  {
+    std::vector<pkm_shape> c;
+    for (int e : {4, 8, 16})
+      for (int tl : {4, 8, 16}) {
+        if ((n / e) * tl > 512 || (n / e) * tl < 64) continue;
+        pkm_shape s2 = cur; s2.e_col = e; s2.tile = tl; c.push_back(s2);
+      }
+    tune(c, {PKM_STAGE_YCOL, PKM_STAGE_XCOMBINE, PKM_STAGE_IYCOL});
+  }
+  {
+    std::vector<pkm_shape> c;
+    for (int e : {4, 8})
+      for (int tl : {1, 2, 4, 8, 16})
+        for (int ax : {1, 2}) {
+          if ((n / e) * tl > 256 || (n / e) * tl < 64) continue;
+          pkm_shape s2 = cur; s2.e_post = e; s2.tile_post = tl; s2.post_axis = ax; c.push_back(s2);
+        }
+    tune(c, {PKM_STAGE_YCOL, PKM_STAGE_XPOST});
+  }
+  double m[PKM_NSTAGES];
+  double tuned = time_shape(cur, m);
+  if (tuned < 0 || tuned > base) {  // no gain over the built-in shape
+    cur = pkm_shape{};
+    tuned = base;
+  }
+  // report the full shape the choice resolves to
+  {
+    FftShape fs{};
+    int ts = 8;
+    make_shape(*p, &fs);
+    while (n % ts) ts /= 2;
+    apply_shape(*p, cur, &fs, &ts, &why);
+    if (best) *best = shape_of(fs, ts);
+  }
+  if (best_ms) *best_ms = tuned;
+  if (default_ms) *default_ms = base;
+  return PKM_OK;
 }
 
 pkm_status pkm_prepare(pkm_plan* pl, int32_t ell_max, const double* k_edges, int32_t n_edges,

@@ -52,6 +52,18 @@ class Device(C.Structure):
                 ("alloc_ctx", C.c_void_p)]
 
 
+class Shape(C.Structure):
+    _fields_ = [(f, C.c_int32) for f in ("e_col", "tile", "e_z", "zlines", "e_post", "tile_post", "paint_tile",
+                                          "post_axis")]
+
+
+def _shape(d):
+    sh = Shape()
+    for f, _ in Shape._fields_:
+        setattr(sh, f, int((d or {}).get(f, 0)))
+    return sh
+
+
 class ServerConfig(C.Structure):
     _fields_ = [("device_id", C.c_int32), ("hbm_budget_bytes", C.c_int64), ("max_inflight", C.c_int32)]
 
@@ -113,6 +125,10 @@ def load_library():
         "pkm_fft3d_inverse": (C.c_int, [P, P, P]),
         "pkm_plan_read_buffer": (C.c_int, [P, C.c_int32, P, C.c_size_t]),
         "pkm_prepare": (C.c_int, [P, C.c_int32, P, C.c_int32, C.c_int64]),
+        "pkm_plan_create_shaped": (C.c_int, [C.POINTER(Params), C.POINTER(Device), C.POINTER(Shape), C.POINTER(P)]),
+        "pkm_plan_shape": (C.c_int, [P, C.POINTER(Shape)]),
+        "pkm_autotune": (C.c_int, [C.POINTER(Params), C.POINTER(Device), C.c_int32, C.c_int64, C.c_int32,
+                                   C.POINTER(Shape), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "pkm_enqueue": (C.c_int, [P, C.POINTER(Catalog), C.POINTER(Catalog)]),
         "pkm_query": (C.c_int, [P]),
         "pkm_finish": (C.c_int, [P, C.POINTER(Result)]),
@@ -225,7 +241,7 @@ class Plan:
 
     def __init__(self, nmesh: int, box_len: float, *, box_origin=None, observer=(0.0, 0.0, 0.0), window=TSC,
                  interlaced=True, compensated=True, precision=FP32, ell_max_hint=4, max_group=0, los=None,
-                 device: int = 0, stream=None, torch_allocator: bool = True):
+                 device: int = 0, stream=None, torch_allocator: bool = True, shape=None):
         self.lib = load_library()
         p = make_params(nmesh, box_len, box_origin=box_origin, observer=observer, window=window,
                         interlaced=interlaced, compensated=compensated, precision=precision,
@@ -245,9 +261,11 @@ class Plan:
             d.free = self._alloc.c_free
         self.dev = d
         h = C.c_void_p()
-        st = self.lib.pkm_plan_create(C.byref(p), C.byref(d), C.byref(h))
+        sh = _shape(shape) if shape else None
+        st = self.lib.pkm_plan_create_shaped(C.byref(p), C.byref(d), C.byref(sh) if sh is not None else None,
+                                             C.byref(h))
         if st:
-            raise PkmError(st, "pkm_plan_create failed")
+            raise PkmError(st, "pkm_plan_create failed" + (" (shape rejected)" if shape and st == 1 else ""))
         self.h = h
         self._keep = []
 
@@ -336,6 +354,11 @@ class Plan:
         out["stage_ms"] = {STAGES[i]: s.stage_ms[i] for i in range(10)}
         out["stage_launches"] = {STAGES[i]: int(s.stage_launches[i]) for i in range(10)}
         return out
+
+    def shape(self) -> dict:
+        sh = Shape()
+        self._check(self.lib.pkm_plan_shape(self.h, C.byref(sh)), "pkm_plan_shape")
+        return {f: getattr(sh, f) for f, _ in Shape._fields_}
 
     def set_stage_timing(self, on: bool):
         self._check(self.lib.pkm_set_stage_timing(self.h, int(bool(on))), "pkm_set_stage_timing")
@@ -502,3 +525,39 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def autotune(nmesh, box_len, *, ell_max=4, n_particles=None, reps=2, device=0, cache=None, **params) -> dict:
+    """Pick launch shapes by timing (pkm_autotune); keyword arguments as for Plan.  With
+    `cache` (a JSON file path) results are stored per device and configuration and reused."""
+    import json
+    key = None
+    if cache:
+        import torch
+        cfg = dict(params, nmesh=int(nmesh), box_len=float(box_len), ell_max=int(ell_max))
+        key = json.dumps({"device": torch.cuda.get_device_name(device), **{k: cfg[k] for k in sorted(cfg)}},
+                         default=str)
+        try:
+            with open(cache) as f:
+                db = json.load(f)
+        except (OSError, ValueError):
+            db = {}
+        if key in db:
+            return db[key]
+    lib = load_library()
+    p = make_params(nmesh, box_len, ell_max_hint=max(ell_max, params.pop("ell_max_hint", 0)), **params)
+    d = Device()
+    d.device_id = device
+    n_particles = int(n_particles or min(2_000_000, 8 * int(nmesh) ** 3 // 64))
+    best, bms, dms = Shape(), C.c_double(), C.c_double()
+    st = lib.pkm_autotune(C.byref(p), C.byref(d), int(ell_max), n_particles, int(reps), C.byref(best), C.byref(bms),
+                          C.byref(dms))
+    if st:
+        raise PkmError(st, "pkm_autotune failed")
+    out = {f: getattr(best, f) for f, _ in Shape._fields_}
+    out.update(ms=bms.value, default_ms=dms.value)
+    if cache:
+        db[key] = out
+        with open(cache, "w") as f:
+            json.dump(db, f, indent=1)
+    return out

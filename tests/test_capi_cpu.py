@@ -80,3 +80,21 @@ def test_plan_create_rejects_bad_params(field, value):
     h = C.c_void_p()
     assert lib.pkm_plan_create(C.byref(p), None, C.byref(h)) == 1
     assert not h.value
+
+
+def test_shape_validation_rejects_before_device():
+    """Launch shapes that break a kernel limit are refused with PKM_EINVAL before any device
+    work (so this runs without a GPU)."""
+    lib = _lib()
+    from paper_1704_02357_amd.pkm import Device, Shape, make_params
+    p = make_params(64, 300.0, observer=(0.0, 0.0, -500.0))
+    d = Device()
+    bad = [dict(tile=3), dict(e_col=5), dict(e_col=12), dict(paint_tile=32), dict(post_axis=3),
+           dict(e_z=8, zlines=128), dict(e_post=4, tile_post=32), dict(zlines=3)]
+    for b in bad:
+        sh = Shape()
+        for k, v in b.items():
+            setattr(sh, k, v)
+        h = C.c_void_p()
+        st = lib.pkm_plan_create_shaped(C.byref(p), C.byref(d), C.byref(sh), C.byref(h))
+        assert st == 1, (b, st)

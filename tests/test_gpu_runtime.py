@@ -195,3 +195,49 @@ def test_server_budget_admission(gpu):
     with pytest.raises(PkmError):
         sv.wait(big)
     sv.close()
+
+
+SHAPES = {  # per mesh size: power-of-two and 3-smooth schedules
+    64: [dict(e_col=4, tile=4, e_z=4, zlines=4, e_post=4, tile_post=2, paint_tile=4, post_axis=2),
+         dict(e_col=8, tile=8, e_z=8, zlines=2, e_post=8, tile_post=4, paint_tile=16, post_axis=1),
+         dict(e_col=16, tile=2, e_post=4, tile_post=8, post_axis=2)],
+    48: [dict(e_col=12, tile=4, e_z=6, zlines=8, e_post=6, tile_post=4, paint_tile=8, post_axis=2),
+         dict(e_col=6, tile=8, e_z=12, zlines=2, e_post=12, tile_post=2, paint_tile=4, post_axis=1),
+         dict(e_col=6, tile=2, e_z=6, zlines=16, e_post=6, tile_post=8, post_axis=2)],
+}
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("n", [48, 64])
+@pytest.mark.parametrize("si", range(3))
+def test_shaped_plan_matches_oracle(gpu, prec, n, si):
+    """Non-default launch shapes (generic kernels, other tiles, radix-3 schedules, the other
+    post-pass axis) give the oracle's multipoles to the precision form's tolerance."""
+    from oracle.estimator import multipoles
+    from tests.parity_util import assert_pole_parity, oracle_params
+    shape = dict(SHAPES[n][si])
+    d, r = small_catalogs(3000, 20000, L, seed=400 + si)
+    p = _plan(n, prec, 4, shape=shape)
+    print(f"[shape] n={n} prec={prec} {p.shape()}", flush=True)
+    p.paint(d, r)
+    got = p.compute_multipoles(4, _edges(n))
+    ref = multipoles(d, r, oracle_params(n, L, OBS, 3, True, True), 4, _edges(n))
+    assert_pole_parity(got, ref, prec, f"shape {si} n={n}")
+    p.close()
+
+
+def test_autotune_picks_valid_shape_and_caches(gpu, tmp_path):
+    from paper_1704_02357_amd import autotune
+    cache = str(tmp_path / "tune.json")
+    kw = dict(observer=OBS, window=3, interlaced=True, compensated=True, precision=0)
+    t = autotune(64, L, ell_max=4, n_particles=60000, reps=1, cache=cache, **kw)
+    print(f"[autotune] {t}", flush=True)
+    assert t["ms"] > 0 and t["default_ms"] > 0 and t["ms"] <= t["default_ms"] * 1.0000001
+    shape = {k: v for k, v in t.items() if k not in ("ms", "default_ms")}
+    p = _plan(64, 0, 4, shape=shape)
+    assert p.shape() == shape
+    d, r = small_catalogs(3000, 20000, L, seed=77)
+    p.paint(d, r)
+    _same(p.compute_multipoles(4, _edges(64)), _alone(64, 0, 4, d, r), 0, "tuned shape")
+    p.close()
+    assert autotune(64, L, ell_max=4, n_particles=60000, reps=1, cache=cache, **kw) == t
