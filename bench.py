@@ -114,13 +114,17 @@ def summarize_profile(directory: str) -> None:
 
 
 def run_form(precision: int, data, rand, edges, steps: int, warmup: int):
+    """One estimate per step through the asynchronous calls: pkm_prepare once, then per step
+    pkm_enqueue (paint, every transform, all (l, m) fields, binning; no host wait inside) and
+    pkm_finish (wait, normalise).  Per-launch HIP events on the plan's stream time each stage."""
     import torch
     from paper_1704_02357_amd import Plan
     plan = Plan(NMESH, BOX, observer=OBSERVER, window=3, interlaced=True, compensated=True, precision=precision,
                 ell_max_hint=ELL_MAX)
+    plan.prepare(ELL_MAX, edges, int(data[0].shape[0] + rand[0].shape[0]))
     for _ in range(warmup):
-        plan.paint(data, rand)
-        res = plan.compute_multipoles(ELL_MAX, edges)
+        plan.enqueue(data, rand)
+        res = plan.finish()
     plan.reset_stats()
     plan.set_stage_timing(True)
     lat = []
@@ -128,8 +132,8 @@ def run_form(precision: int, data, rand, edges, steps: int, warmup: int):
     t0 = time.perf_counter()
     for _ in range(steps):
         s0 = time.perf_counter()
-        plan.paint(data, rand)
-        res = plan.compute_multipoles(ELL_MAX, edges)
+        plan.enqueue(data, rand)
+        res = plan.finish()
         lat.append(time.perf_counter() - s0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()

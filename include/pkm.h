@@ -256,8 +256,11 @@ pkm_status pkm_plan_read_buffer(pkm_plan* plan, int32_t which, void* host_dst, s
  * pkm_enqueue     enqueues one whole estimate (paint, transforms, multipoles, and the copy
  *                 of the bin sums to the plan's pinned staging) on the plan's stream and
  *                 returns without waiting.  Catalogs must be device-resident (on_device = 1)
- *                 and stay valid and unmodified until pkm_finish returns.  Allocates nothing,
- *                 issues no synchronous HIP call: the enqueue may be captured into a graph.
+ *                 and stay valid and unmodified until pkm_finish returns.  Allocates no device
+ *                 memory and issues no synchronous HIP call: the enqueue may be captured into a
+ *                 graph (with stage timing off; with it on, the plan's per-launch timing events
+ *                 are recorded too, the first enqueues may create them, and pkm_finish adds the
+ *                 times to pkm_stats).
  *                 PKM_EBUSY if a previous enqueue has not been finished; PKM_EORDER if the
  *                 plan is not prepared; PKM_EINVAL above the reserved particle count.
  * pkm_query       PKM_OK when the enqueued estimate has completed, PKM_EBUSY while it runs.

@@ -21,7 +21,9 @@ int64_t device_bytes(const pkm_plan* pl);
 std::string& error_of(pkm_plan* pl);
 // One whole estimate of device catalogs, results to a pinned host slot; no allocation, no
 // host wait (capturable).
-pkm_status enqueue(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* randoms, double* slot);
+// `timed`: record the plan's per-launch timing events when stage timing is on (never inside
+// a graph capture).
+pkm_status enqueue(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* randoms, double* slot, bool timed);
 // Normalise a completed slot into `out` (the prepared ell_max and edges).
 void finish(pkm_plan* pl, const double* slot, int64_t nd, int64_t nr, pkm_result* out);
 // Device bytes a plan with these parameters would hold for one request (admission control).

@@ -1030,7 +1030,7 @@ std::string& error_of(pkm_plan* pl) { return pl->err; }
 
 // Enqueue one estimate of device catalogs with its results copied to `slot` (pinned host,
 // slot_doubles(pl) doubles).  No allocation, no host wait: safe inside stream capture.
-pkm_status enqueue(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* randoms, double* slot) {
+pkm_status enqueue(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* randoms, double* slot, bool timed) {
   if (validate_pair(pl, data, randoms) != PKM_OK) return PKM_EINVAL;
   if (!data->on_device || (randoms && !randoms->on_device)) {
     pl->err = "asynchronous estimates take device-resident catalogs";
@@ -1041,8 +1041,9 @@ pkm_status enqueue(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* ran
     pl->err = "particle count above the prepared capacity";
     return PKM_EINVAL;
   }
+  // per-launch timing events only when asked for and not recorded into a graph
   const bool timing = pl->stage_timing;
-  pl->stage_timing = false;
+  pl->stage_timing = timing && timed;
   pkm_status st = guarded(pl, [&] {
     DevCats dc;
     dc.dp = data->pos; dc.dw = data->w; dc.dn = data->nbar; dc.nd = data->n;
@@ -1449,7 +1450,7 @@ pkm_status pkm_enqueue(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog*
   if (!data) { pl->err = "data catalog is NULL"; return PKM_EINVAL; }
   pkm_status st = guarded(pl, [&] { check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice"); });
   if (st != PKM_OK) return st;
-  st = pkm_internal::enqueue(pl, data, randoms, pl->slot);
+  st = pkm_internal::enqueue(pl, data, randoms, pl->slot, true);
   if (st != PKM_OK) return st;
   st = guarded(pl, [&] { check_hip(pl, hipEventRecord(pl->done, pl->stream), "event"); });
   if (st != PKM_OK) return st;
@@ -1476,6 +1477,7 @@ pkm_status pkm_finish(pkm_plan* pl, pkm_result* out) {
   pkm_status st = guarded(pl, [&] { check_hip(pl, hipEventSynchronize(pl->done), "event synchronize"); });
   pl->pending_async = false;
   if (st != PKM_OK) return st;
+  resolve_stages(pl);
   finish_from_slot(pl, pl->slot, pl->pend_nd, pl->pend_nr, out);
   pl->alpha = out->alpha;
   pl->norm_I = out->norm_I;

@@ -111,7 +111,8 @@ pkm_status issue(pkm_batch* b) {
     if ((e = hipStreamWaitEvent(s, b->fork, 0)) != hipSuccess) return hip_fail(b, e, "stream wait");
   for (size_t i = 0; i < b->items.size(); ++i) {
     BatchItem& it = b->items[i];
-    const pkm_status st = pkm_internal::enqueue(it.plan, &it.data, it.has_rand ? &it.rand : nullptr, it.slot->p);
+    const pkm_status st =
+        pkm_internal::enqueue(it.plan, &it.data, it.has_rand ? &it.rand : nullptr, it.slot->p, false);
     if (st != PKM_OK) {
       b->err = "item " + std::to_string(i) + ": " + pkm_internal::error_of(it.plan);
       return st;
@@ -477,7 +478,7 @@ bool admit_head(pkm_server* sv, std::unique_lock<std::mutex>& lk) {
   if (st == PKM_OK) {
     pkm_catalog d{}, rr{};
     catalogs_of(r.get(), use, &d, &rr);
-    st = pkm_internal::enqueue(use->plan, &d, r->has_rand ? &rr : nullptr, use->result.p);
+    st = pkm_internal::enqueue(use->plan, &d, r->has_rand ? &rr : nullptr, use->result.p, false);
     if (st != PKM_OK) r->err = pkm_internal::error_of(use->plan);
   }
   if (st == PKM_OK && (hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess ||
