@@ -394,21 +394,24 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n_rt, int g_rt, uint3
     }
   }
   if (nf == 0) return;
-  // unit vectors from the observer to this thread's nodes (x, y fixed by the line)
+  // unit vectors from the observer to this thread's nodes (x, y fixed by the line), formed
+  // in FP64 and rounded once: in FP32 the distance to a far observer rounds the same way for
+  // whole planes of nodes, and the slope of high-degree harmonics near the pole would turn
+  // that common bias into a systematic error of the multipoles
   const int ix = (int)(lineg / n), iy = (int)(lineg % n);
-  const T px = (T)(off0 + ix * h), py = (T)(off1 + iy * h);
-  const T pxy2 = px * px + py * py;
+  const double px = off0 + ix * h, py = off1 + iy * h;
+  const double pxy2 = px * px + py * py;
   // a node at the observer has no direction: its weighted value is zero for every field
   T ux[2 * E], uy[2 * E], uz[2 * E];
 #pragma unroll
   for (int q = 0; q < 2 * E; ++q) {
-    const T pz = (T)(off2 + (2 * (t + pt * (q >> 1)) + (q & 1)) * h);
-    const T rr = sqrt(pxy2 + pz * pz);
-    const bool zero = !(rr > T(0));
-    const T inv = zero ? T(0) : T(1) / rr;
-    ux[q] = px * inv;
-    uy[q] = py * inv;
-    uz[q] = pz * inv;
+    const double pz = off2 + (2 * (t + pt * (q >> 1)) + (q & 1)) * h;
+    const double rr = sqrt(pxy2 + pz * pz);
+    const bool zero = !(rr > 0.0);
+    const double inv = zero ? 0.0 : 1.0 / rr;
+    ux[q] = (T)(px * inv);
+    uy[q] = (T)(py * inv);
+    uz[q] = (T)(pz * inv);
     if (zero) r[q] = T(0);
   }
   YRun<T, 2 * E> yr;

@@ -9,6 +9,7 @@ from .lognormal import (  # noqa: F401
     SurveyGeometry,
     lognormal_survey,
     uniform_box,
+    modulated_box,
     uniform_survey_randoms,
     config_c1,
     config_c2,

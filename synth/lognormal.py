@@ -206,6 +206,28 @@ def uniform_box(box_len: float, n: int, seed: int, origin=None) -> Catalog:
     return Catalog(pos, np.ones(n), None)
 
 
+def modulated_box(box_len: float, n: int, seed: int, j: int, amp: float, origin=None) -> Catalog:
+    """Poisson catalog in a periodic box whose mean density is modulated in the (x, y) plane,
+    n(x) proportional to 1 + amp [cos(2 pi j x'/L) + cos(2 pi j y'/L)] / 2 with x' = x - o,
+    the transverse systematic of the cubic-box test in Sec. 3.2 (drawn by rejection; the
+    modulation puts its power on the four modes j k_f along x and y, all at mu = 0 for a line of
+    sight along z).  0 <= amp <= 1."""
+    if not 0.0 <= amp <= 1.0:
+        raise ValueError("amp must be in [0, 1]")
+    rng = np.random.default_rng(seed)
+    o = np.full(3, -0.5 * box_len) if origin is None else np.asarray(origin, dtype=np.float64)
+    out = []
+    have = 0
+    while have < n:
+        u = rng.random((max(2 * (n - have), 1024), 3))
+        p = (1.0 + 0.5 * amp * (np.cos(2 * np.pi * j * u[:, 0]) + np.cos(2 * np.pi * j * u[:, 1]))) / (1.0 + amp)
+        keep = u[rng.random(u.shape[0]) < p]
+        out.append(keep[: n - have])
+        have += out[-1].shape[0]
+    pos = o + np.concatenate(out) * box_len
+    return Catalog(pos, np.ones(n), None)
+
+
 # Named workloads -------------------------------------------------------------------------
 
 def config_c1(seed: int = 1704, n_gal: int = 30_000):
