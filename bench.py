@@ -273,6 +273,51 @@ def batch_bench(args) -> dict:
             "max_scaled_err_vs_sequential": max(errs)}
 
 
+def basis_bench(args) -> dict:
+    """Sec. 2.1's transform-count comparison measured as device time: the multipole pass
+    (everything after painting) of the 512^3 workload through the spherical-harmonic
+    decomposition and through the Cartesian one, l <= 4 and l <= 16, on one painted plan."""
+    import torch
+    from paper_1704_02357_amd import CARTESIAN, SPHERICAL, Plan
+    from synth import config_c2
+    data, rand, info = config_c2(n_gal=args.ngal, random_factor=args.random_factor)
+    n, L = 512, 2500.0
+    edges = np.arange(int(math.floor(math.pi * n / L / 0.01)) + 1, dtype=np.float64) * 0.01
+    rows = []
+    for prec in (0, 1):
+        # 64 weighted fields resident at a time, the same for both decompositions
+        plan = Plan(n, L, observer=OBSERVER, window=3, interlaced=True, compensated=True, precision=prec,
+                    ell_max_hint=16, max_group=64)
+        plan.paint(data, rand)
+        for lmax in (4, 16):
+            for basis, name in ((SPHERICAL, "spherical"), (CARTESIAN, "cartesian")):
+                reps = max(1, min(args.steps, 10 if lmax == 4 else 3))
+                r = plan.compute_multipoles(lmax, edges, basis=basis)   # warm-up (tables, buffers)
+                ms = []
+                for _ in range(reps):
+                    r = plan.compute_multipoles(lmax, edges, basis=basis)
+                    ms.append(plan.stats()["ms_compute"])
+                nf = r["n_transforms"] - 3
+                rows.append({"precision": "f64" if prec else "f32", "ell_max": lmax, "basis": name,
+                             "weighted_fields": nf, "ms_compute": round(float(np.median(ms)), 3),
+                             "ms_per_field": round(float(np.median(ms)) / nf, 4)})
+                log(f"[basis] {rows[-1]}")
+        plan.close()
+        torch.cuda.empty_cache()
+    ratios = {}
+    for prec in ("f32", "f64"):
+        for lmax in (4, 16):
+            sp = next(x for x in rows if x["precision"] == prec and x["ell_max"] == lmax and x["basis"] == "spherical")
+            ca = next(x for x in rows if x["precision"] == prec and x["ell_max"] == lmax and x["basis"] == "cartesian")
+            ratios[f"{prec}_l{lmax}"] = {"fields_ratio": round(ca["weighted_fields"] / sp["weighted_fields"], 3),
+                                         "time_ratio": round(ca["ms_compute"] / sp["ms_compute"], 3)}
+    return {"metric": "multipole-pass device time by decomposition of L_l (512^3, after painting)",
+            "unit": "ms", "higher_is_better": False, "n_gpus": 1, "rows": rows, "cartesian_over_spherical": ratios,
+            "data": "synthetic (seeded lognormal survey mock, resident in HBM)",
+            "config": {"workload": "512^3 mesh, L=2500 Mpc/h, 1e6 galaxies + 2e7 randoms, TSC + interlacing + "
+                                   "compensation, 0.01 h/Mpc bins, at most 64 weighted fields resident"}}
+
+
 def serve_bench(args) -> dict:
     """Poisson-arrival request stream mixing Nmesh 256-768, l_max 4/8/16, 1e5-3e6 galaxies
     (2x randoms), FP32 and FP64, through the serving loop; throughput and latency."""
@@ -345,8 +390,9 @@ def main():
                     help="run a plain 1 GiB device copy (x3) first, to calibrate HBM byte counters")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="print the kernel summary of a rocprofv3 CSV output directory and exit")
-    ap.add_argument("--mode", choices=["estimate", "batch", "serve"], default="estimate",
-                    help="estimate: the 512^3 l<=4 line (default); batch: covariance mocks; serve: request stream")
+    ap.add_argument("--mode", choices=["estimate", "batch", "serve", "basis"], default="estimate",
+                    help="estimate: the 512^3 l<=4 line (default); batch: covariance mocks; serve: request stream; "
+                         "basis: spherical against Cartesian decomposition")
     ap.add_argument("--mocks", type=int, default=64)
     ap.add_argument("--requests", type=int, default=48)
     ap.add_argument("--rate", type=float, default=1.0, help="request arrivals per second (serve mode)")
@@ -364,7 +410,7 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     if args.mode != "estimate":
-        out = batch_bench(args) if args.mode == "batch" else serve_bench(args)
+        out = {"batch": batch_bench, "serve": serve_bench, "basis": basis_bench}[args.mode](args)
         print(json.dumps(out), flush=True)
         return
     if args.calib_copy:

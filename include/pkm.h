@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define PKM_ABI_VERSION 2
+#define PKM_ABI_VERSION 3
 
 typedef enum {
   PKM_OK = 0,
@@ -205,6 +205,24 @@ pkm_status pkm_paint(pkm_plan* plan, const pkm_catalog* data, const pkm_catalog*
  * Requires a prior pkm_paint (else PKM_EORDER).                                           */
 pkm_status pkm_compute_multipoles(pkm_plan* plan, int32_t ell_max, const double* k_edges, int32_t n_edges,
                                   pkm_result* out);
+
+/* The same multipoles through either decomposition of L_l(khat . xhat) named in Sec. 2.1:
+ *   PKM_BASIS_SPHERICAL  the addition theorem (eq. add-theorem, eq. Fell): 2l+1 transforms
+ *                        per l; identical to pkm_compute_multipoles.
+ *   PKM_BASIS_CARTESIAN  the Cartesian decomposition the paper compares against: L_l is
+ *                        expanded in powers (khat . xhat)^p and each power into monomials,
+ *                        (p+1)(p+2)/2 transforms per even degree p >= 2, shared by every l
+ *                        (22 transforms in all for l <= 4, 525 for l <= 16, against 15 and
+ *                        153).  The degree sums are combined with the Legendre coefficients
+ *                        on the host in FP64; the cancellation among those coefficients
+ *                        (their absolute sum is 8.5 at l = 4 and 1.7e5 at l = 16)
+ *                        multiplies the rounding error of the FP32 form by as much.
+ * Arguments, outputs and errors as pkm_compute_multipoles; other basis values: PKM_EINVAL.
+ * out->n_transforms counts the transforms of the chosen basis.                              */
+#define PKM_BASIS_SPHERICAL 0
+#define PKM_BASIS_CARTESIAN 1
+pkm_status pkm_compute_multipoles_basis(pkm_plan* plan, int32_t ell_max, const double* k_edges, int32_t n_edges,
+                                        int32_t basis, pkm_result* out);
 
 /* Fixed line of sight (the plan's `los`): P(k_i, mu_j) = sum |C|^2 / (I N_ij) - S over the
  * modes with mu = |khat . los| in [mu_j, mu_{j+1}) (mu = 1 in the last bin).  Outputs are

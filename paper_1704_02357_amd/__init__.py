@@ -5,6 +5,6 @@ The numerical work runs in the HIP library ``libpkm.so`` (C ABI in ``include/pkm
 this package only marshals arguments (``pkm.py``) and builds the library (``build.py``).
 """
 from .pkm import (  # noqa: F401
-    ABI_VERSION, CIC, NGP, TSC, FP32, FP64, Batch, Plan, PkmError, Server, autotune, lib_path, load_library,
+    ABI_VERSION, CIC, NGP, TSC, FP32, FP64, SPHERICAL, CARTESIAN, Batch, Plan, PkmError, Server, autotune, lib_path, load_library,
     nonuniform_mu_edges, wedges,
 )

@@ -350,6 +350,40 @@ constexpr int YLM_STRIDE = 2 * YLM_LMAX + 2;
 // nothing, and a field with |m| one larger costs one complex multiply plus a restart of the
 // recurrence.  Fields in any other order restart from scratch (still correct).  Control flow
 // depends only on (l, m), which are wave-uniform.
+// Cartesian decomposition (Sec. 2.1, the monomial form the spherical-harmonic expansion
+// replaces): a field of degree p is weighted by the monomial u_x^i u_y^j u_z^(p-i-j), its
+// index packed as code = 32 i + j.  out = coef * monomial for NV directions.
+__host__ __device__ constexpr int cart_code(int i, int j) { return 32 * i + j; }
+
+template <typename T, int NV>
+__device__ __forceinline__ void monomial_eval(int p, int code, T coef, const T* ux, const T* uy, const T* uz,
+                                              T* out) {
+  const int i = code >> 5, j = code & 31, k = p - i - j;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[v] = coef;
+  for (int q = 0; q < i; ++q) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] *= ux[v];
+  }
+  for (int q = 0; q < j; ++q) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] *= uy[v];
+  }
+  for (int q = 0; q < k; ++q) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] *= uz[v];
+  }
+}
+
+// p! / (i! j! (p-i-j)!), exact in integers for p <= 16 (at most 2018016)
+__device__ __forceinline__ int multinomial(int p, int code) {
+  const int i = code >> 5, j = code & 31;
+  long long c = 1;
+  for (int q = 1; q <= i; ++q) c = c * (p - i + q) / q;          // binom(p, i)
+  for (int q = 1; q <= j; ++q) c = c * (p - i - j + q) / q;      // binom(p - i, j)
+  return (int)c;
+}
+
 template <typename T, int NV> struct YRun {
   T cr[NV], ci[NV], q0[NV], q1[NV];
   int am, l;

@@ -83,19 +83,22 @@ hipError_t launch_xcombine(const FftShape& fs, void* s1, void* s2, void* c_out, 
 // Inverse z (half-complex to real) of G, scaled to D_c, then for every field f in the group
 // the Y_lm(xhat)-weighted forward transform along z into bufs[f].  If real_in != null the
 // field D_c is read directly from that real mesh instead.  If real_out != null D_c is also
-// written there.
+// written there.  basis 1 (Cartesian decomposition): field f is weighted by the monomial
+// xhat^a of degree fields[4f+1] and index code fields[4f+2] instead of Y_lm(xhat).
 template <typename T>
 hipError_t launch_zpre(const FftShape& fs, const void* g_in, const T* real_in, T* real_out, void* const* bufs_dev,
                        int nf, const int* fields_dev, double scale, const double* off, double h, const void* ytab,
-                       const void* tw, hipStream_t s);
+                       const void* tw, int basis, hipStream_t s);
 
 // Last transform pass of every field of the group (along x for axis 0, along y for axis 1),
 // sum over m of Y_lm(khat) B_lm per multipole slot, product with C and binning.  Per block the partial sums are rows of nb bins:
 // [count, sum |k|, sum |C|^2] when with_l0, then one row of sum 4 pi Y Re[C conj B] per slot.
+// basis 1: the slot sums (p!/a!) khat^a B_a over the monomials a of one degree p, and its row
+// holds sum Re[C conj (that sum)] without the 4 pi.
 template <typename T>
 hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const int* fields_dev, int nslots,
                         int with_l0, const void* c_in, const void* ytab, const BinSpec& bs, double kf,
-                        double* partial, int* nblocks_out, const void* tw, int axis, hipStream_t s);
+                        double* partial, int* nblocks_out, const void* tw, int axis, int basis, hipStream_t s);
 
 // out[map[v]] (+)= sum_b partial[b*nvals + v] (map null -> identity), fixed order.
 hipError_t launch_reduce(const double* partial, int nblocks, int nvals, double* out, const int* map, int accumulate,

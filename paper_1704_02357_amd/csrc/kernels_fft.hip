@@ -340,7 +340,7 @@ __global__ void __launch_bounds__(XMAX_THREADS) k_xcombine(int n_rt, int tile_rt
 // Each line is handled by the threads of one wavefront (compile-time path), so the field
 // loop needs no block barrier.
 // ------------------------------------------------------------------------------------------
-template <typename T, int E, int NC, int TC>
+template <typename T, int E, int NC, int TC, bool CART = false>
 __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n_rt, int g_rt, uint32_t sched, int nst,
                                                         const cx<T>* __restrict__ gin, const T* __restrict__ real_in,
                                                         T* __restrict__ real_out, void* const* __restrict__ bufs,
@@ -418,7 +418,10 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n_rt, int g_rt, uint3
   yrun_init(yr);
   for (int f = 0; f < nf; ++f) {
     T yv[2 * E];
-    yrun_eval<T, 2 * E>(yr, fields[4 * f + 1], fields[4 * f + 2], ux, uy, uz, yv, ytab);
+    if constexpr (CART)
+      monomial_eval<T, 2 * E>(fields[4 * f + 1], fields[4 * f + 2], T(1), ux, uy, uz, yv);
+    else
+      yrun_eval<T, 2 * E>(yr, fields[4 * f + 1], fields[4 * f + 2], ux, uy, uz, yv, ytab);
     cx<T> u[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) u[e] = mk<T>(r[2 * e] * yv[2 * e], r[2 * e + 1] * yv[2 * e + 1]);
@@ -500,7 +503,7 @@ __device__ __forceinline__ void kbins_lds(const long long* thr, int nb, const in
   }
 }
 
-template <typename T, int E, int NC, int TC>
+template <typename T, int E, int NC, int TC, bool CART = false>
 __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, uint32_t sched, int nst,
                                                           void* const* __restrict__ bufs, int nf,
                                                           const int* __restrict__ fields, int nslots, int with_l0,
@@ -553,7 +556,8 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
     const size_t base = base_of(tl);
     const int fo = sfreq(o, n);
     const bool onyq = (o == nh);
-    const double w4pi = ((kz == 0) ? 1.0 : 2.0) * FOUR_PI;
+    // Hermitian weight; the spherical sum also carries the 4 pi of the addition theorem
+    const double w4pi = ((kz == 0) ? 1.0 : 2.0) * (CART ? 1.0 : FOUR_PI);
     // per element: k bin (-1 when the mode is excluded), C, unit wave vector
     int bin[E];
     cx<T> cv[E];
@@ -596,7 +600,11 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
       const int slot = fields[4 * f + 3];
       {
         T yv[E];
-        yrun_eval<T, E, false>(yr, fields[4 * f + 1], fields[4 * f + 2], ux, uy, uz, yv, ytab);
+        if constexpr (CART)
+          monomial_eval<T, E>(fields[4 * f + 1], fields[4 * f + 2], (T)multinomial(fields[4 * f + 1], fields[4 * f + 2]),
+                              ux, uy, uz, yv);
+        else
+          yrun_eval<T, E, false>(yr, fields[4 * f + 1], fields[4 * f + 2], ux, uy, uz, yv, ytab);
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[e] = mk<T>(acc[e].x + yv[e] * u[e].x, acc[e].y + yv[e] * u[e].y);
       }
@@ -827,16 +835,16 @@ hipError_t launch_xcombine(const FftShape& fs, void* s1, void* s2, void* c_out, 
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_zpre(const FftShape& fs, const void* g_in, const T* real_in, T* real_out, void* const* bufs_dev,
-                       int nf, const int* fields_dev, double scale, const double* off, double h, const void* ytab,
-                       const void* tw, hipStream_t s) {
+template <typename T, bool CART>
+hipError_t launch_zpre_basis(const FftShape& fs, const void* g_in, const T* real_in, T* real_out,
+                             void* const* bufs_dev, int nf, const int* fields_dev, double scale, const double* off,
+                             double h, const void* ytab, const void* tw, hipStream_t s) {
   const int lines = fs.n * fs.n;
   const size_t sm = zsmem(fs, sizeof(cx<T>));
-  PKM_TRY_Z((k_zpre<T, E, NC, TC><<<lines / fs.zlines, zthreads(fs), sm, s>>>(
+  PKM_TRY_Z((k_zpre<T, E, NC, TC, CART><<<lines / fs.zlines, zthreads(fs), sm, s>>>(
       fs.n, fs.zlines, fs.sched_z, fs.nst_z, (const cx<T>*)g_in, real_in, real_out, bufs_dev, nf, fields_dev,
       (T)scale, off[0], off[1], off[2], h, (const T*)ytab, (const cx<T>*)tw)));
-  PKM_DISPATCH_E(fs.e_z, (k_zpre<T, E, 0, 0><<<lines / fs.zlines, zthreads(fs), sm, s>>>(
+  PKM_DISPATCH_E(fs.e_z, (k_zpre<T, E, 0, 0, CART><<<lines / fs.zlines, zthreads(fs), sm, s>>>(
                              fs.n, fs.zlines, fs.sched_z, fs.nst_z, (const cx<T>*)g_in, real_in, real_out, bufs_dev,
                              nf, fields_dev, (T)scale, off[0], off[1], off[2], h, (const T*)ytab,
                              (const cx<T>*)tw)));
@@ -844,9 +852,20 @@ hipError_t launch_zpre(const FftShape& fs, const void* g_in, const T* real_in, T
 }
 
 template <typename T>
-hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const int* fields_dev, int nslots,
-                        int with_l0, const void* c_in, const void* ytab, const BinSpec& bs, double kf,
-                        double* partial, int* nblocks_out, const void* tw, int axis, hipStream_t s) {
+hipError_t launch_zpre(const FftShape& fs, const void* g_in, const T* real_in, T* real_out, void* const* bufs_dev,
+                       int nf, const int* fields_dev, double scale, const double* off, double h, const void* ytab,
+                       const void* tw, int basis, hipStream_t s) {
+  if (basis == 1)
+    return launch_zpre_basis<T, true>(fs, g_in, real_in, real_out, bufs_dev, nf, fields_dev, scale, off, h, ytab, tw,
+                                      s);
+  return launch_zpre_basis<T, false>(fs, g_in, real_in, real_out, bufs_dev, nf, fields_dev, scale, off, h, ytab, tw,
+                                     s);
+}
+
+template <typename T, bool CART>
+hipError_t launch_xpost_basis(const FftShape& fs, void* const* bufs_dev, int nf, const int* fields_dev, int nslots,
+                              int with_l0, const void* c_in, const void* ytab, const BinSpec& bs, double kf,
+                              double* partial, int* nblocks_out, const void* tw, int axis, hipStream_t s) {
   if (nslots < 0) return hipErrorInvalidValue;
   const int rows = (with_l0 ? 3 : 0) + nslots;
   const size_t sm = xpost_base_bytes(fs, sizeof(T) == 8) + sizeof(double) * (size_t)bs.hist_copies * rows * bs.nb +
@@ -855,14 +874,25 @@ hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const
   const int nthr = (fs.n / fs.e_post) * fs.tile_post;
   if (nthr > XPOST_THREADS) return hipErrorInvalidValue;
   *nblocks_out = nblk;
-  PKM_TRY_POST((k_xpost<T, E, NC, TC><<<nblk, nthr, sm, s>>>(
+  PKM_TRY_POST((k_xpost<T, E, NC, TC, CART><<<nblk, nthr, sm, s>>>(
       fs.n, fs.tile_post, fs.sched_post, fs.nst_post, bufs_dev, nf, fields_dev, nslots, with_l0, kf,
       (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies, partial, (const cx<T>*)tw, axis)));
-  PKM_DISPATCH_E(fs.e_post, (k_xpost<T, E, 0, 0><<<nblk, nthr, sm, s>>>(
+  PKM_DISPATCH_E(fs.e_post, (k_xpost<T, E, 0, 0, CART><<<nblk, nthr, sm, s>>>(
                                 fs.n, fs.tile_post, fs.sched_post, fs.nst_post, bufs_dev, nf, fields_dev, nslots,
                                 with_l0, kf, (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies,
                                 partial, (const cx<T>*)tw, axis)));
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const int* fields_dev, int nslots,
+                        int with_l0, const void* c_in, const void* ytab, const BinSpec& bs, double kf,
+                        double* partial, int* nblocks_out, const void* tw, int axis, int basis, hipStream_t s) {
+  if (basis == 1)
+    return launch_xpost_basis<T, true>(fs, bufs_dev, nf, fields_dev, nslots, with_l0, c_in, ytab, bs, kf, partial,
+                                       nblocks_out, tw, axis, s);
+  return launch_xpost_basis<T, false>(fs, bufs_dev, nf, fields_dev, nslots, with_l0, c_in, ytab, bs, kf, partial,
+                                      nblocks_out, tw, axis, s);
 }
 
 hipError_t launch_reduce(const double* partial, int nblocks, int nvals, double* out, const int* map, int accumulate,
@@ -888,9 +918,9 @@ hipError_t launch_kmu(const FftShape& fs, const void* c_in, const double* los, c
   template hipError_t launch_xcombine<T>(const FftShape&, void*, void*, void*, void*, int, int, const void*,     \
                                          const void*, const void*, hipStream_t);                                 \
   template hipError_t launch_zpre<T>(const FftShape&, const void*, const T*, T*, void* const*, int, const int*,   \
-                                     double, const double*, double, const void*, const void*, hipStream_t);       \
+                                     double, const double*, double, const void*, const void*, int, hipStream_t);  \
   template hipError_t launch_xpost<T>(const FftShape&, void* const*, int, const int*, int, int, const void*,     \
-                                      const void*, const BinSpec&, double, double*, int*, const void*, int,      \
+                                      const void*, const BinSpec&, double, double*, int*, const void*, int, int, \
                                       hipStream_t);                                                              \
   template hipError_t launch_kmu<T>(const FftShape&, const void*, const double*, const BinSpec&, const double*,   \
                                     int, double*, int, hipStream_t);

@@ -35,6 +35,7 @@ struct GroupCfg {
 };
 struct ComputeCfg {
   int ell_max = -1;
+  int basis = 0;  // 0: spherical harmonics (Sec. 2.1), 1: Cartesian monomials
   std::vector<double> edges;
   int nb = 0, total_vals = 0, nfields_total = 0;
   std::vector<GroupCfg> groups;
@@ -275,10 +276,29 @@ template <typename T> void upload_tables(pkm_plan* pl) {
   check_hip(pl, hipMemcpy(pl->ytab, yt.data(), yt.size() * sizeof(T), hipMemcpyHostToDevice), "upload ylm table");
 }
 
-int fields_for(int ell_max) {
+// Weighted fields of a request: 2l+1 per even l >= 2 (spherical), or (p+1)(p+2)/2 monomials
+// per even degree p >= 2 (Cartesian); the l = 0 / p = 0 field is C itself.
+int fields_for(int ell_max, int basis = 0) {
   int f = 0;
-  for (int l = 2; l <= ell_max; l += 2) f += 2 * l + 1;
+  for (int l = 2; l <= ell_max; l += 2) f += basis == 1 ? (l + 1) * (l + 2) / 2 : 2 * l + 1;
   return f;
+}
+
+// Coefficients of the Legendre polynomial L_l in powers of mu: L_l = sum_p c[p] mu^p (FP64,
+// exact: the denominators are powers of two), by Bonnet's recurrence.
+std::vector<double> legendre_coeffs(int l) {
+  std::vector<double> a(l + 1, 0.0), b(l + 1, 0.0), c(l + 1, 0.0);
+  a[0] = 1.0;
+  if (l == 0) return a;
+  b[1] = 1.0;
+  for (int k = 1; k < l; ++k) {  // (k+1) L_{k+1} = (2k+1) mu L_k - k L_{k-1}
+    std::fill(c.begin(), c.end(), 0.0);
+    for (int p = 0; p < l; ++p) c[p + 1] += (2.0 * k + 1.0) * b[p];
+    for (int p = 0; p <= l; ++p) c[p] = (c[p] - k * a[p]) / (k + 1.0);
+    a = b;
+    b = c;
+  }
+  return b;
 }
 
 void ensure_fields(pkm_plan* pl, int want) {
@@ -486,16 +506,17 @@ template <typename T> void run_paint(pkm_plan* pl, const pkm_catalog* data, cons
 
 // Host tables of a multipole request (thresholds, field groups, reduce maps, partial sums),
 // cached until ell_max or the edges change.
-template <typename T> void prepare_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges) {
+template <typename T>
+void prepare_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, int basis = 0) {
   ComputeCfg& cc = pl->cc;
-  if (cc.ell_max == ell_max && cc.edges.size() == (size_t)n_edges &&
+  if (cc.ell_max == ell_max && cc.basis == basis && cc.edges.size() == (size_t)n_edges &&
       std::equal(cc.edges.begin(), cc.edges.end(), k_edges))
     return;
   cc = ComputeCfg{};
   const int n = pl->p.nmesh;
   const int nb = n_edges - 1;
   {
-    const int need = fields_for(ell_max);
+    const int need = fields_for(ell_max, basis);
     if ((int)pl->fields.size() < need && (pl->p.max_group <= 0 || (int)pl->fields.size() < pl->p.max_group))
       ensure_fields(pl, pl->p.max_group > 0 ? std::min(need, pl->p.max_group) : need);
   }
@@ -518,19 +539,26 @@ template <typename T> void prepare_compute(pkm_plan* pl, int ell_max, const doub
   std::vector<std::vector<F>> groups;
   const int fmax = (int)pl->fields.size();
   {
-    // fields ordered by l; a group holds at most fmax fields (any number of multipoles)
+    // fields ordered by l (or degree p); a group holds at most fmax fields (any number of
+    // multipoles).  Cartesian fields carry (p, 32 i + j) for the monomial x^i y^j z^(p-i-j).
     std::vector<F> cur;
     int nl = 0, last_l = -1;
+    auto add = [&](int l, int m) {
+      if ((int)cur.size() == fmax) {
+        groups.push_back(cur);
+        cur.clear();
+        nl = 0;
+        last_l = -1;
+      }
+      if (l != last_l) { ++nl; last_l = l; }
+      cur.push_back({l, m, nl - 1});
+    };
     for (int l = 2; l <= ell_max; l += 2) {
-      for (int m = -l; m <= l; ++m) {
-        if ((int)cur.size() == fmax) {
-          groups.push_back(cur);
-          cur.clear();
-          nl = 0;
-          last_l = -1;
-        }
-        if (l != last_l) { ++nl; last_l = l; }
-        cur.push_back({l, m, nl - 1});
+      if (basis == 1) {
+        for (int i = 0; i <= l; ++i)
+          for (int j = 0; i + j <= l; ++j) add(l, 32 * i + j);
+      } else {
+        for (int m = -l; m <= l; ++m) add(l, m);
       }
     }
     if (!cur.empty()) groups.push_back(cur);
@@ -557,7 +585,9 @@ template <typename T> void prepare_compute(pkm_plan* pl, int ell_max, const doub
     const auto& g = groups[gi];
     std::vector<int> idx(g.size());
     for (size_t i = 0; i < g.size(); ++i) idx[i] = (int)i;
-    auto key_pre = [&](int i) { return std::make_tuple(std::abs(g[i].m), g[i].l, g[i].m < 0); };
+    auto key_pre = [&](int i) {
+      return basis == 1 ? std::make_tuple(g[i].l, g[i].m, false) : std::make_tuple(std::abs(g[i].m), g[i].l, g[i].m < 0);
+    };
     auto key_post = [&](int i) { return std::make_tuple(g[i].slot, std::abs(g[i].m), g[i].m < 0); };
     std::vector<int> pre = idx, post = idx;
     std::stable_sort(pre.begin(), pre.end(), [&](int a, int b) { return key_pre(a) < key_pre(b); });
@@ -611,6 +641,7 @@ template <typename T> void prepare_compute(pkm_plan* pl, int ell_max, const doub
     gc.copies = std::max(1, copies);
   }
   cc.ell_max = ell_max;
+  cc.basis = basis;
   cc.nb = nb;
   cc.total_vals = total_vals;
   cc.edges.assign(k_edges, k_edges + n_edges);
@@ -636,7 +667,7 @@ template <typename T> void enqueue_compute(pkm_plan* pl) {
       {
         StageScope ss(pl, PKM_STAGE_ZPRE);
         check_hip(pl, launch_zpre<T>(pl->fs, pl->g, dc_real ? (const T*)pl->d1 : nullptr, nullptr, pl->ptrs_dev,
-                                     gc.nf, ft, dc_scale, off, h, pl->ytab, pl->tw, s),
+                                     gc.nf, ft, dc_scale, off, h, pl->ytab, pl->tw, cc.basis, s),
                   "zpre");
       }
       // the column pass takes the axis the post-pass does not: FP64 fields take their x pass
@@ -651,7 +682,7 @@ template <typename T> void enqueue_compute(pkm_plan* pl) {
       StageScope ss(pl, PKM_STAGE_XPOST);
       check_hip(pl, launch_xpost<T>(pl->fs, pl->ptrs_dev, gc.nf, ftp, gc.nslots, gi == 0 ? 1 : 0, pl->c, pl->ytab,
                                     BinSpec{pl->thr_dev, cc.nb, gc.copies}, (double)(2.0 * M_PI / pl->p.box_len),
-                                    pl->partial, &nblocks, pl->tw, post_axis, s),
+                                    pl->partial, &nblocks, pl->tw, post_axis, cc.basis, s),
                 "post-pass");
     }
     StageScope ss(pl, PKM_STAGE_REDUCE);
@@ -669,7 +700,15 @@ void normalize(const pkm_plan* pl, const double* res, double norm_I, double shot
     if (out->k_mean) out->k_mean[b] = cnt > 0 ? res[nb + b] / cnt : NAN;
     if (out->poles) {
       for (int il = 0; il <= cc.ell_max / 2; ++il) {
-        const double q = res[(2 + il) * nb + b];
+        double q = res[(2 + il) * nb + b];
+        if (cc.basis == 1) {
+          // Cartesian rows hold R_p = sum Re[C conj M_p], M_p the transform of D_c (khat.xhat)^p
+          // (R_0 = sum |C|^2); P_l takes (2l+1) sum_p c_lp R_p with L_l = sum_p c_lp mu^p
+          const std::vector<double> c = legendre_coeffs(2 * il);
+          q = 0.0;
+          for (int p = 0; p <= 2 * il; p += 2) q += c[p] * res[(2 + p / 2) * nb + b];
+          q *= 4.0 * il + 1.0;
+        }
         double v = cnt > 0 ? q / (norm_I * cnt) : NAN;
         if (il == 0) v -= shot;
         out->poles[(size_t)il * nb + b] = v;
@@ -682,9 +721,9 @@ void normalize(const pkm_plan* pl, const double* res, double norm_I, double shot
 }
 
 template <typename T>
-void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, pkm_result* out) {
+void run_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, int basis, pkm_result* out) {
   hipStream_t s = pl->stream;
-  prepare_compute<T>(pl, ell_max, k_edges, n_edges);
+  prepare_compute<T>(pl, ell_max, k_edges, n_edges, basis);
   const ComputeCfg& cc = pl->cc;
   check_hip(pl, hipEventRecord(pl->ev0, s), "event");
   enqueue_compute<T>(pl);
@@ -788,7 +827,7 @@ template <typename T> void run_fft_inverse(pkm_plan* pl, void* in, void* out) {
   const double off[3] = {0, 0, 0};
   const int n = pl->p.nmesh;
   check_hip(pl, launch_zpre<T>(pl->fs, in, nullptr, (T*)out, pl->ptrs_dev, 0, pl->ftab_dev, 2.0 / ((double)n * n * n),
-                               off, 1.0, pl->ytab, pl->tw, s),
+                               off, 1.0, pl->ytab, pl->tw, 0, s),
             "z inverse");
   check_hip(pl, hipStreamSynchronize(s), "sync");
 }
@@ -803,7 +842,7 @@ template <typename T> void read_dc(pkm_plan* pl, void* host, size_t bytes) {
   const double off[3] = {0, 0, 0};
   const int n = pl->p.nmesh;
   hipError_t e = launch_zpre<T>(pl->fs, pl->g, nullptr, (T*)tmp, pl->ptrs_dev, 0, pl->ftab_dev,
-                                2.0 / ((double)n * n * n), off, 1.0, pl->ytab, pl->tw, s);
+                                2.0 / ((double)n * n * n), off, 1.0, pl->ytab, pl->tw, 0, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess) e = hipMemcpy(host, tmp, bytes, hipMemcpyDeviceToHost);
   dfree(pl, tmp);
@@ -1194,20 +1233,29 @@ pkm_status pkm_paint(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* r
   return st;
 }
 
-pkm_status pkm_compute_multipoles(pkm_plan* pl, int32_t ell_max, const double* k_edges, int32_t n_edges,
-                                  pkm_result* out) {
+pkm_status pkm_compute_multipoles_basis(pkm_plan* pl, int32_t ell_max, const double* k_edges, int32_t n_edges,
+                                        int32_t basis, pkm_result* out) {
   if (!pl) return PKM_EINVAL;
   if (!out) { pl->err = "need a result"; return PKM_EINVAL; }
+  if (basis != PKM_BASIS_SPHERICAL && basis != PKM_BASIS_CARTESIAN) {
+    pl->err = "basis must be PKM_BASIS_SPHERICAL or PKM_BASIS_CARTESIAN";
+    return PKM_EINVAL;
+  }
   if (validate_request(pl, ell_max, k_edges, n_edges) != PKM_OK) return PKM_EINVAL;
   if (pl->pending_async) { pl->err = "an enqueued estimate has not been finished"; return PKM_EBUSY; }
   if (!pl->painted) { pl->err = "pkm_paint must succeed before pkm_compute_multipoles"; return PKM_EORDER; }
   pkm_status st = guarded(pl, [&] {
     check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
-    if (pl->fp64) run_compute<double>(pl, ell_max, k_edges, n_edges, out);
-    else run_compute<float>(pl, ell_max, k_edges, n_edges, out);
+    if (pl->fp64) run_compute<double>(pl, ell_max, k_edges, n_edges, basis, out);
+    else run_compute<float>(pl, ell_max, k_edges, n_edges, basis, out);
   });
   pl->stats.device_bytes = pl->bytes;
   return st;
+}
+
+pkm_status pkm_compute_multipoles(pkm_plan* pl, int32_t ell_max, const double* k_edges, int32_t n_edges,
+                                  pkm_result* out) {
+  return pkm_compute_multipoles_basis(pl, ell_max, k_edges, n_edges, PKM_BASIS_SPHERICAL, out);
 }
 
 pkm_status pkm_kmu_global(pkm_plan* pl, const double* k_edges, int32_t n_k_edges, const double* mu_edges,

@@ -12,9 +12,10 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-ABI_VERSION = 2
+ABI_VERSION = 3
 NGP, CIC, TSC = 1, 2, 3
 FP32, FP64 = 0, 1
+SPHERICAL, CARTESIAN = 0, 1   # decompositions of L_l(khat . xhat) (Sec. 2.1)
 LOS_LOCAL, LOS_GLOBAL = 0, 1
 STATUS = {0: "PKM_OK", 1: "PKM_EINVAL", 2: "PKM_EORDER", 3: "PKM_ENOMEM", 4: "PKM_EDEVICE", 5: "PKM_EBUSY",
           6: "PKM_ECANCELLED"}
@@ -113,6 +114,7 @@ def load_library():
         "pkm_plan_create": (C.c_int, [C.POINTER(Params), C.POINTER(Device), C.POINTER(P)]),
         "pkm_paint": (C.c_int, [P, C.POINTER(Catalog), C.POINTER(Catalog)]),
         "pkm_compute_multipoles": (C.c_int, [P, C.c_int32, P, C.c_int32, C.POINTER(Result)]),
+        "pkm_compute_multipoles_basis": (C.c_int, [P, C.c_int32, P, C.c_int32, C.c_int32, C.POINTER(Result)]),
         "pkm_kmu_global": (C.c_int, [P, P, C.c_int32, P, C.c_int32, P, P]),
         "pkm_wedges": (C.c_int, [P, C.c_int32, C.c_int32, P, C.c_int32, P]),
         "pkm_nonuniform_mu_edges": (C.c_int, [C.c_int32, P]),
@@ -304,11 +306,12 @@ class Plan:
         self._keep = []
         self._check(st, "pkm_paint")
 
-    def compute_multipoles(self, ell_max: int, k_edges) -> dict:
+    def compute_multipoles(self, ell_max: int, k_edges, basis: int = SPHERICAL) -> dict:
+        """basis SPHERICAL (2l+1 transforms per l) or CARTESIAN (the monomial decomposition)."""
         e = np.ascontiguousarray(k_edges, dtype=np.float64)
         r, poles, kmean, nmodes = _result_arrays(ell_max, e.size - 1)
-        st = self.lib.pkm_compute_multipoles(self.h, int(ell_max), _ptr(e), e.size, C.byref(r))
-        self._check(st, "pkm_compute_multipoles")
+        st = self.lib.pkm_compute_multipoles_basis(self.h, int(ell_max), _ptr(e), e.size, int(basis), C.byref(r))
+        self._check(st, "pkm_compute_multipoles_basis")
         return _result_dict(r, poles, kmean, nmodes, ell_max)
 
     # -- asynchronous estimate -------------------------------------------------------------

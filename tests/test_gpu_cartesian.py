@@ -1,0 +1,96 @@
+"""The Cartesian decomposition (Sec. 2.1: L_l(khat.xhat) expanded in powers of khat.xhat and
+those in monomials, (p+1)(p+2)/2 transforms per even degree p) on the same passes as the
+spherical-harmonic path, against the oracle's definition of P_l.
+
+Both decompositions compute the same P_l; the Cartesian one combines its degree sums with the
+coefficients c_lp of L_l = sum_p c_lp mu^p, whose cancellation multiplies the rounding error by
+A_l = sum_p |c_lp| (1, 2, 8.5, 41, 208 ... 1.7e5 at l = 16).  The pass rule is therefore
+the spherical path's, per l, times A_l.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from tests.parity_util import TOL, oracle_params, pole_errors, small_catalogs
+
+pytestmark = pytest.mark.gpu
+
+OBS = (30.0, -40.0, -700.0)
+
+
+def amplification(ell: int) -> float:
+    from numpy.polynomial import legendre as npl
+    return float(np.sum(np.abs(npl.leg2poly(np.eye(ell + 1)[ell]))))
+
+
+def cartesian_transforms(ell_max: int, interlaced=True, compensated=True) -> int:
+    return sum((p + 1) * (p + 2) // 2 for p in range(2, ell_max + 1, 2)) + (2 if interlaced else 1) + \
+        (1 if (interlaced or compensated) else 0)
+
+
+def assert_per_ell(got, ref, prec, label):
+    assert np.array_equal(np.asarray(got["n_modes"]), np.asarray(ref["n_modes"]))
+    for i, ell in enumerate(range(0, 2 * (len(ref["poles"]) - 1) + 1, 2)):
+        po = np.asarray(ref["poles"])
+        raw0 = po[0] + ref["shot_noise"]
+        scale = np.maximum(np.abs(po[i]), np.abs(raw0))
+        ok = np.isfinite(po[i])
+        err = float(np.max(np.abs(np.asarray(got["poles"])[i] - po[i])[ok] / scale[ok])) if ok.any() else 0.0
+        tol = TOL[prec] * amplification(ell)
+        print(f"[parity] {label} l={ell} scaled_err={err:.3e} tol={tol:.1e}", flush=True)
+        assert err <= tol, f"{label} l={ell}: {err:.3e} > {tol:.1e}"
+
+
+@pytest.fixture(scope="module")
+def case64():
+    from oracle.estimator import default_k_edges, multipoles
+    n, L = 64, 600.0
+    d, r = small_catalogs(40_000, 200_000, L, seed=4242)
+    edges = default_k_edges(n, L, 0.02)
+    print("[oracle] 64^3 l<=16", flush=True)
+    r16 = multipoles(d, r, oracle_params(n, L, OBS, 3, True, True), 16, edges, workers=8)
+    ref = {16: r16, 8: dict(r16, poles=r16["poles"][:5], ells=r16["ells"][:5])}
+    return n, L, d, r, edges, ref
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("ell_max", [8, 16])
+def test_cartesian_64_vs_oracle(gpu, case64, prec, ell_max):
+    from paper_1704_02357_amd import CARTESIAN, SPHERICAL, Plan
+    n, L, d, r, edges, ref = case64
+    print(f"[case] cartesian 64^3 l<={ell_max} prec={prec}", flush=True)
+    plan = Plan(n, L, observer=OBS, window=3, interlaced=True, compensated=True, precision=prec,
+                ell_max_hint=ell_max)
+    plan.paint(d, r)
+    cart = plan.compute_multipoles(ell_max, edges, basis=CARTESIAN)
+    sph = plan.compute_multipoles(ell_max, edges, basis=SPHERICAL)
+    plan.close()
+    assert cart["n_transforms"] == cartesian_transforms(ell_max)
+    assert sph["n_transforms"] == (ell_max + 1) * (ell_max + 2) // 2 - 1 + 3
+    for key in ("alpha", "norm_I", "shot_noise"):
+        assert cart[key] == sph[key]
+    assert np.array_equal(cart["k_mean"], sph["k_mean"])
+    assert_per_ell(cart, ref[ell_max], prec, f"cartesian 64^3 l<={ell_max}")
+    # the spherical path on the same plan keeps the plain rule
+    scaled, _ = pole_errors(sph, ref[ell_max])
+    assert scaled <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_cartesian_512_l4_vs_stored_oracle(gpu, prec):
+    from paper_1704_02357_amd import CARTESIAN, Plan
+    from synth import catalog_digest, config_c2
+    from tests.test_gpu_workloads import GOLDEN_512, OBS as OBS512, _edges, load_golden
+    data, rand, info = config_c2()
+    gold = load_golden(GOLDEN_512)
+    assert catalog_digest(data, rand) == gold["digest"]
+    n, L = 512, 2500.0
+    edges = _edges(n, L)
+    print(f"[case] cartesian 512^3 l<=4 prec={prec}", flush=True)
+    plan = Plan(n, L, observer=OBS512, window=3, interlaced=True, compensated=True, precision=prec, ell_max_hint=4)
+    plan.paint(data, rand)
+    got = plan.compute_multipoles(4, edges, basis=CARTESIAN)
+    plan.close()
+    assert got["n_transforms"] == 24
+    assert_per_ell(got, gold, prec, "cartesian 512^3 l<=4")
