@@ -240,6 +240,17 @@ pkm_status pkm_wedges(const double* poles, int32_t ell_max, int32_t n_k, const d
  * every bin but the first integrates L_{ell_max+1}(mu)/mu to zero.  Host only.             */
 pkm_status pkm_nonuniform_mu_edges(int32_t ell_max, double* edges_out);
 
+/* Sec. 4.1 eq. gamma: the angular part of the Gaussian covariance of wedges reconstructed
+ * from the even multipoles l <= ell_max of a linear Kaiser spectrum (1 + beta mu^2)^2 P(k),
+ *   gamma_out[m*(n_mu_edges-1) + n] = sum_{l,l'} (2l+1)(2l'+1) Lbar_l(mu_m) Lbar_l'(mu_n)
+ *                                     int_{-1}^{1} (dmu/2) L_l L_l' (1 + beta mu^2)^4,
+ * so that cov[P(k_i, mu_m), P(k_i, mu_n)] = 2 gamma_mn P^2 / N_k (eq. trunc-Cmn), and the
+ * wedge correlation matrix is gamma normalised by its diagonal.  Host only, FP64; the mu
+ * integral is done by an exact Gauss rule.  mu edges strictly increasing in [0, 1],
+ * ell_max even 0..64, beta finite; otherwise PKM_EINVAL.                                    */
+pkm_status pkm_kaiser_wedge_gamma(int32_t ell_max, const double* mu_edges, int32_t n_mu_edges, double beta,
+                                  double* gamma_out);
+
 pkm_status pkm_stats(const pkm_plan* plan, pkm_stats_t* out);
 /* Enable (1) or disable (0) per-launch event timing; pkm_reset_stats clears the sums. */
 pkm_status pkm_set_stage_timing(pkm_plan* plan, int32_t enable);

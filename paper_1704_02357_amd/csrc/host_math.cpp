@@ -123,3 +123,40 @@ extern "C" pkm_status pkm_nonuniform_mu_edges(int32_t ell_max, double* edges_out
   edges_out[ell_max / 2 + 1] = 1.0;
   return PKM_OK;
 }
+
+extern "C" pkm_status pkm_kaiser_wedge_gamma(int32_t ell_max, const double* mu_edges, int32_t n_mu_edges, double beta,
+                                             double* gamma_out) {
+  if (!mu_edges || !gamma_out) return PKM_EINVAL;
+  if (ell_max < 0 || ell_max % 2 || ell_max > 64 || n_mu_edges < 2 || !std::isfinite(beta)) return PKM_EINVAL;
+  for (int j = 0; j < n_mu_edges; ++j) {
+    if (!(mu_edges[j] >= 0.0 && mu_edges[j] <= 1.0)) return PKM_EINVAL;
+    if (j > 0 && !(mu_edges[j] > mu_edges[j - 1])) return PKM_EINVAL;
+  }
+  const int nmu = n_mu_edges - 1;
+  const int nl = ell_max / 2 + 1;
+  // A_ll' = int_{-1}^{1} (dmu/2) L_l L_l' (1 + beta mu^2)^4: a polynomial of degree
+  // 2 ell_max + 8, integrated exactly by ell_max + 5 Gauss points
+  std::vector<double> gx, gw;
+  pkm_host::gauss_legendre(ell_max + 5, gx, gw);
+  std::vector<double> a((size_t)nl * nl, 0.0);
+  for (size_t q = 0; q < gx.size(); ++q) {
+    const double mu = gx[q], s = 1.0 + beta * mu * mu;
+    const double k4 = s * s * s * s;
+    for (int i = 0; i < nl; ++i) {
+      const double li = pkm_host::legendre(2 * i, mu);
+      for (int j = 0; j < nl; ++j) a[(size_t)i * nl + j] += 0.5 * gw[q] * li * pkm_host::legendre(2 * j, mu) * k4;
+    }
+  }
+  // (2l+1) Lbar_l(mu_m) per wedge
+  std::vector<double> lb((size_t)nl * nmu);
+  for (int i = 0; i < nl; ++i)
+    for (int m = 0; m < nmu; ++m) lb[(size_t)i * nmu + m] = (4 * i + 1) * pkm_host::lbar(2 * i, mu_edges[m], mu_edges[m + 1]);
+  for (int m = 0; m < nmu; ++m)
+    for (int n = 0; n < nmu; ++n) {
+      double g = 0.0;
+      for (int i = 0; i < nl; ++i)
+        for (int j = 0; j < nl; ++j) g += lb[(size_t)i * nmu + m] * lb[(size_t)j * nmu + n] * a[(size_t)i * nl + j];
+      gamma_out[(size_t)m * nmu + n] = g;
+    }
+  return PKM_OK;
+}

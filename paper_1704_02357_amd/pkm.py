@@ -117,6 +117,7 @@ def load_library():
         "pkm_compute_multipoles_basis": (C.c_int, [P, C.c_int32, P, C.c_int32, C.c_int32, C.POINTER(Result)]),
         "pkm_kmu_global": (C.c_int, [P, P, C.c_int32, P, C.c_int32, P, P]),
         "pkm_wedges": (C.c_int, [P, C.c_int32, C.c_int32, P, C.c_int32, P]),
+        "pkm_kaiser_wedge_gamma": (C.c_int, [C.c_int32, P, C.c_int32, C.c_double, P]),
         "pkm_nonuniform_mu_edges": (C.c_int, [C.c_int32, P]),
         "pkm_stats": (C.c_int, [P, C.POINTER(Stats)]),
         "pkm_set_stage_timing": (C.c_int, [P, C.c_int32]),
@@ -171,6 +172,17 @@ def wedges(poles: np.ndarray, ell_max: int, mu_edges) -> np.ndarray:
     st = lib.pkm_wedges(_ptr(poles), ell_max, nk, _ptr(mu), mu.size, _ptr(out))
     if st:
         raise PkmError(st, "pkm_wedges rejected its arguments")
+    return out
+
+
+def kaiser_wedge_gamma(ell_max: int, mu_edges, beta: float) -> np.ndarray:
+    """Sec. 4.1 eq. gamma (host, FP64): (n_mu, n_mu) angular covariance of Kaiser wedges."""
+    lib = load_library()
+    mu = np.ascontiguousarray(mu_edges, dtype=np.float64)
+    out = np.empty((mu.size - 1, mu.size - 1))
+    st = lib.pkm_kaiser_wedge_gamma(int(ell_max), _ptr(mu), mu.size, float(beta), _ptr(out))
+    if st:
+        raise PkmError(st, "pkm_kaiser_wedge_gamma rejected its arguments")
     return out
 
 

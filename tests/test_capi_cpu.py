@@ -57,6 +57,25 @@ def test_nonuniform_edges_match_oracle():
         assert np.max(np.abs(nonuniform_mu_edges(lmax) - oedges(lmax))) < 1e-10
 
 
+@pytest.mark.parametrize("lmax", [0, 4, 8, 16])
+def test_kaiser_gamma_matches_oracle(lmax):
+    from paper_1704_02357_amd import kaiser_wedge_gamma, nonuniform_mu_edges
+    from oracle.covariance import kaiser_gamma
+    for edges in (np.linspace(0, 1, 10), nonuniform_mu_edges(max(lmax, 2)), np.array([0.0, 0.2, 0.9, 1.0])):
+        for beta in (0.0, 0.35, 1.2):
+            got = kaiser_wedge_gamma(lmax, edges, beta)
+            ref = kaiser_gamma(lmax, edges, beta)
+            assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_kaiser_gamma_validation():
+    from paper_1704_02357_amd import PkmError, kaiser_wedge_gamma
+    for args in ((3, [0, 1], 0.3), (4, [0.5, 0.2], 0.3), (4, [0, 1.5], 0.3), (4, [0, 1], float("nan")),
+                 (66, [0, 1], 0.3)):
+        with pytest.raises(PkmError):
+            kaiser_wedge_gamma(*args)
+
+
 def test_wedges_validation():
     lib = _lib()
     poles = np.zeros((3, 4))

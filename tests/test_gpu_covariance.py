@@ -1,0 +1,33 @@
+"""Sec. 4.1 on the GPU path: the covariance of wedges reconstructed from estimated multipoles
+of Gaussian linear-Kaiser mocks (no shot noise, line of sight z) against linear theory
+(eq. gamma), and the conditioning of uniform against non-uniform mu bins.
+
+300 mocks at 64^3 (L = 600 Mpc/h, beta = 0.35), l <= 16, run through the batch path (one HIP
+graph per batch of 32).  The sample correlation of 300 mocks has a standard error of about
+0.06 per entry and k bin; averaged over the 20 bins in 0.1 <= k <= 0.3 h/Mpc the largest of
+the 81 entries stays below 0.08 (about 5 standard errors).
+"""
+from __future__ import annotations
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def test_kaiser_wedge_covariance(gpu):
+    from bench import covariance_study
+    print("[case] kaiser covariance 64^3 300 mocks l<=16", flush=True)
+    out = covariance_study(n=64, box_len=600.0, n_mocks=300, k_range=(0.1, 0.3))
+    print(f"[covariance] {out['correlation']}", flush=True)
+    print(f"[condition] {out['condition_number']}", flush=True)
+    assert out["k_bins_used"] >= 15
+    for key, v in out["correlation"].items():
+        assert v["max_abs_diff_vs_linear_theory"] < 0.08, key
+    c = out["correlation"]
+    # Sec. 4.1: nine multipoles de-correlate nine wedges more than three do, and the non-uniform
+    # bins give the more diagonal matrix at l <= 16
+    assert c["l16_uniform"]["mean_abs_offdiag_measured"] < c["l4_uniform"]["mean_abs_offdiag_measured"]
+    assert c["l16_nonuniform"]["mean_abs_offdiag_measured"] < c["l16_uniform"]["mean_abs_offdiag_measured"]
+    k = out["condition_number"]
+    assert k["l16_uniform"]["theory"] > 100 * k["l16_nonuniform"]["theory"]
+    assert k["l16_uniform"]["measured"] > 3 * k["l16_nonuniform"]["measured"]
