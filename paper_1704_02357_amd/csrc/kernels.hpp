@@ -32,6 +32,20 @@ size_t colpass_smem_bytes(const FftShape& fs, bool fp64);
 // LDS bytes of a post-pass block without its histograms.
 size_t xpost_base_bytes(const FftShape& fs, bool fp64);
 
+// Orthogonal matrix (rows r[0..2], r[3..5], r[6..8]) applied to every unit vector, node
+// direction and wave vector alike, before harmonics or monomials are evaluated.  The sums
+// over m (or over the monomials of one degree) depend on k.x only, so any orthogonal matrix
+// gives the same multipoles; the plan picks one that turns the mean line of sight to
+// (1,1,1)/sqrt(3), away from the coordinate poles where FP32 rounding of a direction
+// cosine becomes a large, and across the survey correlated, angle error.
+struct Frame {
+  double r[9];
+  float f[9];  // the same, rounded (FP32 passes)
+  template <typename T> __host__ __device__ T at(int i) const {
+    if constexpr (sizeof(T) == 4) return f[i]; else return (T)r[i];
+  }
+};
+
 struct BinSpec {
   const long long* thr;  // device, nb+1 integer thresholds on |n|^2
   int nb;
@@ -88,7 +102,7 @@ hipError_t launch_xcombine(const FftShape& fs, void* s1, void* s2, void* c_out, 
 template <typename T>
 hipError_t launch_zpre(const FftShape& fs, const void* g_in, const T* real_in, T* real_out, void* const* bufs_dev,
                        int nf, const int* fields_dev, double scale, const double* off, double h, const void* ytab,
-                       const void* tw, int basis, hipStream_t s);
+                       const void* tw, const Frame& frame, int basis, hipStream_t s);
 
 // Last transform pass of every field of the group (along x for axis 0, along y for axis 1),
 // sum over m of Y_lm(khat) B_lm per multipole slot, product with C and binning.  Per block the partial sums are rows of nb bins:
@@ -98,7 +112,8 @@ hipError_t launch_zpre(const FftShape& fs, const void* g_in, const T* real_in, T
 template <typename T>
 hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const int* fields_dev, int nslots,
                         int with_l0, const void* c_in, const void* ytab, const BinSpec& bs, double kf,
-                        double* partial, int* nblocks_out, const void* tw, int axis, int basis, hipStream_t s);
+                        double* partial, int* nblocks_out, const void* tw, int axis, const Frame& frame, int basis,
+                        hipStream_t s);
 
 // out[map[v]] (+)= sum_b partial[b*nvals + v] (map null -> identity), fixed order.
 hipError_t launch_reduce(const double* partial, int nblocks, int nvals, double* out, const int* map, int accumulate,

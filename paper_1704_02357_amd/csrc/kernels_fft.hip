@@ -346,7 +346,8 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n_rt, int g_rt, uint3
                                                         T* __restrict__ real_out, void* const* __restrict__ bufs,
                                                         int nf, const int* __restrict__ fields, T scale, double off0,
                                                         double off1, double off2, double h,
-                                                        const T* __restrict__ ytab, const cx<T>* __restrict__ tw) {
+                                                        const T* __restrict__ ytab, const cx<T>* __restrict__ tw,
+                                                        Frame fr) {
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
   const int n = NC > 0 ? NC : n_rt;
@@ -409,9 +410,10 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n_rt, int g_rt, uint3
     const double rr = sqrt(pxy2 + pz * pz);
     const bool zero = !(rr > 0.0);
     const double inv = zero ? 0.0 : 1.0 / rr;
-    ux[q] = (T)(px * inv);
-    uy[q] = (T)(py * inv);
-    uz[q] = (T)(pz * inv);
+    const double vx = px * inv, vy = py * inv, vz = pz * inv;
+    ux[q] = (T)(fr.r[0] * vx + fr.r[1] * vy + fr.r[2] * vz);
+    uy[q] = (T)(fr.r[3] * vx + fr.r[4] * vy + fr.r[5] * vz);
+    uz[q] = (T)(fr.r[6] * vx + fr.r[7] * vy + fr.r[8] * vz);
     if (zero) r[q] = T(0);
   }
   YRun<T, 2 * E> yr;
@@ -444,7 +446,7 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n_rt, int g_rt, uint3
 // x post-pass: forward x of each field, sum_m Y_lm(khat) B, product with C, binning.
 // Fields come l-major (slots contiguous).  One complex accumulator per element holds
 // sum_m Y_lm(khat) B_lm of the current slot; at the last field of a slot it is folded
-// against C (held in registers for the whole block) into the FP64 bin histogram.  Two tile
+// against C (held in registers for the whole tile) into the FP64 bin histogram.  Two tile
 // buffers alternate between fields, so one block barrier per field suffices; the transform
 // itself runs within one wavefront per column on the compile-time path.
 // ------------------------------------------------------------------------------------------
@@ -511,7 +513,7 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
                                                           const T* __restrict__ ytab,
                                                           const long long* __restrict__ thr, int nb, int copies,
                                                           double* __restrict__ partial,
-                                                          const cx<T>* __restrict__ tw, int axis) {
+                                                          const cx<T>* __restrict__ tw, int axis, Frame frm) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = NC > 0 ? NC : n_rt;
   const int tile = TC > 0 ? TC : tile_rt;
@@ -572,10 +574,13 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
         n2[e] = fr * fr + fo * fo + kz * kz;
         excl[e] = onyq || x == nh || n2[e] == 0;
         cv[e] = gload<T>(cin, base + c + (size_t)x * rs);
+        // wave vectors cover every direction, so their rounding is not correlated: the
+        // rotation runs in the working precision
         const T ki = n2[e] > 0 ? T(1) / sqrt((T)n2[e]) : T(0);
-        ux[e] = (T)(axis ? fo : fr) * ki;
-        uy[e] = (T)(axis ? fr : fo) * ki;
-        uz[e] = (T)kz * ki;
+        const T vx = (T)(axis ? fo : fr) * ki, vy = (T)(axis ? fr : fo) * ki, vz = (T)kz * ki;
+        ux[e] = frm.at<T>(0) * vx + frm.at<T>(1) * vy + frm.at<T>(2) * vz;
+        uy[e] = frm.at<T>(3) * vx + frm.at<T>(4) * vy + frm.at<T>(5) * vz;
+        uz[e] = frm.at<T>(6) * vx + frm.at<T>(7) * vy + frm.at<T>(8) * vz;
       }
       kbins_lds<E>(thr_l, nb, n2, excl, bin);
     }
@@ -838,34 +843,35 @@ hipError_t launch_xcombine(const FftShape& fs, void* s1, void* s2, void* c_out, 
 template <typename T, bool CART>
 hipError_t launch_zpre_basis(const FftShape& fs, const void* g_in, const T* real_in, T* real_out,
                              void* const* bufs_dev, int nf, const int* fields_dev, double scale, const double* off,
-                             double h, const void* ytab, const void* tw, hipStream_t s) {
+                             double h, const void* ytab, const void* tw, const Frame& frame, hipStream_t s) {
   const int lines = fs.n * fs.n;
   const size_t sm = zsmem(fs, sizeof(cx<T>));
   PKM_TRY_Z((k_zpre<T, E, NC, TC, CART><<<lines / fs.zlines, zthreads(fs), sm, s>>>(
       fs.n, fs.zlines, fs.sched_z, fs.nst_z, (const cx<T>*)g_in, real_in, real_out, bufs_dev, nf, fields_dev,
-      (T)scale, off[0], off[1], off[2], h, (const T*)ytab, (const cx<T>*)tw)));
+      (T)scale, off[0], off[1], off[2], h, (const T*)ytab, (const cx<T>*)tw, frame)));
   PKM_DISPATCH_E(fs.e_z, (k_zpre<T, E, 0, 0, CART><<<lines / fs.zlines, zthreads(fs), sm, s>>>(
                              fs.n, fs.zlines, fs.sched_z, fs.nst_z, (const cx<T>*)g_in, real_in, real_out, bufs_dev,
                              nf, fields_dev, (T)scale, off[0], off[1], off[2], h, (const T*)ytab,
-                             (const cx<T>*)tw)));
+                             (const cx<T>*)tw, frame)));
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_zpre(const FftShape& fs, const void* g_in, const T* real_in, T* real_out, void* const* bufs_dev,
                        int nf, const int* fields_dev, double scale, const double* off, double h, const void* ytab,
-                       const void* tw, int basis, hipStream_t s) {
+                       const void* tw, const Frame& frame, int basis, hipStream_t s) {
   if (basis == 1)
     return launch_zpre_basis<T, true>(fs, g_in, real_in, real_out, bufs_dev, nf, fields_dev, scale, off, h, ytab, tw,
-                                      s);
+                                      frame, s);
   return launch_zpre_basis<T, false>(fs, g_in, real_in, real_out, bufs_dev, nf, fields_dev, scale, off, h, ytab, tw,
-                                     s);
+                                     frame, s);
 }
 
 template <typename T, bool CART>
 hipError_t launch_xpost_basis(const FftShape& fs, void* const* bufs_dev, int nf, const int* fields_dev, int nslots,
                               int with_l0, const void* c_in, const void* ytab, const BinSpec& bs, double kf,
-                              double* partial, int* nblocks_out, const void* tw, int axis, hipStream_t s) {
+                              double* partial, int* nblocks_out, const void* tw, int axis, const Frame& frame,
+                              hipStream_t s) {
   if (nslots < 0) return hipErrorInvalidValue;
   const int rows = (with_l0 ? 3 : 0) + nslots;
   const size_t sm = xpost_base_bytes(fs, sizeof(T) == 8) + sizeof(double) * (size_t)bs.hist_copies * rows * bs.nb +
@@ -876,23 +882,24 @@ hipError_t launch_xpost_basis(const FftShape& fs, void* const* bufs_dev, int nf,
   *nblocks_out = nblk;
   PKM_TRY_POST((k_xpost<T, E, NC, TC, CART><<<nblk, nthr, sm, s>>>(
       fs.n, fs.tile_post, fs.sched_post, fs.nst_post, bufs_dev, nf, fields_dev, nslots, with_l0, kf,
-      (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies, partial, (const cx<T>*)tw, axis)));
+      (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies, partial, (const cx<T>*)tw, axis, frame)));
   PKM_DISPATCH_E(fs.e_post, (k_xpost<T, E, 0, 0, CART><<<nblk, nthr, sm, s>>>(
                                 fs.n, fs.tile_post, fs.sched_post, fs.nst_post, bufs_dev, nf, fields_dev, nslots,
                                 with_l0, kf, (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies,
-                                partial, (const cx<T>*)tw, axis)));
+                                partial, (const cx<T>*)tw, axis, frame)));
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const int* fields_dev, int nslots,
                         int with_l0, const void* c_in, const void* ytab, const BinSpec& bs, double kf,
-                        double* partial, int* nblocks_out, const void* tw, int axis, int basis, hipStream_t s) {
+                        double* partial, int* nblocks_out, const void* tw, int axis, const Frame& frame, int basis,
+                        hipStream_t s) {
   if (basis == 1)
     return launch_xpost_basis<T, true>(fs, bufs_dev, nf, fields_dev, nslots, with_l0, c_in, ytab, bs, kf, partial,
-                                       nblocks_out, tw, axis, s);
+                                       nblocks_out, tw, axis, frame, s);
   return launch_xpost_basis<T, false>(fs, bufs_dev, nf, fields_dev, nslots, with_l0, c_in, ytab, bs, kf, partial,
-                                      nblocks_out, tw, axis, s);
+                                      nblocks_out, tw, axis, frame, s);
 }
 
 hipError_t launch_reduce(const double* partial, int nblocks, int nvals, double* out, const int* map, int accumulate,
@@ -918,10 +925,11 @@ hipError_t launch_kmu(const FftShape& fs, const void* c_in, const double* los, c
   template hipError_t launch_xcombine<T>(const FftShape&, void*, void*, void*, void*, int, int, const void*,     \
                                          const void*, const void*, hipStream_t);                                 \
   template hipError_t launch_zpre<T>(const FftShape&, const void*, const T*, T*, void* const*, int, const int*,   \
-                                     double, const double*, double, const void*, const void*, int, hipStream_t);  \
+                                     double, const double*, double, const void*, const void*, const Frame&, int,   \
+                                     hipStream_t);                                                                 \
   template hipError_t launch_xpost<T>(const FftShape&, void* const*, int, const int*, int, int, const void*,     \
-                                      const void*, const BinSpec&, double, double*, int*, const void*, int, int, \
-                                      hipStream_t);                                                              \
+                                      const void*, const BinSpec&, double, double*, int*, const void*, int,      \
+                                      const Frame&, int, hipStream_t);                                           \
   template hipError_t launch_kmu<T>(const FftShape&, const void*, const double*, const BinSpec&, const double*,   \
                                     int, double*, int, hipStream_t);
 PKM_INST(float)

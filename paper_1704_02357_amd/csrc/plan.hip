@@ -49,6 +49,7 @@ struct pkm_plan {
   size_t es = 4;        // real element bytes
   size_t mesh_bytes = 0;
   FftShape fs{};
+  Frame frame{};        // harmonic frame (mean line of sight -> (1,1,1)/sqrt 3)
   // resident buffers
   void* d1 = nullptr;
   void* d2 = nullptr;
@@ -274,6 +275,32 @@ template <typename T> void upload_tables(pkm_plan* pl) {
   check_hip(pl, hipMemcpy(pl->invw, invw.data(), invw.size() * sizeof(T), hipMemcpyHostToDevice), "upload window");
   check_hip(pl, hipMemcpy(pl->phase, ph.data(), ph.size() * sizeof(T), hipMemcpyHostToDevice), "upload phase");
   check_hip(pl, hipMemcpy(pl->ytab, yt.data(), yt.size() * sizeof(T), hipMemcpyHostToDevice), "upload ylm table");
+}
+
+// The Householder reflection that takes the mean line of sight (observer to box centre) to
+// (1,1,1)/sqrt(3); the identity when they already agree or the observer is at the centre.
+Frame harmonic_frame(const pkm_params& p) {
+  Frame f{};
+  double l[3], nl = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    l[a] = p.box_origin[a] + 0.5 * p.box_len - p.observer[a];
+    nl += l[a] * l[a];
+  }
+  for (int a = 0; a < 9; ++a) f.r[a] = (a % 4 == 0) ? 1.0 : 0.0;
+  for (int a = 0; a < 9; ++a) f.f[a] = (float)f.r[a];
+  nl = std::sqrt(nl);
+  if (!(nl > 0.0)) return f;
+  const double b = 1.0 / std::sqrt(3.0);
+  double w[3], nw = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    w[a] = l[a] / nl - b;
+    nw += w[a] * w[a];
+  }
+  if (nw >= 1e-24)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) f.r[3 * i + j] -= 2.0 * w[i] * w[j] / nw;
+  for (int a = 0; a < 9; ++a) f.f[a] = (float)f.r[a];
+  return f;
 }
 
 // Weighted fields of a request: 2l+1 per even l >= 2 (spherical), or (p+1)(p+2)/2 monomials
@@ -667,7 +694,7 @@ template <typename T> void enqueue_compute(pkm_plan* pl) {
       {
         StageScope ss(pl, PKM_STAGE_ZPRE);
         check_hip(pl, launch_zpre<T>(pl->fs, pl->g, dc_real ? (const T*)pl->d1 : nullptr, nullptr, pl->ptrs_dev,
-                                     gc.nf, ft, dc_scale, off, h, pl->ytab, pl->tw, cc.basis, s),
+                                     gc.nf, ft, dc_scale, off, h, pl->ytab, pl->tw, pl->frame, cc.basis, s),
                   "zpre");
       }
       // the column pass takes the axis the post-pass does not: FP64 fields take their x pass
@@ -682,7 +709,7 @@ template <typename T> void enqueue_compute(pkm_plan* pl) {
       StageScope ss(pl, PKM_STAGE_XPOST);
       check_hip(pl, launch_xpost<T>(pl->fs, pl->ptrs_dev, gc.nf, ftp, gc.nslots, gi == 0 ? 1 : 0, pl->c, pl->ytab,
                                     BinSpec{pl->thr_dev, cc.nb, gc.copies}, (double)(2.0 * M_PI / pl->p.box_len),
-                                    pl->partial, &nblocks, pl->tw, post_axis, cc.basis, s),
+                                    pl->partial, &nblocks, pl->tw, post_axis, pl->frame, cc.basis, s),
                 "post-pass");
     }
     StageScope ss(pl, PKM_STAGE_REDUCE);
@@ -827,7 +854,7 @@ template <typename T> void run_fft_inverse(pkm_plan* pl, void* in, void* out) {
   const double off[3] = {0, 0, 0};
   const int n = pl->p.nmesh;
   check_hip(pl, launch_zpre<T>(pl->fs, in, nullptr, (T*)out, pl->ptrs_dev, 0, pl->ftab_dev, 2.0 / ((double)n * n * n),
-                               off, 1.0, pl->ytab, pl->tw, 0, s),
+                               off, 1.0, pl->ytab, pl->tw, pl->frame, 0, s),
             "z inverse");
   check_hip(pl, hipStreamSynchronize(s), "sync");
 }
@@ -842,7 +869,7 @@ template <typename T> void read_dc(pkm_plan* pl, void* host, size_t bytes) {
   const double off[3] = {0, 0, 0};
   const int n = pl->p.nmesh;
   hipError_t e = launch_zpre<T>(pl->fs, pl->g, nullptr, (T*)tmp, pl->ptrs_dev, 0, pl->ftab_dev,
-                                2.0 / ((double)n * n * n), off, 1.0, pl->ytab, pl->tw, 0, s);
+                                2.0 / ((double)n * n * n), off, 1.0, pl->ytab, pl->tw, pl->frame, 0, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess) e = hipMemcpy(host, tmp, bytes, hipMemcpyDeviceToHost);
   dfree(pl, tmp);
@@ -1154,6 +1181,7 @@ pkm_status pkm_plan_create_shaped(const pkm_params* p, const pkm_device* dev, co
   pkm_plan* pl = new (std::nothrow) pkm_plan();
   if (!pl) return PKM_ENOMEM;
   pl->p = *p;
+  pl->frame = harmonic_frame(pl->p);
   if (pl->p.ell_max_hint == 0) pl->p.ell_max_hint = 4;
   if (dev) pl->dev = *dev;
   pl->stream = (hipStream_t)pl->dev.hip_stream;
