@@ -142,6 +142,79 @@ def run_form(precision: int, data, rand, edges, steps: int, warmup: int):
     return res, (t1 - t0), np.array(lat), st
 
 
+def catalog_upload(data, rand, dst) -> dict:
+    """Host-to-device copy of the catalog arrays (positions, weights, n-bar of both catalogs)
+    into the resident device buffers: from pageable numpy memory and from pinned memory; the
+    median of three copies each.  Not part of the estimate's timed region."""
+    import torch
+    host = [np.ascontiguousarray(a, dtype=np.float64) for a in (data.pos, data.w, data.nbar, rand.pos, rand.w, rand.nbar)]
+    nbytes = sum(a.nbytes for a in host)
+    pinned = [torch.from_numpy(a).pin_memory() for a in host]
+    out = {"bytes": int(nbytes)}
+    for name, srcs in (("pageable", [torch.from_numpy(a) for a in host]), ("pinned", pinned)):
+        ms = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for d, h in zip(dst, srcs):
+                d.copy_(h.view_as(d), non_blocking=(name == "pinned"))
+            torch.cuda.synchronize()
+            ms.append(1e3 * (time.perf_counter() - t0))
+        out[f"ms_{name}"] = round(float(np.median(ms)), 3)
+        out[f"GBps_{name}"] = round(nbytes / (np.median(ms) * 1e-3) / 1e9, 1)
+    del pinned
+    return out
+
+
+def fft_bench(args) -> dict:
+    """The library's 3D real-to-complex transform (the one pkm_paint applies to each painted
+    mesh) against ROCm's FFT library through torch.fft.rfftn, same sizes and precisions, device
+    time per transform; for comparison only (the estimator never calls the library FFT)."""
+    import torch
+    from paper_1704_02357_amd import Plan
+    rows = []
+    for n in (256, 512, 1024):
+        for prec in (0, 1):
+            rdt, cdt = (torch.float64, torch.complex128) if prec else (torch.float32, torch.complex64)
+            g = torch.Generator(device="cuda")
+            g.manual_seed(n + prec)
+            x = torch.randn((n, n, n), generator=g, dtype=rdt, device="cuda")
+            plan = Plan(n, 1000.0, precision=prec)
+            ours = torch.empty((n, n, n // 2), dtype=cdt, device="cuda")
+
+            def timed(fn, reps):
+                fn()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    fn()
+                e1.record()
+                torch.cuda.synchronize()
+                return e0.elapsed_time(e1) / reps
+
+            reps = 20 if n <= 512 else 5
+            ms_ours = timed(lambda: plan.fft3d_forward(x, ours), reps)
+            ref = {}
+            ms_lib = timed(lambda: ref.__setitem__("y", torch.fft.rfftn(x)), reps)
+            y = ref["y"][:, :, : n // 2]
+            err = float((ours - y).abs().max() / y.abs().max())
+            # algorithmic bytes of one R2C transform: the real input read, the half spectrum written
+            byts = x.numel() * x.element_size() + ours.numel() * ours.element_size()
+            rows.append({"n": n, "precision": "f64" if prec else "f32", "ms_ours": round(ms_ours, 3),
+                         "ms_library": round(ms_lib, 3), "ours_over_library": round(ms_lib / ms_ours, 3),
+                         "ours_GBps_in_plus_out": round(byts / (ms_ours * 1e-3) / 1e9, 1),
+                         "max_rel_diff": err})
+            log(f"[fft] {rows[-1]}")
+            plan.close()
+            del x, ours, ref, y
+            torch.cuda.empty_cache()
+    return {"metric": "3D R2C transform device time, this library against ROCm's FFT (torch.fft.rfftn)",
+            "unit": "ms", "higher_is_better": False, "n_gpus": 1, "rows": rows,
+            "data": "synthetic (standard normal real meshes)",
+            "config": {"workload": "N^3 real to half spectrum, N = 256, 512, 1024, FP32 and FP64"}}
+
+
 def cpu_baseline(data, rand, edges, workers: int) -> dict:
     """FP64 oracle timed on a bounded sample of one estimate, scaled to estimates/s.
 
@@ -482,10 +555,10 @@ def main():
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="print the kernel summary of a rocprofv3 CSV output directory and exit")
     ap.add_argument("--cov-mocks", type=int, default=1000, help="mocks of the covariance mode")
-    ap.add_argument("--mode", choices=["estimate", "batch", "serve", "basis", "covariance"], default="estimate",
+    ap.add_argument("--mode", choices=["estimate", "batch", "serve", "basis", "covariance", "fft"], default="estimate",
                     help="estimate: the 512^3 l<=4 line (default); batch: covariance mocks; serve: request stream; "
                          "basis: spherical against Cartesian decomposition; covariance: Kaiser-mock wedge "
-                         "covariance")
+                         "covariance; fft: the 3D transform against ROCm's FFT library")
     ap.add_argument("--mocks", type=int, default=64)
     ap.add_argument("--requests", type=int, default=48)
     ap.add_argument("--rate", type=float, default=1.0, help="request arrivals per second (serve mode)")
@@ -504,7 +577,7 @@ def main():
         sys.exit(1)
     if args.mode != "estimate":
         out = {"batch": batch_bench, "serve": serve_bench, "basis": basis_bench,
-               "covariance": covariance_bench}[args.mode](args)
+               "covariance": covariance_bench, "fft": fft_bench}[args.mode](args)
         print(json.dumps(out), flush=True)
         return
     if args.calib_copy:
@@ -524,6 +597,7 @@ def main():
     gdata = (dev(data.pos), dev(data.w), dev(data.nbar))
     grand = (dev(rand.pos), dev(rand.w), dev(rand.nbar))
     torch.cuda.synchronize()
+    upload = catalog_upload(data, rand, gdata + grand)
     res32, sec32, lat32, st32 = run_form(0, gdata, grand, edges, args.steps, args.warmup)
     log(f"[bench] fp32: {args.steps / sec32:.2f} est/s, {1e3 * sec32 / args.steps:.3f} ms/step")
     k64 = args.fp64_steps or max(2, args.steps // 2)
@@ -579,6 +653,8 @@ def main():
                  "latency_ms": {"p50": round(1e3 * float(np.percentile(lat64, 50)), 3),
                                 "p99": round(1e3 * float(np.percentile(lat64, 99)), 3)}},
         "fp32_vs_fp64_max_scaled_err": fp32_err,
+        "catalog_upload": dict(upload, estimates_per_s_incl_pinned_upload=round(
+            1.0 / (sec32 / args.steps + 1e-3 * upload["ms_pinned"]), 3)),
         "model_GB_per_estimate_fp32": round(total_model / 1e9, 3),
         "effective_GBps_fp32": round(total_model * args.steps / sec32 / 1e9, 1),
         "roofline": roof,
