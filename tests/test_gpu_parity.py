@@ -229,3 +229,23 @@ def test_edge_cases(gpu, prec):
     got = plan.compute_multipoles(2, edges)
     ref = multipoles(one, None, p, 2, edges)
     assert_pole_parity(got, ref, prec, "one galaxy")
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("observer", [(0.0, 0.0, 0.0), (-103.125, 37.5, -65.625), (-1000.0, -1000.0, -1000.0)],
+                         ids=["centre-node", "interior-node", "along-111"])
+def test_observer_positions(gpu, prec, observer):
+    """Observers at the box centre and at an interior mesh node (a node with no direction:
+    its weighted values are zero for l > 0), and one whose line of sight already lies along
+    (1,1,1): the harmonic frame is then the identity.  l <= 8 against the oracle."""
+    from oracle.estimator import multipoles
+    n, L = 32, 300.0
+    d, r = small_catalogs(4000, 30000, L, seed=77)
+    edges = np.arange(0.0, math.pi * n / L + 1e-9, 0.03)
+    print(f"[case] observer={observer} prec={prec}", flush=True)
+    plan = _plan(n, L, prec, observer, ell_max_hint=8)
+    plan.paint(d, r)
+    got = plan.compute_multipoles(8, edges)
+    plan.close()
+    ref = multipoles(d, r, oracle_params(n, L, observer, 3, True, True), 8, edges)
+    assert_pole_parity(got, ref, prec, f"observer {observer}")
