@@ -884,18 +884,22 @@ bool make_shape(const pkm_params& p, FftShape* out) {
   fs.n = n;
   fs.e_col = pick_e(n);
   fs.e_z = pick_e(n / 2);
-  // register budget: FP64 column passes and all z-line passes use at most 8 (or 12 / 6
-  // for lengths with a factor 3) elements per thread
-  if (fp64 && fs.e_col == 16) fs.e_col = 8;
+  // register budget: z-line passes, and FP64 column passes of the generic kernels, use at
+  // most 8 (or 12 / 6 for lengths with a factor 3) elements per thread; the compile-time
+  // FP64 column kernels for 256..1024 take 16 (the autotuner's pick at 512^3)
+  const bool pow2_table = n >= 256 && n <= 1024 && (n & (n - 1)) == 0;
+  if (fp64 && fs.e_col == 16 && !pow2_table) fs.e_col = 8;
   if (fs.e_z == 16) fs.e_z = 8;
   if (!fs.e_col || !fs.e_z || !make_sched(n, fs.e_col, &fs.sched_col, &fs.nst_col) ||
       !make_sched(n / 2, fs.e_z, &fs.sched_z, &fs.nst_z)) {
     return false;
   }
-  // tile columns: 128-byte rows, at most 512 threads per column-pass block
-  fs.tile = fp64 ? 8 : 16;
+  // tile columns: 16 (128-byte rows in FP32, 256 in FP64: the autotuner's pick for FP64 at
+  // 512^3), at most 512 threads and the LDS of one compute unit per column-pass block
+  fs.tile = 16;
   const int pt_col = n / fs.e_col;
-  while (fs.tile > 1 && (pt_col * fs.tile > 512 || (n / 2) % fs.tile)) fs.tile /= 2;
+  while (fs.tile > 1 && (pt_col * fs.tile > 512 || (n / 2) % fs.tile || colpass_smem_bytes(fs, fp64) > 160 * 1024))
+    fs.tile /= 2;
   // post-pass: at most 8 elements per thread (register budget of the fused recurrence)
   fs.e_post = fs.e_col > 8 && fs.e_col % 8 == 0 ? 8 : fs.e_col;
   if (fs.e_post == 12) fs.e_post = 6;
