@@ -21,7 +21,7 @@ OBS = (30.0, -40.0, -700.0)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("n", [16, 32, 48, 64, 96, 128])
+@pytest.mark.parametrize("n", [16, 32, 48, 64, 96, 128, 256])
 def test_fft3d_forward_inverse(gpu, prec, n):
     import torch
     print(f"[case] fft3d n={n} prec={prec}", flush=True)
