@@ -52,9 +52,10 @@ struct BinSpec {
   int hist_copies;       // per-block histogram copies (1 .. number of waves)
 };
 
-// Catalog sums: out2[0] = sum w^2, out2[1] = sum w^2 nbar (w, nbar may be null => 1).
+// Catalog sums: out2[0] = sum w^2, out2[1] = sum w^2 nbar, *wmax = max |w| (w, nbar may be
+// null => 1).  partial holds 3 nblk doubles.
 hipError_t launch_catalog_sums(const double* w, const double* nbar, int64_t n, double* partial, int nblk,
-                               double* out2, hipStream_t s);
+                               double* out2, double* wmax, hipStream_t s);
 
 template <typename T> hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s);
 
@@ -74,8 +75,11 @@ constexpr int TILE_COUNT_COPIES = 8;
 inline int tile_scan_scratch(int ntiles) { return (ntiles + 1023) / 1024 + 1; }
 // Tile-wise painting from the sorted payload.
 template <typename T>
+// wmax_d / wmax_r: device pointers to the largest |w| of each catalog (wmax_r null without
+// randoms); they bound the per-tile fixed-point accumulation of FP32 meshes.
 hipError_t launch_paint_tiles(const int* off, const void* payload, int ntiles, const double* origin, double scale,
-                              int nmesh, int window, int ts, T* d1, T* d2, hipStream_t s);
+                              int nmesh, int window, int ts, T* d1, T* d2, const double* wmax_d,
+                              const double* wmax_r, double alpha, hipStream_t s);
 
 // Forward real-to-half-complex transform along z of nbuf real meshes (nbuf <= 2).
 template <typename T>

@@ -14,52 +14,60 @@ constexpr int SUM_THREADS = 256;
 __global__ void __launch_bounds__(SUM_THREADS) k_catalog_sums(const double* __restrict__ w,
                                                               const double* __restrict__ nbar, int64_t n,
                                                               double* __restrict__ partial) {
-  __shared__ double s0[SUM_THREADS], s1[SUM_THREADS];
-  double a0 = 0.0, a1 = 0.0;
+  __shared__ double s0[SUM_THREADS], s1[SUM_THREADS], s2[SUM_THREADS];
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const double wi = w ? w[i] : 1.0;
     const double w2 = wi * wi;
     a0 += w2;
     a1 += w2 * (nbar ? nbar[i] : 1.0);
+    a2 = fmax(a2, fabs(wi));
   }
   s0[threadIdx.x] = a0;
   s1[threadIdx.x] = a1;
+  s2[threadIdx.x] = a2;
   __syncthreads();
   for (int h = SUM_THREADS / 2; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) {
       s0[threadIdx.x] += s0[threadIdx.x + h];
       s1[threadIdx.x] += s1[threadIdx.x + h];
+      s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + h]);
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    partial[2 * blockIdx.x] = s0[0];
-    partial[2 * blockIdx.x + 1] = s1[0];
+    partial[3 * blockIdx.x] = s0[0];
+    partial[3 * blockIdx.x + 1] = s1[0];
+    partial[3 * blockIdx.x + 2] = s2[0];
   }
 }
 
 __global__ void __launch_bounds__(SUM_THREADS) k_sum_partials2(const double* __restrict__ partial, int nblk,
-                                                               double* __restrict__ out2) {
-  __shared__ double s0[SUM_THREADS], s1[SUM_THREADS];
-  double a0 = 0.0, a1 = 0.0;
+                                                               double* __restrict__ out2, double* __restrict__ wmax) {
+  __shared__ double s0[SUM_THREADS], s1[SUM_THREADS], s2[SUM_THREADS];
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   for (int b = threadIdx.x; b < nblk; b += SUM_THREADS) {
-    a0 += partial[2 * b];
-    a1 += partial[2 * b + 1];
+    a0 += partial[3 * b];
+    a1 += partial[3 * b + 1];
+    a2 = fmax(a2, partial[3 * b + 2]);
   }
   s0[threadIdx.x] = a0;
   s1[threadIdx.x] = a1;
+  s2[threadIdx.x] = a2;
   __syncthreads();
   for (int h = SUM_THREADS / 2; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) {
       s0[threadIdx.x] += s0[threadIdx.x + h];
       s1[threadIdx.x] += s1[threadIdx.x + h];
+      s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + h]);
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     out2[0] = s0[0];
     out2[1] = s1[0];
+    *wmax = s2[0];
   }
 }
 
@@ -221,9 +229,21 @@ __device__ __forceinline__ void taps_unwrapped(double u, long long* c0, double* 
   }
 }
 
+// One tap into the LDS region: FP64 atomic add (FP64 meshes), or, for FP32 meshes, an
+// integer add of the tap rounded to a multiple of 1/sc (fixed point; 64-bit integer LDS atomics
+// are faster than FP64 ones on gfx950, and FP32 LDS atomics far slower).
+template <typename T>
+__device__ __forceinline__ void region_add(double* __restrict__ reg, int i, double v, double sc) {
+  if constexpr (sizeof(T) == 4)
+    lds_atomic_add<unsigned long long>(reinterpret_cast<unsigned long long*>(reg) + i,
+                                       (unsigned long long)__double2ll_rn(v * sc));
+  else
+    lds_atomic_add<double>(reg + i, v);
+}
+
 template <typename T, int W>
 __device__ __forceinline__ void tile_scatter(double* __restrict__ reg, T* __restrict__ mesh, const double* u,
-                                             double wgt, int nmesh, const long long* r0, int rsz) {
+                                             double wgt, int nmesh, const long long* r0, int rsz, double sc) {
   long long c0[3];
   double w[3][W];
   taps_unwrapped<W>(u[0], &c0[0], w[0]);
@@ -240,7 +260,7 @@ __device__ __forceinline__ void tile_scatter(double* __restrict__ reg, T* __rest
         const double wab = wa * w[1][b];
         const int row = ((ra0 + a) * rsz + (rb0 + b)) * rsz + rc0;
 #pragma unroll
-        for (int c = 0; c < W; ++c) lds_atomic_add<double>(&reg[row + c], wab * w[2][c]);
+        for (int c = 0; c < W; ++c) region_add<T>(reg, row + c, wab * w[2][c], sc);
       }
     }
     return;
@@ -265,7 +285,9 @@ __device__ __forceinline__ void tile_scatter(double* __restrict__ reg, T* __rest
 template <typename T, int W, int TS>
 __global__ void __launch_bounds__(256) k_paint_tiles(const int* __restrict__ off, const double4* __restrict__ payload,
                                                      double o0, double o1, double o2, double scale, int nmesh,
-                                                     T* __restrict__ d1, T* __restrict__ d2) {
+                                                     T* __restrict__ d1, T* __restrict__ d2,
+                                                     const double* __restrict__ wmax_d,
+                                                     const double* __restrict__ wmax_r, double alpha) {
   constexpr int ts = TS;
   extern __shared__ __align__(16) unsigned char smem[];
   // natural tile order: consecutive tiles land on different XCDs, which spreads the dense
@@ -282,6 +304,16 @@ __global__ void __launch_bounds__(256) k_paint_tiles(const int* __restrict__ off
   const int tpa = nmesh / ts;
   const int tz = tile % tpa, ty = (tile / tpa) % tpa, tx = tile / (tpa * tpa);
   const int t0[3] = {tx * ts, ty * ts, tz * ts};
+  // fixed-point scale (FP32 meshes): no region cell can exceed B = (particles of the tile) x
+  // (largest |payload weight|), since a particle's taps sum to its weight; B sc <= 2^61
+  double sc = 1.0;
+  if constexpr (sizeof(T) == 4) {
+    const double wm = fmax(*wmax_d, wmax_r ? alpha * *wmax_r : 0.0);
+    const double bound = (double)(end - start) * wm;
+    int e = 0;
+    if (bound > 0.0) (void)frexp(bound, &e);  // bound < 2^e
+    sc = ldexp(1.0, 61 - e);
+  }
   __syncthreads();
   for (int j = start + threadIdx.x; j < end; j += blockDim.x) {
     const double4 p = payload[j];
@@ -296,20 +328,25 @@ __global__ void __launch_bounds__(256) k_paint_tiles(const int* __restrict__ off
       const long long cu = (long long)floor(u[a]);
       r0[a] = cu - (wrap(cu, nmesh) - t0[a]) - 1;
     }
-    tile_scatter<T, W>(r1, d1, u, wgt, nmesh, r0, rsz);
+    tile_scatter<T, W>(r1, d1, u, wgt, nmesh, r0, rsz, sc);
     if (d2) {
       u[0] = __dadd_rn(u[0], 0.5);
       u[1] = __dadd_rn(u[1], 0.5);
       u[2] = __dadd_rn(u[2], 0.5);
-      tile_scatter<T, W>(r2, d2, u, wgt, nmesh, r0, rsz);
+      tile_scatter<T, W>(r2, d2, u, wgt, nmesh, r0, rsz, sc);
     }
   }
   __syncthreads();
   for (int m = 0; m < nreg; ++m) {
     const double* reg = m ? r2 : r1;
     T* mesh = m ? d2 : d1;
+    const double isc = 1.0 / sc;  // a power of two: exact
     for (int i = threadIdx.x; i < rcells; i += blockDim.x) {
-      const T v = (T)reg[i];
+      T v;
+      if constexpr (sizeof(T) == 4)
+        v = (T)((double)reinterpret_cast<const long long*>(reg)[i] * isc);
+      else
+        v = (T)reg[i];
       if (v == T(0)) continue;
       // region node (ra, rb, rc) is mesh node t0 - 1 + (ra, rb, rc), wrapped once at most
       const int rc = i % rsz, rb = (i / rsz) % rsz, ra = i / (rsz * rsz);
@@ -325,11 +362,11 @@ __global__ void __launch_bounds__(256) k_paint_tiles(const int* __restrict__ off
 }  // namespace
 
 hipError_t launch_catalog_sums(const double* w, const double* nbar, int64_t n, double* partial, int nblk,
-                               double* out2, hipStream_t s) {
+                               double* out2, double* wmax, hipStream_t s) {
   k_catalog_sums<<<nblk, SUM_THREADS, 0, s>>>(w, nbar, n, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_sum_partials2<<<1, SUM_THREADS, 0, s>>>(partial, nblk, out2);
+  k_sum_partials2<<<1, SUM_THREADS, 0, s>>>(partial, nblk, out2, wmax);
   return hipGetLastError();
 }
 
@@ -370,13 +407,14 @@ hipError_t launch_tile_offsets(int* count, int ntiles, int* off, const int* tile
 
 template <typename T>
 hipError_t launch_paint_tiles(const int* off, const void* payload, int ntiles, const double* origin, double scale,
-                              int nmesh, int window, int ts, T* d1, T* d2, hipStream_t s) {
+                              int nmesh, int window, int ts, T* d1, T* d2, const double* wmax_d,
+                              const double* wmax_r, double alpha, hipStream_t s) {
   const size_t sm = sizeof(double) * (size_t)(ts + 4) * (ts + 4) * (ts + 4) * (d2 ? 2 : 1);
   const double4* pl = (const double4*)payload;
 #define PKM_PAINT(WV, TV)                                                                                    \
   if (window == WV && ts == TV) {                                                                            \
     k_paint_tiles<T, WV, TV><<<ntiles, 256, sm, s>>>(off, pl, origin[0], origin[1], origin[2], scale, nmesh, d1, \
-                                                    d2);                                                     \
+                                                    d2, wmax_d, wmax_r, alpha);                              \
     return hipGetLastError();                                                                                \
   }
   PKM_PAINT(1, 4) PKM_PAINT(2, 4) PKM_PAINT(3, 4)
@@ -387,9 +425,9 @@ hipError_t launch_paint_tiles(const int* off, const void* payload, int ntiles, c
 }
 
 template hipError_t launch_paint_tiles<float>(const int*, const void*, int, const double*, double, int, int, int,
-                                              float*, float*, hipStream_t);
+                                              float*, float*, const double*, const double*, double, hipStream_t);
 template hipError_t launch_paint_tiles<double>(const int*, const void*, int, const double*, double, int, int, int,
-                                               double*, double*, hipStream_t);
+                                               double*, double*, const double*, const double*, double, hipStream_t);
 template hipError_t launch_fill<float>(float*, size_t, float, hipStream_t);
 template hipError_t launch_fill<int>(int*, size_t, int, hipStream_t);
 template hipError_t launch_fill<double>(double*, size_t, double, hipStream_t);

@@ -82,7 +82,7 @@ struct pkm_plan {
   size_t partial_cap = 0;  // doubles
   double* out_dev = nullptr;
   size_t out_cap = 0;
-  double* sums_dev = nullptr;  // 4 doubles + block partials
+  double* sums_dev = nullptr;  // 4 sums, the 2 catalogs' max |w|, 3 x SUM_BLOCKS partials
   double* cat_dev = nullptr;   // staging for host catalogs
   size_t cat_cap = 0;          // doubles
   // tile sort of the particles
@@ -448,9 +448,13 @@ template <typename T> void enqueue_paint(pkm_plan* pl, const DevCats& dc) {
   const bool has_r = dc.nr > 0;
   {
     StageScope ss(pl, PKM_STAGE_SUMS);
-    check_hip(pl, launch_catalog_sums(dc.dw, nullptr, dc.nd, pl->sums_dev + 4, SUM_BLOCKS, pl->sums_dev, s), "sums");
+    // sums_dev: [0..3] the sums of both catalogs, [4], [5] their largest |w|, then partials
+    check_hip(pl, launch_catalog_sums(dc.dw, nullptr, dc.nd, pl->sums_dev + 6, SUM_BLOCKS, pl->sums_dev,
+                                      pl->sums_dev + 4, s),
+              "sums");
     if (has_r)
-      check_hip(pl, launch_catalog_sums(dc.rw, dc.rn, dc.nr, pl->sums_dev + 4, SUM_BLOCKS, pl->sums_dev + 2, s),
+      check_hip(pl, launch_catalog_sums(dc.rw, dc.rn, dc.nr, pl->sums_dev + 6, SUM_BLOCKS, pl->sums_dev + 2,
+                                        pl->sums_dev + 5, s),
                 "sums");
   }
   T* d1 = (T*)pl->d1;
@@ -481,7 +485,8 @@ template <typename T> void enqueue_paint(pkm_plan* pl, const DevCats& dc) {
                                       ntot, dc.dp, dc.dw, dc.rp, dc.rw, alpha, pl->payload, pl->scan_sums, s),
               "tile offsets");
     check_hip(pl, launch_paint_tiles<T>(pl->tile_off, pl->payload, pl->ntiles, pl->p.box_origin, scale, n,
-                                        pl->p.window, pl->ts, d1, d2, s),
+                                        pl->p.window, pl->ts, d1, d2, pl->sums_dev + 4,
+                                        has_r ? pl->sums_dev + 5 : nullptr, alpha, s),
               "paint");
   }
   const int nbuf = d2 ? 2 : 1;
@@ -1213,7 +1218,7 @@ pkm_status pkm_plan_create_shaped(const pkm_params* p, const pkm_device* dev, co
     pl->invw = dalloc(pl, pl->es * n);
     pl->phase = dalloc(pl, 2 * pl->es * n);
     pl->ytab = dalloc(pl, pl->es * (YLM_LMAX + 1) * YLM_STRIDE);
-    pl->sums_dev = (double*)dalloc(pl, sizeof(double) * (4 + 2 * SUM_BLOCKS));
+    pl->sums_dev = (double*)dalloc(pl, sizeof(double) * (6 + 3 * SUM_BLOCKS));
     pl->ts = ts0;
     pl->ntiles = (n / pl->ts) * (n / pl->ts) * (n / pl->ts);
     pl->tile_count = (int*)dalloc(pl, sizeof(int) * (size_t)TILE_COUNT_COPIES * (pl->ntiles + 1));
