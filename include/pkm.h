@@ -291,7 +291,10 @@ pkm_status pkm_plan_read_buffer(pkm_plan* plan, int32_t which, void* host_dst, s
  *                 are recorded too, the first enqueues may create them, and pkm_finish adds the
  *                 times to pkm_stats).
  *                 PKM_EBUSY if a previous enqueue has not been finished; PKM_EORDER if the
- *                 plan is not prepared; PKM_EINVAL above the reserved particle count.
+ *                 plan is not prepared, or if a synchronous pkm_compute_multipoles(_basis)
+ *                 with another ell_max, other edges or the Cartesian basis has replaced the
+ *                 prepared request since (prepare again); PKM_EINVAL above the reserved
+ *                 particle count.
  * pkm_query       PKM_OK when the enqueued estimate has completed, PKM_EBUSY while it runs.
  * pkm_finish      waits for it and normalises (FP64, host) into `out` as pkm_compute_multipoles
  *                 does for the prepared ell_max and edges.  Afterwards the plan holds the

@@ -63,6 +63,8 @@ struct pkm_plan {
   void** paint_ptrs = nullptr;  // device array {s1, s2, g} for the paint passes
   ComputeCfg cc;              // tables of the last prepared multipole request
   // asynchronous estimate (pkm_prepare / pkm_enqueue / pkm_finish)
+  int prep_ell = -1;          // the request of the last pkm_prepare (spherical basis)
+  std::vector<double> prep_edges;
   double* slot = nullptr;     // pinned host staging, slot_cap doubles
   size_t slot_cap = 0;
   hipEvent_t done = nullptr;
@@ -1083,6 +1085,8 @@ pkm_status prepare(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges
     if (pl->fp64) prepare_compute<double>(pl, ell_max, k_edges, n_edges);
     else prepare_compute<float>(pl, ell_max, k_edges, n_edges);
     reserve_particles(pl, max_particles);
+    pl->prep_ell = ell_max;
+    pl->prep_edges.assign(k_edges, k_edges + n_edges);
     const size_t want = 4 + (size_t)pl->cc.total_vals;
     if (pl->slot_cap < want) {
       if (pl->slot) check_hip(pl, hipHostFree(pl->slot), "hipHostFree");
@@ -1097,7 +1101,13 @@ pkm_status prepare(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges
 
 // Doubles of a result slot (catalog sums + bin sums) of the prepared request.
 size_t slot_doubles(const pkm_plan* pl) { return 4 + (size_t)pl->cc.total_vals; }
-bool prepared(const pkm_plan* pl) { return pl->cc.ell_max >= 0 && pl->sort_cap > 0; }
+// The request tables are shared with the synchronous calls: a pkm_compute_multipoles with
+// other settings replaces them, and then the prepared request (and the size of its result
+// slot) no longer holds until pkm_prepare is called again.
+bool prepared(const pkm_plan* pl) {
+  return pl->prep_ell >= 0 && pl->sort_cap > 0 && pl->cc.ell_max == pl->prep_ell && pl->cc.basis == 0 &&
+         pl->cc.edges == pl->prep_edges;
+}
 hipStream_t stream_of(const pkm_plan* pl) { return pl->stream; }
 int device_of(const pkm_plan* pl) { return pl->dev.device_id; }
 int64_t device_bytes(const pkm_plan* pl) { return pl->bytes; }
@@ -1111,7 +1121,10 @@ pkm_status enqueue(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* ran
     pl->err = "asynchronous estimates take device-resident catalogs";
     return PKM_EINVAL;
   }
-  if (!prepared(pl)) { pl->err = "plan not prepared (pkm_prepare)"; return PKM_EORDER; }
+  if (!prepared(pl)) {
+    pl->err = "plan not prepared for this request (pkm_prepare, again after a synchronous call with other settings)";
+    return PKM_EORDER;
+  }
   if ((size_t)(data->n + (randoms ? randoms->n : 0)) > pl->sort_cap) {
     pl->err = "particle count above the prepared capacity";
     return PKM_EINVAL;

@@ -92,6 +92,18 @@ def test_async_estimate_matches_sync(gpu, prec):
     # the plan now holds the painted field: a synchronous compute agrees
     again = p.compute_multipoles(lmax, _edges(n))
     _same(again, ref, prec, f"after finish prec={prec}")
+    # a synchronous request with other settings replaces the prepared one: enqueue refuses
+    # (its result slot was sized for the prepared request) until the plan is prepared again
+    from paper_1704_02357_amd import CARTESIAN
+    for other in (dict(ell_max=8, k_edges=_edges(n)), dict(ell_max=lmax, k_edges=_edges(n)[:-3]),
+                  dict(ell_max=lmax, k_edges=_edges(n), basis=CARTESIAN)):
+        p.compute_multipoles(**other)
+        with pytest.raises(PkmError) as e:
+            p.enqueue(dd, rr)
+        assert e.value.status == 2
+    p.prepare(lmax, _edges(n), 30000)
+    p.enqueue(dd, rr)
+    _same(p.finish(), ref, prec, f"re-prepared prec={prec}")
     p.close()
 
 
