@@ -34,8 +34,9 @@ def log(*a):
 
 
 def stage_bytes(nmesh: int, es: int, n_part: int, nfields: int) -> dict:
-    """Algorithmic HBM bytes per estimate of each kernel stage (one read + one write of
-    every element a pass must touch; see the design doc for the derivation)."""
+    """Algorithmic HBM bytes per estimate of each kernel stage: one read and one write of
+    every element a pass must touch (X bytes per mesh or half spectrum, 40 bytes per
+    catalog object read by the sums and the painter)."""
     X = es * nmesh ** 3          # half spectrum (N x N x N/2 complex) == real mesh bytes
     return {
         "sums": 40.0 * n_part,
@@ -568,7 +569,7 @@ def main():
         summarize_profile(args.summarize_profile)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1).",
               file=sys.stderr)
         sys.exit(2)
     import torch

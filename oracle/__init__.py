@@ -20,7 +20,7 @@ Everything is plain numpy / scipy in float64, written from the paper
 * ``systematics`` - delta_l (eq. delta-ell), response R(mu) (eq. response) and the
                   non-uniform mu edges (eq. nonuniform-bins).
 
-Conventions (the paper leaves them open; the readings are listed in the design doc):
+Conventions (points the paper leaves open, read the same way by the GPU library):
 node c of an N^3 mesh sits at o + c H (H = L/N); forward DFT uses exp(-2 pi i n.c/N);
 integer frequencies n_a lie in [-N/2, N/2); modes with any n_a = -N/2 (the Nyquist
 planes) are zero in the combined field and belong to no k bin; k = 0 belongs to no bin.
