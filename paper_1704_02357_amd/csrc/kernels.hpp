@@ -17,7 +17,7 @@ struct FftShape {
   int nst_z;
   int tile;         // columns per column-pass tile
   int zlines;       // lines per z-pass block
-  int e_post;       // elements per thread in the post-pass (x transform + binning)
+  int e_post;       // elements per thread in the post-pass (last transform + binning)
   uint32_t sched_post;
   int nst_post;
   int tile_post;    // columns per post-pass tile

@@ -12,8 +12,12 @@
 //   column   : length-N transforms along y or x over tiles of `tile` adjacent kz columns.
 //   xcombine : forward x of both painted meshes + interlace combine + compensation +
 //              Nyquist zero, then inverse x of C.
-//   xpost    : forward x of every field of a group, sum_m Y_lm(khat) B_lm, product with
-//              C, and binning into per-block partial sums.
+//   xpost    : last transform of every field of a group (along x for FP32, along y for
+//              FP64), sum_m Y_lm(khat) B_lm, product with C, and binning into per-block
+//              partial sums.
+// Both harmonic passes evaluate Y_lm for the direction turned by the plan's Frame (any
+// orthogonal frame gives the same sums over m), or, with the CART flag, the monomials of
+// the Cartesian decomposition.
 //
 // Every kernel takes two extra template constants: NC (mesh side) and TC (tile width, or
 // lines per block for the z passes).  For power-of-two meshes the launchers instantiate them

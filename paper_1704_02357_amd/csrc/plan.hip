@@ -6,10 +6,12 @@
 //   of C) -> inverse y of G,
 // leaving C (the combined field, F_0 of eq. Pell-ours) and G (D_c, transformed along z only)
 // resident.  pkm_compute_multipoles then runs, per group of (l, m) fields,
-//   zpre (inverse z of G = D_c, Y_lm(xhat) weighting, forward z per field) -> forward y per
-//   field -> xpost (forward x, sum_m Y_lm(khat) B_lm, product with C, binning)
+//   zpre (inverse z of G = D_c, Y_lm(xhat) weighting, forward z per field) -> column pass
+//   per field (y for FP32, x for FP64) -> xpost (the remaining axis, sum_m Y_lm(khat) B_lm,
+//   product with C, binning)
 // and one fixed-order reduction per group.  The l = 0 bin (|C|^2) and the mode counts are
-// taken in the first xpost pass.
+// taken in the first xpost pass.  pkm_prepare / pkm_enqueue / pkm_finish issue the same
+// work asynchronously; runtime.hip builds batches and the serving loop on them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
