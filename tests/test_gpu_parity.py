@@ -249,3 +249,32 @@ def test_observer_positions(gpu, prec, observer):
     plan.close()
     ref = multipoles(d, r, oracle_params(n, L, observer, 3, True, True), 8, edges)
     assert_pole_parity(got, ref, prec, f"observer {observer}")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_paint_weights_over_three_decades(gpu, prec):
+    """Painted meshes (both, interlaced TSC) for weights log-uniform in [0.01, 10] on data and
+    randoms: the FP32 form accumulates in fixed point with a per-tile scale set by the
+    largest |w|, the FP64 form in FP64."""
+    from oracle.catalog import catalog_scalars
+    from oracle.mesh import fkp_meshes
+    from synth import Catalog
+    n, L = 32, 200.0
+    rng = np.random.default_rng(303)
+    o = -0.5 * L
+    nd, nr = 4000, 30000
+    d = Catalog(o + rng.random((nd, 3)) * L, 10.0 ** rng.uniform(-2, 1, nd), np.full(nd, nd / L ** 3))
+    r = Catalog(o + rng.random((nr, 3)) * L, 10.0 ** rng.uniform(-2, 1, nr), np.full(nr, nd / L ** 3))
+    print(f"[case] paint three-decade weights prec={prec}", flush=True)
+    plan = _plan(n, L, prec, OBS, 3, True, True)
+    plan.paint(d, r)
+    sc = catalog_scalars(d, r, L)
+    p = oracle_params(n, L, OBS, 3, True, True)
+    d1, d2 = fkp_meshes(d, r, sc["alpha"], n, L, p["box_origin"], 3, True)
+    tol = 1e-13 if prec else 2e-6
+    for which, ref in ((0, d1), (1, d2)):
+        got = plan.read_buffer(which)
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        print(f"[paint] mesh {which} prec={prec} max_err/max={err:.2e}", flush=True)
+        assert err <= tol
+    plan.close()
