@@ -36,7 +36,9 @@
  *
  * Errors.  Every function returns a pkm_status; nothing aborts or throws across the ABI.
  *   On error the outputs are untouched and pkm_plan_last_error() holds a message.
- *   PKM_EINVAL leaves the plan unchanged.  After PKM_EDEVICE the plan must be destroyed.
+ *   PKM_EINVAL leaves the plan unchanged, except for the normalisation check of painting
+ *   (pkm_paint, pkm_finish), which leaves it unpainted.  After PKM_EDEVICE the plan must be
+ *   destroyed.
  */
 #ifndef PKM_H
 #define PKM_H
@@ -197,7 +199,10 @@ pkm_status pkm_autotune(const pkm_params* p, const pkm_device* dev, int32_t ell_
 /* Sec. 2.1 (eq. FKP-density) and Sec. 2.3: catalog scalars, painting of data minus
  * alpha x randoms (randoms NULL -> periodic box), forward transforms, interlace combine,
  * compensation, and the inverse transform of the combined field.  Replaces any previous
- * paint of this plan.                                                                       */
+ * paint of this plan.  The estimate divides by the normalisation I = alpha sum_r n-bar w^2
+ * (n-bar sum_d w^2 in a periodic box): when I is not positive (every random weight or n-bar
+ * zero, or every data weight in a periodic box), PKM_EINVAL and the plan is left unpainted
+ * (PKM_EORDER until the next successful paint).                                            */
 pkm_status pkm_paint(pkm_plan* plan, const pkm_catalog* data, const pkm_catalog* randoms);
 
 /* Sec. 2.1 eq. Pell-ours / eq. Fell, binned as in Sec. 2.2 (uniform or arbitrary increasing
@@ -298,7 +303,8 @@ pkm_status pkm_plan_read_buffer(pkm_plan* plan, int32_t which, void* host_dst, s
  * pkm_query       PKM_OK when the enqueued estimate has completed, PKM_EBUSY while it runs.
  * pkm_finish      waits for it and normalises (FP64, host) into `out` as pkm_compute_multipoles
  *                 does for the prepared ell_max and edges.  Afterwards the plan holds the
- *                 painted field as after pkm_paint.
+ *                 painted field as after pkm_paint.  PKM_EINVAL (plan unpainted, `out`
+ *                 untouched) when the normalisation I is not positive, as for pkm_paint.
  * pkm_paint / pkm_compute_multipoles return PKM_EBUSY between pkm_enqueue and pkm_finish.
  * ------------------------------------------------------------------------------------- */
 pkm_status pkm_prepare(pkm_plan* plan, int32_t ell_max, const double* k_edges, int32_t n_edges,
@@ -319,7 +325,9 @@ pkm_status pkm_finish(pkm_plan* plan, pkm_result* out);
  * while the batch holds them.
  *   pkm_batch_run    issues (or replays) every item, waits, and reports the device time
  *                    from the fork to the join in *ms_out (may be NULL).
- *   pkm_batch_result normalises item `index` of the last run into `out` (FP64, host).
+ *   pkm_batch_result normalises item `index` of the last run into `out` (FP64, host);
+ *                    PKM_EINVAL, `out` untouched, when the item's normalisation I is not
+ *                    positive (as for pkm_paint).
  * ------------------------------------------------------------------------------------- */
 typedef struct pkm_batch pkm_batch;
 pkm_status pkm_batch_create(int32_t device_id, pkm_batch** out);
@@ -342,7 +350,8 @@ void pkm_batch_destroy(pkm_batch* batch);
  * Results are computed exactly as by pkm_paint + pkm_compute_multipoles.
  *   pkm_server_submit  queues a request and returns its ticket (PKM_EINVAL on bad input).
  *   pkm_server_poll    PKM_EBUSY until the request has finished, then copies the result
- *                      into `out` (arrays sized as for pkm_compute_multipoles) once.
+ *                      into `out` (arrays sized as for pkm_compute_multipoles) once.  A
+ *                      request whose normalisation I is not positive fails with PKM_EINVAL.
  *   pkm_server_wait    blocks until then.
  *   pkm_server_stats   completed / failed / queued / in-flight counts, resident and peak
  *                      device bytes, the largest number of concurrent estimates seen,

@@ -24,8 +24,9 @@ std::string& error_of(pkm_plan* pl);
 // `timed`: record the plan's per-launch timing events when stage timing is on (never inside
 // a graph capture).
 pkm_status enqueue(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* randoms, double* slot, bool timed);
-// Normalise a completed slot into `out` (the prepared ell_max and edges).
-void finish(pkm_plan* pl, const double* slot, int64_t nd, int64_t nr, pkm_result* out);
+// Normalise a completed slot into `out` (the prepared ell_max and edges).  PKM_EINVAL
+// (reason in *why, `out` untouched) when the normalisation I is not positive.
+pkm_status finish(pkm_plan* pl, const double* slot, int64_t nd, int64_t nr, pkm_result* out, std::string* why);
 // Device bytes a plan with these parameters would hold for one request (admission control).
 int64_t footprint(const pkm_params* p, int ell_max, int n_edges, int64_t n_particles);
 

@@ -443,6 +443,12 @@ void scalars_of(const pkm_plan* pl, const double* sums, int64_t nd, int64_t nr, 
   }
 }
 
+// The estimator divides by I (Sec. 2.1, eq. FKP-density): it has no value when I is not positive, as when every
+// random weight (or n-bar), or in a periodic box every data weight, is zero.
+bool norm_ok(double norm_I) { return norm_I > 0.0 && std::isfinite(norm_I); }
+const char* const ZERO_NORM = "normalisation I is not positive (the weights or n-bar of the randoms, or the "
+                              "weights of the data in a periodic box, sum to zero)";
+
 // Catalog sums, painting, forward transforms, combine and inverse of the combined field.
 // Leaves the sums in sums_dev[0..3], C and G resident.  Needs sort capacity >= nd + nr.
 template <typename T> void enqueue_paint(pkm_plan* pl, const DevCats& dc) {
@@ -527,6 +533,10 @@ template <typename T> void run_paint(pkm_plan* pl, const pkm_catalog* data, cons
   check_hip(pl, hipEventRecord(pl->ev1, s), "event");
   check_hip(pl, hipStreamSynchronize(s), "sync");
   scalars_of(pl, sums, dc.nd, dc.nr, &pl->alpha, &pl->norm_I, &pl->shot);
+  if (!norm_ok(pl->norm_I)) {
+    pl->err = ZERO_NORM;
+    throw Fail{PKM_EINVAL};
+  }
   resolve_stages(pl);
   float ms = 0;
   (void)hipEventElapsedTime(&ms, pl->ev0, pl->ev1);
@@ -799,13 +809,16 @@ template <typename T> void enqueue_estimate(pkm_plan* pl, const DevCats& dc, dou
             "download bins");
 }
 
-void finish_from_slot(const pkm_plan* pl, const double* slot, int64_t nd, int64_t nr, pkm_result* out) {
+// PKM_EINVAL, with `out` untouched, when the normalisation has no value.
+pkm_status finish_from_slot(const pkm_plan* pl, const double* slot, int64_t nd, int64_t nr, pkm_result* out) {
   double alpha, norm_I, shot;
   scalars_of(pl, slot, nd, nr, &alpha, &norm_I, &shot);
+  if (!norm_ok(norm_I)) return PKM_EINVAL;
   normalize(pl, slot + 4, norm_I, shot, out);
   out->alpha = alpha;
   out->norm_I = norm_I;
   out->shot_noise = shot;
+  return PKM_OK;
 }
 
 template <typename T>
@@ -1145,8 +1158,10 @@ pkm_status enqueue(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* ran
   return st;
 }
 
-void finish(pkm_plan* pl, const double* slot, int64_t nd, int64_t nr, pkm_result* out) {
-  finish_from_slot(pl, slot, nd, nr, out);
+pkm_status finish(pkm_plan* pl, const double* slot, int64_t nd, int64_t nr, pkm_result* out, std::string* why) {
+  const pkm_status st = finish_from_slot(pl, slot, nd, nr, out);
+  if (st != PKM_OK) *why = ZERO_NORM;
+  return st;
 }
 
 int64_t footprint(const pkm_params* p, int ell_max, int n_edges, int64_t n_particles) {
@@ -1578,7 +1593,10 @@ pkm_status pkm_finish(pkm_plan* pl, pkm_result* out) {
   pl->pending_async = false;
   if (st != PKM_OK) return st;
   resolve_stages(pl);
-  finish_from_slot(pl, pl->slot, pl->pend_nd, pl->pend_nr, out);
+  if (finish_from_slot(pl, pl->slot, pl->pend_nd, pl->pend_nr, out) != PKM_OK) {
+    pl->err = ZERO_NORM;  // the plan stays unpainted
+    return PKM_EINVAL;
+  }
   pl->alpha = out->alpha;
   pl->norm_I = out->norm_I;
   pl->shot = out->shot_noise;

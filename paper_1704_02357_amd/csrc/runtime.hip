@@ -226,8 +226,7 @@ pkm_status pkm_batch_result(pkm_batch* b, int32_t index, pkm_result* out) {
   if (!out || index < 0 || (size_t)index >= b->items.size()) { b->err = "bad index or result"; return PKM_EINVAL; }
   if (!b->ran) { b->err = "batch has not run since its last change"; return PKM_EORDER; }
   BatchItem& it = b->items[index];
-  pkm_internal::finish(it.plan, it.slot->p, it.data.n, it.has_rand ? it.rand.n : 0, out);
-  return PKM_OK;
+  return pkm_internal::finish(it.plan, it.slot->p, it.data.n, it.has_rand ? it.rand.n : 0, out, &b->err);
 }
 
 int32_t pkm_batch_size(const pkm_batch* b) { return b ? (int32_t)b->items.size() : 0; }
@@ -520,7 +519,7 @@ void reap(pkm_server* sv, std::unique_lock<std::mutex>& lk) {
       res.poles = r->poles.data();
       res.k_mean = r->kmean.data();
       res.n_modes = r->nmodes.data();
-      pkm_internal::finish(r->slot_plan->plan, r->slot_plan->result.p, r->nd, r->nr, &res);
+      st = pkm_internal::finish(r->slot_plan->plan, r->slot_plan->result.p, r->nd, r->nr, &res, &r->err);
       r->alpha = res.alpha;
       r->norm_I = res.norm_I;
       r->shot = res.shot_noise;

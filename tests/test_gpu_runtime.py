@@ -107,6 +107,74 @@ def test_async_estimate_matches_sync(gpu, prec):
     p.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_zero_normalisation_rejected(gpu, prec):
+    """A catalog whose normalisation I vanishes (every random weight zero, or every data
+    weight zero in a periodic box) has no estimate: painting, the asynchronous finish, a
+    batch item and a served request report PKM_EINVAL, outputs untouched and the plan left
+    unpainted; the next good paint on the same plan gives the estimate run alone."""
+    import torch
+    from paper_1704_02357_amd import Batch, PkmError, Server
+    from synth import Catalog
+    n, lmax = 32, 4
+    d, r = small_catalogs(2000, 12000, L, seed=81)
+    r0 = Catalog(r.pos, np.zeros(len(r.pos)), r.nbar)
+    d0 = Catalog(d.pos, np.zeros(len(d.pos)), d.nbar)
+    ref = _alone(n, prec, lmax, d, r)
+    print(f"[case] zero normalisation prec={prec}: synchronous paint", flush=True)
+    p = _plan(n, prec, lmax)
+    for bad in ((d, r0), (d0, None)):
+        with pytest.raises(PkmError) as e:
+            p.paint(*bad)
+        assert e.value.status == 1 and "normalisation" in str(e.value)
+        with pytest.raises(PkmError) as e:
+            p.compute_multipoles(lmax, _edges(n))
+        assert e.value.status == 2
+    p.paint(d, r)
+    _same(p.compute_multipoles(lmax, _edges(n)), ref, prec, f"after rejected paint prec={prec}")
+    p.close()
+
+    print(f"[case] zero normalisation prec={prec}: enqueue / finish", flush=True)
+    p = _plan(n, prec, lmax, stream=torch.cuda.Stream())
+    p.prepare(lmax, _edges(n), 14000)
+    dd, rr, rr0 = _dev(d), _dev(r), _dev(r0)
+    p.enqueue(dd, rr0)
+    with pytest.raises(PkmError) as e:
+        p.finish()
+    assert e.value.status == 1
+    with pytest.raises(PkmError) as e:
+        p.compute_multipoles(lmax, _edges(n))
+    assert e.value.status == 2
+    p.enqueue(dd, rr)
+    _same(p.finish(), ref, prec, f"enqueue after rejected finish prec={prec}")
+
+    print(f"[case] zero normalisation prec={prec}: batch", flush=True)
+    q = _plan(n, prec, lmax, stream=torch.cuda.Stream())
+    q.prepare(lmax, _edges(n), 14000)
+    b = Batch()
+    b.add(p, dd, rr0)
+    b.add(q, dd, rr)
+    b.run(use_graph=False)
+    with pytest.raises(PkmError) as e:
+        b.result(0)
+    assert e.value.status == 1
+    _same(b.result(1), ref, prec, f"batch item beside a rejected one prec={prec}")
+    b.close()
+    p.close()
+    q.close()
+
+    print(f"[case] zero normalisation prec={prec}: server", flush=True)
+    sv = Server(max_inflight=2)
+    kw = dict(observer=OBS, window=3, interlaced=True, compensated=True, precision=prec, ell_max_hint=lmax)
+    bad = sv.submit(n, L, lmax, _edges(n), d, r0, **kw)
+    good = sv.submit(n, L, lmax, _edges(n), d, r, **kw)
+    with pytest.raises(PkmError) as e:
+        sv.wait(bad)
+    assert e.value.status == 1
+    _same(sv.wait(good), ref, prec, f"served request beside a rejected one prec={prec}")
+    sv.close()
+
+
 def test_batch_uneven_mocks_graph_replays(gpu):
     """Six mocks on three mesh sizes (two plans per size, each on its own stream), issued
     directly and as one captured graph; replays with eager work in between, and a replay
