@@ -519,13 +519,18 @@ def serve_bench(args) -> dict:
                 time.sleep(delay)
             tickets[i] = sv.submit(n, L, lmax, edges, d, r, observer=OBSERVER, window=3, interlaced=True,
                                    compensated=True, precision=prec, ell_max_hint=lmax)
+            if (i + 1) % 50 == 0:
+                log(f"[serve] {i + 1} of {len(reqs)} requests submitted at {time.perf_counter() - start:.0f} s, "
+                    f"{sv.stats()['completed']} completed")
 
     s0 = time.perf_counter()
     th = threading.Thread(target=submitter)
     th.start()
     th.join()
-    for t in tickets:
+    for i, t in enumerate(tickets):
         sv.wait(t)
+        if (i + 1) % 100 == 0:
+            log(f"[serve] {i + 1} of {len(reqs)} results collected at {time.perf_counter() - s0:.0f} s")
     wall = time.perf_counter() - s0
     st = sv.stats()
     sv.close()
