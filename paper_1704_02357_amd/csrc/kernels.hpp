@@ -23,6 +23,8 @@ struct FftShape {
   int tile_post;    // columns per post-pass tile
   int cus;          // compute units of the device (0: unknown)
   int post_axis;    // last transform axis of the weighted fields: 0 = x, 1 = y
+  int fpad;         // extra elements per x plane of a field buffer (post_axis 0 only): the
+                    // plane stride n n/2 + fpad is then not a power of two
 };
 
 // Bytes of LDS of the z-pass and column-pass blocks of a shape.
@@ -87,9 +89,10 @@ hipError_t launch_zfwd(const FftShape& fs, const T* in0, const T* in1, void* out
                        const void* tw, hipStream_t s);
 
 // Column transform along y (axis = 1) or x (axis = 0) of nbuf half-spectra in place.
+// fields = true: the buffers are field buffers (x planes fs.fpad elements apart beyond n n/2).
 template <typename T>
 hipError_t launch_col(const FftShape& fs, void* const* bufs_dev, int nbuf, int axis, bool inverse,
-                      const void* tw, hipStream_t s);
+                      const void* tw, hipStream_t s, bool fields = false);
 
 // x-pass of the forward transforms of the two painted meshes, interlace combine,
 // compensation and Nyquist zeroing; writes C and, when g_out != null, G = C inverse-

@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n_rt, int g_rt, uint3
                                                         int nf, const int* __restrict__ fields, T scale, double off0,
                                                         double off1, double off2, double h,
                                                         const T* __restrict__ ytab, const cx<T>* __restrict__ tw,
-                                                        Frame fr) {
+                                                        Frame fr, int fpad) {
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
   const int n = NC > 0 ? NC : n_rt;
@@ -437,7 +437,7 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n_rt, int g_rt, uint3
     for (int e = 0; e < E; ++e) line[padi<ZPAD>(t + pt * e)] = u[e];
     if constexpr (NC > 0) ct_sync<WAVE>(); else __syncthreads();
     cx<T>* out = reinterpret_cast<cx<T>*>(bufs[fields[4 * f]]);
-    const size_t ob = lineg * nh;
+    const size_t ob = (size_t)ix * ((size_t)n * nh + fpad) + (size_t)iy * nh;  // padded x planes
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int k = t + pt * e;
@@ -517,7 +517,8 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
                                                           const T* __restrict__ ytab,
                                                           const long long* __restrict__ thr, int nb, int copies,
                                                           double* __restrict__ partial,
-                                                          const cx<T>* __restrict__ tw, int axis, Frame frm) {
+                                                          const cx<T>* __restrict__ tw, int axis, Frame frm,
+                                                          int fpad) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = NC > 0 ? NC : n_rt;
   const int tile = TC > 0 ? TC : tile_rt;
@@ -550,10 +551,12 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
   const TileWalk walk(n * tiles_x);
   __syncthreads();  // histogram zeroed, thresholds and twiddles staged
   auto base_of = [&](int tl) { return (size_t)(tl / tiles_x) * os + (size_t)(tl % tiles_x) * tile; };
+  // field rows (x planes, axis 0) are fpad elements further apart than those of C
+  const size_t frs = rs + fpad;
   cx<T> nxt[E];
   int j = walk.first;
   if (j < walk.end && nf > 0)
-    tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[0]]), base_of(walk.tile(j)), rs, tile, bs);
+    tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[0]]), base_of(walk.tile(j)), frs, tile, bs);
   int parity = 0;
   for (; j < walk.end; j += walk.step) {
     const int tl = walk.tile(j);
@@ -599,9 +602,9 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
       tile_to_lds<T, E, XPAD>(tb, nxt, tile, pitch, bs);
       // prefetch the next field's tile (or the next tile's first field) during this one
       if (f + 1 < nf)
-        tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[4 * (f + 1)]]), base, rs, tile, bs);
+        tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[4 * (f + 1)]]), base, frs, tile, bs);
       else if (j + walk.step < walk.end)
-        tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[0]]), base_of(walk.tile(j + walk.step)), rs,
+        tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[0]]), base_of(walk.tile(j + walk.step)), frs,
                         tile, bs);
       __syncthreads();
       cx<T> u[E];
@@ -808,10 +811,12 @@ hipError_t launch_zfwd(const FftShape& fs, const T* in0, const T* in1, void* out
 
 template <typename T>
 hipError_t launch_col(const FftShape& fs, void* const* bufs_dev, int nbuf, int axis, bool inverse, const void* tw,
-                      hipStream_t s) {
+                      hipStream_t s, bool fields) {
   const size_t nh = fs.n / 2;
-  const size_t row_stride = axis == 1 ? nh : (size_t)fs.n * nh;
-  const size_t outer_stride = axis == 1 ? (size_t)fs.n * nh : nh;
+  const size_t plane = (size_t)fs.n * nh + (fields ? fs.fpad : 0);
+  if (fields && fs.fpad && axis != 1) return hipErrorInvalidValue;
+  const size_t row_stride = axis == 1 ? nh : plane;
+  const size_t outer_stride = axis == 1 ? plane : nh;
   dim3 grid(xpass_blocks(fs), nbuf);
   const size_t sm = colsmem(fs, sizeof(cx<T>));
   if (inverse) {
@@ -852,11 +857,11 @@ hipError_t launch_zpre_basis(const FftShape& fs, const void* g_in, const T* real
   const size_t sm = zsmem(fs, sizeof(cx<T>));
   PKM_TRY_Z((k_zpre<T, E, NC, TC, CART><<<lines / fs.zlines, zthreads(fs), sm, s>>>(
       fs.n, fs.zlines, fs.sched_z, fs.nst_z, (const cx<T>*)g_in, real_in, real_out, bufs_dev, nf, fields_dev,
-      (T)scale, off[0], off[1], off[2], h, (const T*)ytab, (const cx<T>*)tw, frame)));
+      (T)scale, off[0], off[1], off[2], h, (const T*)ytab, (const cx<T>*)tw, frame, fs.fpad)));
   PKM_DISPATCH_E(fs.e_z, (k_zpre<T, E, 0, 0, CART><<<lines / fs.zlines, zthreads(fs), sm, s>>>(
                              fs.n, fs.zlines, fs.sched_z, fs.nst_z, (const cx<T>*)g_in, real_in, real_out, bufs_dev,
                              nf, fields_dev, (T)scale, off[0], off[1], off[2], h, (const T*)ytab,
-                             (const cx<T>*)tw, frame)));
+                             (const cx<T>*)tw, frame, fs.fpad)));
   return hipGetLastError();
 }
 
@@ -876,7 +881,7 @@ hipError_t launch_xpost_basis(const FftShape& fs, void* const* bufs_dev, int nf,
                               int with_l0, const void* c_in, const void* ytab, const BinSpec& bs, double kf,
                               double* partial, int* nblocks_out, const void* tw, int axis, const Frame& frame,
                               hipStream_t s) {
-  if (nslots < 0) return hipErrorInvalidValue;
+  if (nslots < 0 || (fs.fpad && axis != 0)) return hipErrorInvalidValue;
   const int rows = (with_l0 ? 3 : 0) + nslots;
   const size_t sm = xpost_base_bytes(fs, sizeof(T) == 8) + sizeof(double) * (size_t)bs.hist_copies * rows * bs.nb +
                     sizeof(long long) * (size_t)(bs.nb + 1);
@@ -886,11 +891,12 @@ hipError_t launch_xpost_basis(const FftShape& fs, void* const* bufs_dev, int nf,
   *nblocks_out = nblk;
   PKM_TRY_POST((k_xpost<T, E, NC, TC, CART><<<nblk, nthr, sm, s>>>(
       fs.n, fs.tile_post, fs.sched_post, fs.nst_post, bufs_dev, nf, fields_dev, nslots, with_l0, kf,
-      (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies, partial, (const cx<T>*)tw, axis, frame)));
+      (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies, partial, (const cx<T>*)tw, axis, frame,
+      fs.fpad)));
   PKM_DISPATCH_E(fs.e_post, (k_xpost<T, E, 0, 0, CART><<<nblk, nthr, sm, s>>>(
                                 fs.n, fs.tile_post, fs.sched_post, fs.nst_post, bufs_dev, nf, fields_dev, nslots,
                                 with_l0, kf, (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies,
-                                partial, (const cx<T>*)tw, axis, frame)));
+                                partial, (const cx<T>*)tw, axis, frame, fs.fpad)));
   return hipGetLastError();
 }
 
@@ -925,7 +931,8 @@ hipError_t launch_kmu(const FftShape& fs, const void* c_in, const double* los, c
 #define PKM_INST(T)                                                                                           \
   template hipError_t launch_zfwd<T>(const FftShape&, const T*, const T*, void*, void*, int, const void*,         \
                                      hipStream_t);                                                                \
-  template hipError_t launch_col<T>(const FftShape&, void* const*, int, int, bool, const void*, hipStream_t);    \
+  template hipError_t launch_col<T>(const FftShape&, void* const*, int, int, bool, const void*, hipStream_t,     \
+                                     bool);                                                                        \
   template hipError_t launch_xcombine<T>(const FftShape&, void*, void*, void*, void*, int, int, const void*,     \
                                          const void*, const void*, hipStream_t);                                 \
   template hipError_t launch_zpre<T>(const FftShape&, const void*, const T*, T*, void* const*, int, const int*,   \

@@ -332,8 +332,11 @@ std::vector<double> legendre_coeffs(int l) {
   return b;
 }
 
+// Bytes of one field buffer: n x planes of n n/2 + fpad complex values.
+size_t field_bytes(const pkm_plan* pl) { return pl->mesh_bytes + (size_t)pl->p.nmesh * pl->fs.fpad * 2 * pl->es; }
+
 void ensure_fields(pkm_plan* pl, int want) {
-  while ((int)pl->fields.size() < want) pl->fields.push_back(dalloc(pl, pl->mesh_bytes));
+  while ((int)pl->fields.size() < want) pl->fields.push_back(dalloc(pl, field_bytes(pl)));
   const int need_ptr = (int)pl->fields.size() + 8;
   if (pl->ptr_cap < need_ptr) {
     dfree(pl, pl->ptrs_dev);
@@ -720,7 +723,7 @@ template <typename T> void enqueue_compute(pkm_plan* pl) {
       // here and their y pass in the post-pass (whose rows are then nh, not n nh, elements
       // apart: measured faster for FP64, slower for FP32)
       StageScope ss(pl, PKM_STAGE_YCOL);
-      check_hip(pl, launch_col<T>(pl->fs, pl->ptrs_dev, gc.nf, post_axis == 1 ? 0 : 1, false, pl->tw, s),
+      check_hip(pl, launch_col<T>(pl->fs, pl->ptrs_dev, gc.nf, post_axis == 1 ? 0 : 1, false, pl->tw, s, true),
                 "field column pass");
     }
     int nblocks = 0;
@@ -899,6 +902,11 @@ template <typename T> void read_dc(pkm_plan* pl, void* host, size_t bytes) {
 }
 
 // Launch shape of the transform passes for one mesh size and precision.
+// Field buffers of a post-pass along x get x planes of n n/2 + 32 elements: with the plain
+// power-of-two plane stride the post-pass's column reads (one row piece per plane) fall on
+// few HBM channels.  Measured at 512^3: 32 and 16 best, 64 close, 128 and 256 slower than none.
+int field_pad(int post_axis) { return post_axis == 0 ? 32 : 0; }
+
 bool make_shape(const pkm_params& p, FftShape* out) {
   FftShape fs{};
   const int n = p.nmesh;
@@ -943,6 +951,7 @@ bool make_shape(const pkm_params& p, FftShape* out) {
   fs.zlines = zl;
   // FP64 fields finish along y (rows nh apart): measured faster; FP32 along x
   fs.post_axis = fp64 ? 1 : 0;
+  fs.fpad = field_pad(fs.post_axis);
   *out = fs;
   return true;
 }
@@ -982,6 +991,7 @@ bool apply_shape(const pkm_params& p, const pkm_shape& sh, FftShape* fs, int* ts
     if (sh.post_axis != 1 && sh.post_axis != 2) return fail("post_axis must be 1 (x) or 2 (y)");
     f.post_axis = sh.post_axis - 1;
   }
+  f.fpad = field_pad(f.post_axis);
   if (sh.paint_tile) {
     if ((sh.paint_tile != 4 && sh.paint_tile != 8 && sh.paint_tile != 16) || n % sh.paint_tile)
       return fail("paint_tile must be 4, 8 or 16 and divide nmesh");
@@ -1173,11 +1183,12 @@ int64_t footprint(const pkm_params* p, int ell_max, int n_edges, int64_t n_parti
   if (p->max_group > 0) nf = std::min(nf, p->max_group);
   nf = std::max(nf, 1);
   const int64_t meshes = (p->interlaced ? 6 : 4) + nf;
+  const int64_t pads = (int64_t)nf * n * fs.fpad * 2 * (p->precision == PKM_FP64 ? 8 : 4);
   const int64_t nb = std::max(1, n_edges - 1);
   const int64_t partial = (int64_t)post_blocks(fs) * (3 + ell_max / 2) * nb * 8;
   const int64_t ts = 8;
   const int64_t ntiles = (n / ts) * (n / ts) * (n / ts);
-  return meshes * mesh + 80 * n_particles + partial + 8 * ntiles + (4 << 20);
+  return meshes * mesh + pads + 80 * n_particles + partial + 8 * ntiles + (4 << 20);
 }
 
 }  // namespace pkm_internal
