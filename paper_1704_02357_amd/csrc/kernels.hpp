@@ -23,8 +23,8 @@ struct FftShape {
   int tile_post;    // columns per post-pass tile
   int cus;          // compute units of the device (0: unknown)
   int post_axis;    // last transform axis of the weighted fields: 0 = x, 1 = y
-  int fpad;         // extra elements per x plane of a field buffer (post_axis 0 only): the
-                    // plane stride n n/2 + fpad is then not a power of two
+  int fpad;         // extra elements per x plane of a field buffer: the plane stride
+                    // n n/2 + fpad is then not a power of two
 };
 
 // Bytes of LDS of the z-pass and column-pass blocks of a shape.

@@ -551,18 +551,23 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
   const TileWalk walk(n * tiles_x);
   __syncthreads();  // histogram zeroed, thresholds and twiddles staged
   auto base_of = [&](int tl) { return (size_t)(tl / tiles_x) * os + (size_t)(tl % tiles_x) * tile; };
-  // field rows (x planes, axis 0) are fpad elements further apart than those of C
-  const size_t frs = rs + fpad;
+  // x planes of the field buffers are fpad elements further apart than those of C: the
+  // field rows (axis 0) or the field tiles' planes (axis 1)
+  const size_t frs = axis ? rs : rs + fpad;
+  auto fbase_of = [&](int tl) {
+    return axis ? (size_t)(tl / tiles_x) * (os + fpad) + (size_t)(tl % tiles_x) * tile : base_of(tl);
+  };
   cx<T> nxt[E];
   int j = walk.first;
   if (j < walk.end && nf > 0)
-    tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[0]]), base_of(walk.tile(j)), frs, tile, bs);
+    tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[0]]), fbase_of(walk.tile(j)), frs, tile, bs);
   int parity = 0;
   for (; j < walk.end; j += walk.step) {
     const int tl = walk.tile(j);
     const int o = tl / tiles_x;  // the tile's fixed x (axis 1) or y (axis 0) index
     const int kz = (tl % tiles_x) * tile + c;
     const size_t base = base_of(tl);
+    const size_t fbase = fbase_of(tl);
     const int fo = sfreq(o, n);
     const bool onyq = (o == nh);
     // Hermitian weight; the spherical sum also carries the 4 pi of the addition theorem
@@ -602,10 +607,10 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
       tile_to_lds<T, E, XPAD>(tb, nxt, tile, pitch, bs);
       // prefetch the next field's tile (or the next tile's first field) during this one
       if (f + 1 < nf)
-        tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[4 * (f + 1)]]), base, frs, tile, bs);
+        tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[4 * (f + 1)]]), fbase, frs, tile, bs);
       else if (j + walk.step < walk.end)
-        tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[0]]), base_of(walk.tile(j + walk.step)), frs,
-                        tile, bs);
+        tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[0]]), fbase_of(walk.tile(j + walk.step)),
+                        frs, tile, bs);
       __syncthreads();
       cx<T> u[E];
       xf_lds_in<T, E, false, XPAD, NC, WAVE>(tb, c, pitch, rt, t, u, twst, twl);
@@ -814,7 +819,6 @@ hipError_t launch_col(const FftShape& fs, void* const* bufs_dev, int nbuf, int a
                       hipStream_t s, bool fields) {
   const size_t nh = fs.n / 2;
   const size_t plane = (size_t)fs.n * nh + (fields ? fs.fpad : 0);
-  if (fields && fs.fpad && axis != 1) return hipErrorInvalidValue;
   const size_t row_stride = axis == 1 ? nh : plane;
   const size_t outer_stride = axis == 1 ? plane : nh;
   dim3 grid(xpass_blocks(fs), nbuf);
@@ -881,7 +885,7 @@ hipError_t launch_xpost_basis(const FftShape& fs, void* const* bufs_dev, int nf,
                               int with_l0, const void* c_in, const void* ytab, const BinSpec& bs, double kf,
                               double* partial, int* nblocks_out, const void* tw, int axis, const Frame& frame,
                               hipStream_t s) {
-  if (nslots < 0 || (fs.fpad && axis != 0)) return hipErrorInvalidValue;
+  if (nslots < 0) return hipErrorInvalidValue;
   const int rows = (with_l0 ? 3 : 0) + nslots;
   const size_t sm = xpost_base_bytes(fs, sizeof(T) == 8) + sizeof(double) * (size_t)bs.hist_copies * rows * bs.nb +
                     sizeof(long long) * (size_t)(bs.nb + 1);

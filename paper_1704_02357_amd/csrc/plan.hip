@@ -902,10 +902,12 @@ template <typename T> void read_dc(pkm_plan* pl, void* host, size_t bytes) {
 }
 
 // Launch shape of the transform passes for one mesh size and precision.
-// Field buffers of a post-pass along x get x planes of n n/2 + 32 elements: with the plain
-// power-of-two plane stride the post-pass's column reads (one row piece per plane) fall on
-// few HBM channels.  Measured at 512^3: 32 and 16 best, 64 close, 128 and 256 slower than none.
-int field_pad(int post_axis) { return post_axis == 0 ? 32 : 0; }
+// Field buffers get x planes of n n/2 complex values plus 256 bytes (32 FP32 or 16 FP64
+// values): with the plain power-of-two plane stride, the passes that step from plane to
+// plane (the FP32 post-pass, the FP64 column pass) fall on few HBM channels.  Measured at
+// 512^3: 256 bytes best in both precisions; 512 bytes close in FP32 and slower in FP64;
+// 1 and 2 KB slower than none in FP32.
+int field_pad(bool fp64) { return fp64 ? 16 : 32; }
 
 bool make_shape(const pkm_params& p, FftShape* out) {
   FftShape fs{};
@@ -951,7 +953,7 @@ bool make_shape(const pkm_params& p, FftShape* out) {
   fs.zlines = zl;
   // FP64 fields finish along y (rows nh apart): measured faster; FP32 along x
   fs.post_axis = fp64 ? 1 : 0;
-  fs.fpad = field_pad(fs.post_axis);
+  fs.fpad = field_pad(fp64);
   *out = fs;
   return true;
 }
@@ -991,7 +993,6 @@ bool apply_shape(const pkm_params& p, const pkm_shape& sh, FftShape* fs, int* ts
     if (sh.post_axis != 1 && sh.post_axis != 2) return fail("post_axis must be 1 (x) or 2 (y)");
     f.post_axis = sh.post_axis - 1;
   }
-  f.fpad = field_pad(f.post_axis);
   if (sh.paint_tile) {
     if ((sh.paint_tile != 4 && sh.paint_tile != 8 && sh.paint_tile != 16) || n % sh.paint_tile)
       return fail("paint_tile must be 4, 8 or 16 and divide nmesh");
