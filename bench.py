@@ -117,7 +117,9 @@ def summarize_profile(directory: str) -> None:
 def run_form(precision: int, data, rand, edges, steps: int, warmup: int):
     """One estimate per step through the asynchronous calls: pkm_prepare once, then per step
     pkm_enqueue (paint, every transform, all (l, m) fields, binning; no host wait inside) and
-    pkm_finish (wait, normalise).  Per-launch HIP events on the plan's stream time each stage."""
+    pkm_finish (wait, normalise).  The headline loop runs with per-launch timing off; a second
+    loop of the same steps records HIP events on the plan's stream around every launch and
+    gives the per-stage device times (and its own wall time, to show the events' overhead)."""
     import torch
     from paper_1704_02357_amd import Plan
     plan = Plan(NMESH, BOX, observer=OBSERVER, window=3, interlaced=True, compensated=True, precision=precision,
@@ -126,8 +128,7 @@ def run_form(precision: int, data, rand, edges, steps: int, warmup: int):
     for _ in range(warmup):
         plan.enqueue(data, rand)
         res = plan.finish()
-    plan.reset_stats()
-    plan.set_stage_timing(True)
+    plan.set_stage_timing(False)
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -138,9 +139,60 @@ def run_form(precision: int, data, rand, edges, steps: int, warmup: int):
         lat.append(time.perf_counter() - s0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # stage pass: the same steps with per-launch events
+    plan.reset_stats()
+    plan.set_stage_timing(True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(steps):
+        plan.enqueue(data, rand)
+        plan.finish()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
     st = plan.stats()
     plan.close()
-    return res, (t1 - t0), np.array(lat), st
+    return res, (t1 - t0), np.array(lat), st, (t3 - t2)
+
+
+def golden_poles(info, data, rand):
+    """The FP64 oracle's P_l(k) for this workload from tests/golden/workload_512_l4_poles.txt
+    (written by tests/golden/make_workload_golden.py from the oracle only), after checking that
+    the catalog digest and sizes match the inputs of this run; None otherwise."""
+    from synth import catalog_digest
+    path = os.path.join(HERE, "tests", "golden", "workload_512_l4_poles.txt")
+    if not os.path.exists(path):
+        return None
+    head, rows = {}, []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("# catalog:"):
+                toks = line.split()
+                head["n_data"] = int(toks[toks.index("n_data") + 1].rstrip(","))
+                head["n_rand"] = int(toks[toks.index("n_rand") + 1].rstrip(","))
+                head["digest"] = toks[toks.index("digest") + 1]
+            elif line.startswith("# shot_noise"):
+                head["shot_noise"] = float(line.split()[-1])
+            elif not line.startswith("#") and line.strip():
+                rows.append([float(v) for v in line.split()])
+    if head.get("n_data") != info["n_data"] or head.get("n_rand") != info["n_rand"]:
+        return None
+    if head.get("digest") != catalog_digest(data, rand):
+        return None
+    a = np.array(rows)
+    return {"poles": a[:, 4:7].T.copy(), "n_modes": a[:, 2].astype(np.int64), "shot_noise": head["shot_noise"],
+            "edges": np.concatenate([a[:, 0], a[-1:, 1]])}
+
+
+def err_vs_oracle(res, ref) -> dict:
+    """Largest per-bin error of a result against the oracle: scaled by max(|P_l|, P_0 + S)
+    (the parity tests' pass rule) and plain relative."""
+    po, pg = ref["poles"], np.asarray(res["poles"])
+    raw0 = po[0] + ref["shot_noise"]
+    scale = np.maximum(np.abs(po), np.abs(raw0)[None, :])
+    ok = np.isfinite(po)
+    rel = np.abs(pg - po)[ok] / np.abs(po)[ok]
+    return {"max_scaled": float(np.max(np.abs(pg - po)[ok] / scale[ok])), "max_plain_rel": float(np.max(rel)),
+            "n_modes_equal": bool(np.array_equal(np.asarray(res["n_modes"]), ref["n_modes"]))}
 
 
 def catalog_upload(data, rand, dst) -> dict:
@@ -604,14 +656,24 @@ def main():
     grand = (dev(rand.pos), dev(rand.w), dev(rand.nbar))
     torch.cuda.synchronize()
     upload = catalog_upload(data, rand, gdata + grand)
-    res32, sec32, lat32, st32 = run_form(0, gdata, grand, edges, args.steps, args.warmup)
-    log(f"[bench] fp32: {args.steps / sec32:.2f} est/s, {1e3 * sec32 / args.steps:.3f} ms/step")
+    res32, sec32, lat32, st32, staged32 = run_form(0, gdata, grand, edges, args.steps, args.warmup)
+    log(f"[bench] fp32: {args.steps / sec32:.2f} est/s, {1e3 * sec32 / args.steps:.3f} ms/step "
+        f"({1e3 * staged32 / args.steps:.3f} ms/step with per-launch events)")
     k64 = args.fp64_steps or max(2, args.steps // 2)
     if args.fp32_only:
-        res64, sec64, lat64, st64 = res32, float("nan"), np.full(1, np.nan), None
+        res64, sec64, lat64, st64, staged64 = res32, float("nan"), np.full(1, np.nan), None, float("nan")
     else:
-        res64, sec64, lat64, st64 = run_form(1, gdata, grand, edges, k64, max(1, args.warmup // 2))
+        res64, sec64, lat64, st64, staged64 = run_form(1, gdata, grand, edges, k64, max(1, args.warmup // 2))
         log(f"[bench] fp64: {k64 / sec64:.2f} est/s")
+    ref = golden_poles(info, data, rand) if np.array_equal(edges, np.arange(len(edges)) * 0.01) else None
+    vs_oracle = None
+    if ref is not None and np.allclose(ref["edges"], edges, rtol=0, atol=1e-12):
+        vs_oracle = {"source": "tests/golden/workload_512_l4_poles.txt (FP64 oracle, catalog digest checked)",
+                     "tolerance_scaled": {"fp32": 1e-5, "fp64": 1e-12},
+                     "fp32": err_vs_oracle(res32, ref)}
+        if not args.fp32_only:
+            vs_oracle["fp64"] = err_vs_oracle(res64, ref)
+        log(f"[bench] vs oracle: {vs_oracle}")
     # FP32 form against the FP64 form (same inputs): the per-bin rule of the parity tests
     raw0 = res64["poles"][0] + res64["shot_noise"]
     scale = np.maximum(np.abs(res64["poles"]), np.abs(raw0)[None, :])
@@ -653,6 +715,8 @@ def main():
                    "n_data": info["n_data"], "n_rand": info["n_rand"]},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat32, 50)), 3),
                        "p99": round(1e3 * float(np.percentile(lat32, 99)), 3)},
+        "ms_per_step_with_stage_events": round(1e3 * staged32 / args.steps, 4),
+        "err_vs_oracle": vs_oracle,
         "fp64": {"value": round(k64 / sec64, 3), "ms_per_step": round(1e3 * sec64 / k64, 4),
                  "stage_ms_per_step": ({k: round(v / k64, 3) for k, v in st64["stage_ms"].items() if v > 0}
                                        if not args.fp32_only else None),

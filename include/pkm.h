@@ -95,7 +95,11 @@ typedef struct {
 
 /* A catalog: n objects, positions pos[3*i + a] (FP64, absolute coordinates), optional
  * weights w[i] (NULL -> 1) and number densities nbar[i] (required for randoms).
- * on_device = 1: the three pointers are device pointers on the plan's device.            */
+ * on_device = 1: the three pointers are device pointers on the plan's device.
+ * One estimate takes at most PKM_MAX_PARTICLES data + random objects (2^31 - 2^16): the
+ * painting sort keeps per-tile counts, offsets and ranks in 32-bit integers.  Larger
+ * catalogs are rejected with PKM_EINVAL before anything is allocated or copied.            */
+#define PKM_MAX_PARTICLES ((int64_t)2147418112)
 typedef struct {
   const double* pos;
   const double* w;
@@ -176,6 +180,13 @@ typedef struct {
 
 int pkm_abi_version(void);
 const char* pkm_status_str(pkm_status s);
+
+/* Host-only check of a data / randoms pair as pkm_paint, pkm_enqueue and pkm_batch_add take
+ * it (Sec. 2.1 eq. FKP-density: data non-empty; randoms NULL for a periodic box, else
+ * non-empty with n-bar; n >= 0; positions present; at most PKM_MAX_PARTICLES objects in
+ * all).  Reads only the structs, never the arrays; no device access.  PKM_OK or
+ * PKM_EINVAL.                                                                               */
+pkm_status pkm_check_catalogs(const pkm_catalog* data, const pkm_catalog* randoms);
 
 /* Validate the parameters, build twiddle / harmonic / compensation tables and allocate the
  * plan's device buffers.  *out is set only on success.                                     */
@@ -322,7 +333,9 @@ pkm_status pkm_finish(pkm_plan* plan, pkm_result* out);
  * later runs replay it with one launch; adding an item drops the graph.  The catalogs'
  * device pointers and counts are recorded: their contents may change between runs, their
  * addresses and sizes may not.  Plans in a batch must not be re-prepared or used directly
- * while the batch holds them.
+ * while the batch holds them: a run checks every item's plan first and, if the plan's
+ * buffers or request tables changed since the item was added, drops the graph, issues
+ * nothing and returns PKM_EORDER (add the items again).
  *   pkm_batch_run    issues (or replays) every item, waits, and reports the device time
  *                    from the fork to the join in *ms_out (may be NULL).
  *   pkm_batch_result normalises item `index` of the last run into `out` (FP64, host);

@@ -18,6 +18,8 @@ bool prepared(const pkm_plan* pl);
 hipStream_t stream_of(const pkm_plan* pl);
 int device_of(const pkm_plan* pl);
 int64_t device_bytes(const pkm_plan* pl);
+// Changes whenever the plan's device buffers or request tables change.
+uint64_t generation(const pkm_plan* pl);
 std::string& error_of(pkm_plan* pl);
 // One whole estimate of device catalogs, results to a pinned host slot; no allocation, no
 // host wait (capturable).

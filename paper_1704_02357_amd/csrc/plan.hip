@@ -108,6 +108,9 @@ struct pkm_plan {
   pkm_stats_t stats{};
   int64_t bytes = 0;
   std::unordered_map<void*, size_t> sizes;
+  // bumped whenever a device buffer is allocated or freed or the request tables are rebuilt:
+  // an issued or captured batch item is only valid for the generation it was added at
+  uint64_t gen = 1;
   // per-launch stage timing
   bool stage_timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -223,6 +226,7 @@ void* dalloc(pkm_plan* pl, size_t bytes) {
   }
   pl->bytes += (int64_t)bytes;
   pl->sizes[ptr] = bytes;
+  ++pl->gen;
   return ptr;
 }
 
@@ -233,6 +237,7 @@ void dfree(pkm_plan* pl, void* ptr) {
     pl->bytes -= (int64_t)it->second;
     pl->sizes.erase(it);
   }
+  ++pl->gen;
   if (pl->dev.free) pl->dev.free(ptr, pl->dev.hip_stream, pl->dev.alloc_ctx);
   else (void)hipFree(ptr);
 }
@@ -562,6 +567,7 @@ void prepare_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edg
       std::equal(cc.edges.begin(), cc.edges.end(), k_edges))
     return;
   cc = ComputeCfg{};
+  ++pl->gen;
   const int n = pl->p.nmesh;
   const int nb = n_edges - 1;
   {
@@ -824,6 +830,10 @@ pkm_status finish_from_slot(const pkm_plan* pl, const double* slot, int64_t nd, 
   return PKM_OK;
 }
 
+// (k, mu) cells of one request: (n_k_edges - 1) (n_mu_edges - 1) <= this, the limit of the
+// binning kernel's LDS histogram (two doubles per cell in 48 KB)
+constexpr int KMU_MAX_CELLS = 3072;
+
 template <typename T>
 void run_kmu(pkm_plan* pl, const double* k_edges, int nke, const double* mu_edges, int nme, double* pk, int64_t* nm) {
   hipStream_t s = pl->stream;
@@ -1040,6 +1050,7 @@ pkm_status validate_params(const pkm_params* p, std::string* why) {
 pkm_status validate_catalog(const pkm_catalog* c, bool need_nbar, std::string* why) {
   if (!c) { *why = "catalog is NULL"; return PKM_EINVAL; }
   if (c->n < 0) { *why = "catalog size must be >= 0"; return PKM_EINVAL; }
+  if (c->n > PKM_MAX_PARTICLES) { *why = "catalog larger than PKM_MAX_PARTICLES"; return PKM_EINVAL; }
   if (c->n > 0 && !c->pos) { *why = "catalog positions are NULL"; return PKM_EINVAL; }
   if (need_nbar && c->n > 0 && !c->nbar) { *why = "randoms need nbar"; return PKM_EINVAL; }
   return PKM_OK;
@@ -1086,14 +1097,26 @@ pkm_status validate_request(pkm_plan* pl, int ell_max, const double* k_edges, in
   return PKM_OK;
 }
 
+// Host-only checks of a data/randoms pair (no device access).
+pkm_status check_pair(const pkm_catalog* data, const pkm_catalog* randoms, std::string* why) {
+  if (validate_catalog(data, false, why) != PKM_OK || (randoms && validate_catalog(randoms, true, why) != PKM_OK))
+    return PKM_EINVAL;
+  if (data->n == 0) { *why = "data catalog is empty"; return PKM_EINVAL; }
+  if (randoms && randoms->n == 0) { *why = "random catalog is empty (pass NULL for a periodic box)"; return PKM_EINVAL; }
+  // the painting sort keeps per-tile counts and offsets in 32-bit integers
+  if (data->n + (randoms ? randoms->n : 0) > PKM_MAX_PARTICLES) {
+    *why = "data + random objects above PKM_MAX_PARTICLES";
+    return PKM_EINVAL;
+  }
+  return PKM_OK;
+}
+
 pkm_status validate_pair(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* randoms) {
   std::string why;
-  if (validate_catalog(data, false, &why) != PKM_OK || (randoms && validate_catalog(randoms, true, &why) != PKM_OK)) {
+  if (check_pair(data, randoms, &why) != PKM_OK) {
     pl->err = why;
     return PKM_EINVAL;
   }
-  if (data->n == 0) { pl->err = "data catalog is empty"; return PKM_EINVAL; }
-  if (randoms && randoms->n == 0) { pl->err = "random catalog is empty (pass NULL for a periodic box)"; return PKM_EINVAL; }
   return PKM_OK;
 }
 
@@ -1104,7 +1127,10 @@ namespace pkm_internal {
 
 pkm_status prepare(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, int64_t max_particles) {
   if (validate_request(pl, ell_max, k_edges, n_edges) != PKM_OK) return PKM_EINVAL;
-  if (max_particles < 1) { pl->err = "max_particles must be positive"; return PKM_EINVAL; }
+  if (max_particles < 1 || max_particles > PKM_MAX_PARTICLES) {
+    pl->err = "max_particles must be in 1..PKM_MAX_PARTICLES";
+    return PKM_EINVAL;
+  }
   if (pl->pending_async) { pl->err = "an enqueued estimate has not been finished"; return PKM_EBUSY; }
   return guarded(pl, [&] {
     check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
@@ -1137,6 +1163,7 @@ bool prepared(const pkm_plan* pl) {
 hipStream_t stream_of(const pkm_plan* pl) { return pl->stream; }
 int device_of(const pkm_plan* pl) { return pl->dev.device_id; }
 int64_t device_bytes(const pkm_plan* pl) { return pl->bytes; }
+uint64_t generation(const pkm_plan* pl) { return pl->gen; }
 std::string& error_of(pkm_plan* pl) { return pl->err; }
 
 // Enqueue one estimate of device catalogs with its results copied to `slot` (pinned host,
@@ -1200,6 +1227,11 @@ int64_t footprint(const pkm_params* p, int ell_max, int n_edges, int64_t n_parti
 extern "C" {
 
 int pkm_abi_version(void) { return PKM_ABI_VERSION; }
+
+pkm_status pkm_check_catalogs(const pkm_catalog* data, const pkm_catalog* randoms) {
+  std::string why;
+  return check_pair(data, randoms, &why);
+}
 
 const char* pkm_status_str(pkm_status s) {
   switch (s) {
@@ -1289,19 +1321,7 @@ pkm_status pkm_plan_create_shaped(const pkm_params* p, const pkm_device* dev, co
 
 pkm_status pkm_paint(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* randoms) {
   if (!pl) return PKM_EINVAL;
-  std::string why;
-  if (validate_catalog(data, false, &why) != PKM_OK || (randoms && validate_catalog(randoms, true, &why) != PKM_OK)) {
-    pl->err = why;
-    return PKM_EINVAL;
-  }
-  if (data->n == 0) {
-    pl->err = "data catalog is empty";
-    return PKM_EINVAL;
-  }
-  if (randoms && randoms->n == 0) {
-    pl->err = "random catalog is empty (pass NULL for a periodic box)";
-    return PKM_EINVAL;
-  }
+  if (validate_pair(pl, data, randoms) != PKM_OK) return PKM_EINVAL;
   if (pl->pending_async) { pl->err = "an enqueued estimate has not been finished"; return PKM_EBUSY; }
   pl->painted = false;
   pkm_status st = guarded(pl, [&] {
@@ -1337,9 +1357,9 @@ pkm_status pkm_compute_multipoles(pkm_plan* pl, int32_t ell_max, const double* k
   return pkm_compute_multipoles_basis(pl, ell_max, k_edges, n_edges, PKM_BASIS_SPHERICAL, out);
 }
 
-pkm_status pkm_kmu_global(pkm_plan* pl, const double* k_edges, int32_t n_k_edges, const double* mu_edges,
-                          int32_t n_mu_edges, double* pkmu_out, int64_t* nmodes_out) {
-  if (!pl) return PKM_EINVAL;
+// Arguments of the (k, mu) calls; PKM_OK when the request can run.
+pkm_status validate_kmu(pkm_plan* pl, const double* k_edges, int32_t n_k_edges, const double* mu_edges,
+                        int32_t n_mu_edges) {
   if (!k_edges || !mu_edges || n_k_edges < 2 || n_mu_edges < 2) { pl->err = "need k and mu edges"; return PKM_EINVAL; }
   for (int i = 0; i < n_k_edges; ++i)
     if (!(k_edges[i] >= 0) || (i > 0 && !(k_edges[i] > k_edges[i - 1]))) { pl->err = "bad k edges"; return PKM_EINVAL; }
@@ -1348,12 +1368,21 @@ pkm_status pkm_kmu_global(pkm_plan* pl, const double* k_edges, int32_t n_k_edges
       pl->err = "mu edges must increase within [0, 1]";
       return PKM_EINVAL;
     }
-  if ((size_t)2 * (n_k_edges - 1) * (n_mu_edges - 1) * sizeof(double) > 48 * 1024) {
+  if ((int64_t)(n_k_edges - 1) * (n_mu_edges - 1) > KMU_MAX_CELLS) {
     pl->err = "too many (k, mu) cells for one pass (limit 3072)";
     return PKM_EINVAL;
   }
   if (pl->p.los_mode != PKM_LOS_GLOBAL) { pl->err = "plan was not created with los_mode = GLOBAL"; return PKM_EINVAL; }
+  if (pl->pending_async) { pl->err = "an enqueued estimate has not been finished"; return PKM_EBUSY; }
   if (!pl->painted) { pl->err = "pkm_paint must succeed first"; return PKM_EORDER; }
+  return PKM_OK;
+}
+
+pkm_status pkm_kmu_global(pkm_plan* pl, const double* k_edges, int32_t n_k_edges, const double* mu_edges,
+                          int32_t n_mu_edges, double* pkmu_out, int64_t* nmodes_out) {
+  if (!pl) return PKM_EINVAL;
+  const pkm_status v = validate_kmu(pl, k_edges, n_k_edges, mu_edges, n_mu_edges);
+  if (v != PKM_OK) return v;
   return guarded(pl, [&] {
     check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
     if (pl->fp64) run_kmu<double>(pl, k_edges, n_k_edges, mu_edges, n_mu_edges, pkmu_out, nmodes_out);

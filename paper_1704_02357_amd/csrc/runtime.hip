@@ -63,6 +63,7 @@ struct BatchItem {
   pkm_plan* plan = nullptr;
   pkm_catalog data{}, rand{};
   bool has_rand = false;
+  uint64_t gen = 0;  // the plan's generation when the item was added
   std::unique_ptr<PinnedBuf> slot;
 };
 
@@ -166,8 +167,13 @@ pkm_status pkm_batch_add(pkm_batch* b, pkm_plan* plan, const pkm_catalog* data, 
     b->err = "batched estimates take device-resident catalogs";
     return PKM_EINVAL;
   }
+  if (pkm_check_catalogs(data, randoms) != PKM_OK) {
+    b->err = "invalid catalogs (empty, missing arrays or n-bar, or above PKM_MAX_PARTICLES)";
+    return PKM_EINVAL;
+  }
   BatchItem it;
   it.plan = plan;
+  it.gen = pkm_internal::generation(plan);
   it.data = *data;
   if (randoms) { it.rand = *randoms; it.has_rand = true; }
   it.slot.reset(new (std::nothrow) PinnedBuf());
@@ -185,6 +191,18 @@ pkm_status pkm_batch_add(pkm_batch* b, pkm_plan* plan, const pkm_catalog* data, 
 pkm_status pkm_batch_run(pkm_batch* b, int32_t use_graph, double* ms_out) {
   if (!b) return PKM_EINVAL;
   if (b->items.empty()) { b->err = "empty batch"; return PKM_EINVAL; }
+  // an item whose plan was re-prepared or reallocated since it was added would run kernels
+  // (recorded or issued) on freed buffers or overrun its result slot: refuse before issuing
+  for (size_t i = 0; i < b->items.size(); ++i) {
+    const BatchItem& it = b->items[i];
+    if (pkm_internal::generation(it.plan) != it.gen || !pkm_internal::prepared(it.plan) ||
+        it.slot->n < pkm_internal::slot_doubles(it.plan)) {
+      drop_graph(b);
+      b->ran = false;
+      b->err = "item " + std::to_string(i) + ": its plan changed after pkm_batch_add (add the items again)";
+      return PKM_EORDER;
+    }
+  }
   hipError_t e = hipSetDevice(b->device);
   if (e != hipSuccess) return hip_fail(b, e, "hipSetDevice");
   b->ran = false;
@@ -626,6 +644,10 @@ pkm_status pkm_server_submit(pkm_server* sv, const pkm_request* rq, int64_t* tic
   }
   if (!rq->k_edges || rq->n_edges < 2 || rq->ell_max < 0 || rq->ell_max > 16 || rq->ell_max % 2) {
     sv->err = "need even ell_max in 0..16 and at least two k edges";
+    return PKM_EINVAL;
+  }
+  if (rq->data.n + (rq->has_randoms ? rq->randoms.n : 0) > PKM_MAX_PARTICLES) {
+    sv->err = "data + random objects above PKM_MAX_PARTICLES";
     return PKM_EINVAL;
   }
   auto r = std::make_shared<Request>();

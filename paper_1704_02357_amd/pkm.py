@@ -13,6 +13,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ABI_VERSION = 3
+MAX_PARTICLES = 2 ** 31 - 2 ** 16   # PKM_MAX_PARTICLES: data + random objects per estimate
 NGP, CIC, TSC = 1, 2, 3
 FP32, FP64 = 0, 1
 SPHERICAL, CARTESIAN = 0, 1   # decompositions of L_l(khat . xhat) (Sec. 2.1)
@@ -111,6 +112,7 @@ def load_library():
     sig = {
         "pkm_abi_version": (C.c_int, []),
         "pkm_status_str": (C.c_char_p, [C.c_int]),
+        "pkm_check_catalogs": (C.c_int, [C.POINTER(Catalog), C.POINTER(Catalog)]),
         "pkm_plan_create": (C.c_int, [C.POINTER(Params), C.POINTER(Device), C.POINTER(P)]),
         "pkm_paint": (C.c_int, [P, C.POINTER(Catalog), C.POINTER(Catalog)]),
         "pkm_compute_multipoles": (C.c_int, [P, C.c_int32, P, C.c_int32, C.POINTER(Result)]),

@@ -89,3 +89,32 @@ def test_summarize_profile_reads_stats_and_counters(tmp_path, capsys):
     zf = [l for l in out if l.startswith("k_zfwd<float, 8, 512, 8>")]
     # counter rows of one dispatch (one per XCD or shader engine) add up; the mean is per dispatch
     assert len(zf) == 1 and zf[0].split()[-3:] == ["FETCH_SIZE", "2", "150"]
+
+
+def test_err_vs_oracle_and_golden_guard(tmp_path, monkeypatch):
+    """The bench line's error against the stored FP64 oracle: the scaled per-bin rule of the
+    parity tests, and no comparison at all when the stored catalog does not match the run."""
+    import numpy as np
+    from synth import Catalog
+    po = np.array([[10.0, 20.0, 30.0], [1.0, -2.0, 0.5], [0.1, 0.2, -0.3]])
+    ref = {"poles": po, "n_modes": np.array([4, 8, 12]), "shot_noise": 5.0}
+    res = {"poles": po + np.array([[1e-4, 0, 0], [0, 3e-4, 0], [0, 0, 0]]), "n_modes": np.array([4, 8, 12])}
+    e = bench.err_vs_oracle(res, ref)
+    # l=0 bin 0: 1e-4 / max(10, 15); l=2 bin 1: 3e-4 / max(2, 25)
+    assert abs(e["max_scaled"] - 3e-4 / 25.0) < 1e-15 and e["n_modes_equal"]
+    assert abs(e["max_plain_rel"] - 1.5e-4) < 1e-12
+    # a stored file for other inputs is ignored
+    monkeypatch.setattr(bench, "HERE", str(tmp_path))
+    (tmp_path / "tests" / "golden").mkdir(parents=True)
+    cat = Catalog(np.zeros((2, 3)), np.ones(2), np.ones(2))
+    (tmp_path / "tests" / "golden" / "workload_512_l4_poles.txt").write_text(
+        "# catalog: synth.config_c2(), n_data 2, n_rand 2, digest ffffffffffffffff\n# shot_noise 1.0\n"
+        "0.0 0.01 4 0.005 1.0 2.0 3.0\n")
+    assert bench.golden_poles({"n_data": 2, "n_rand": 2}, cat, cat) is None
+    assert bench.golden_poles({"n_data": 3, "n_rand": 2}, cat, cat) is None
+    from synth import catalog_digest
+    (tmp_path / "tests" / "golden" / "workload_512_l4_poles.txt").write_text(
+        f"# catalog: synth.config_c2(), n_data 2, n_rand 2, digest {catalog_digest(cat, cat)}\n# shot_noise 1.0\n"
+        "0.0 0.01 4 0.005 1.0 2.0 3.0\n")
+    g = bench.golden_poles({"n_data": 2, "n_rand": 2}, cat, cat)
+    assert g is not None and g["poles"].shape == (3, 1) and g["n_modes"][0] == 4

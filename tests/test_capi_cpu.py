@@ -117,3 +117,24 @@ def test_shape_validation_rejects_before_device():
         h = C.c_void_p()
         st = lib.pkm_plan_create_shaped(C.byref(p), C.byref(d), C.byref(sh), C.byref(h))
         assert st == 1, (b, st)
+
+
+def test_particle_limit_rejected_on_host():
+    """More than PKM_MAX_PARTICLES data + random objects (the painting sort's 32-bit counts
+    and offsets) is refused on the host before any array is read."""
+    lib = _lib()
+    from paper_1704_02357_amd.pkm import Catalog, MAX_PARTICLES
+    hdr = open(HEADER).read()
+    assert f"#define PKM_MAX_PARTICLES ((int64_t){MAX_PARTICLES})" in hdr
+    fake = C.c_void_p(0x1000)  # never dereferenced: the check reads only the structs
+    def cat(n, on_dev=1):
+        return Catalog(fake, None, fake, n, on_dev)
+    ok_d, ok_r = cat(1000), cat(20000)
+    assert lib.pkm_check_catalogs(C.byref(ok_d), C.byref(ok_r)) == 0
+    assert lib.pkm_check_catalogs(C.byref(ok_d), None) == 0
+    for d, r in ((cat(MAX_PARTICLES - 10), cat(11)), (cat(MAX_PARTICLES + 1), None), (cat(2 ** 31), cat(5)),
+                 (cat(0), ok_r), (ok_d, cat(0)), (cat(-1), None)):
+        assert lib.pkm_check_catalogs(C.byref(d), None if r is None else C.byref(r)) == 1
+    assert lib.pkm_check_catalogs(C.byref(cat(MAX_PARTICLES - 10)), C.byref(cat(10))) == 0
+    nonbar = Catalog(fake, None, None, 10, 1)
+    assert lib.pkm_check_catalogs(C.byref(ok_d), C.byref(nonbar)) == 1

@@ -321,3 +321,56 @@ def test_autotune_picks_valid_shape_and_caches(gpu, tmp_path):
     _same(p.compute_multipoles(4, _edges(64)), _alone(64, 0, 4, d, r), 0, "tuned shape")
     p.close()
     assert autotune(64, L, ell_max=4, n_particles=60000, reps=1, cache=cache, **kw) == t
+
+
+def test_batch_refuses_changed_plan(gpu):
+    """A plan re-prepared after pkm_batch_add (larger ell_max: larger result slot, new
+    tables and field buffers) makes the next run return PKM_EORDER before anything is
+    issued, with or without a captured graph; items added again run and match alone."""
+    import torch
+    from paper_1704_02357_amd import Batch, PkmError
+    n, prec = 32, 0
+    d, r = small_catalogs(1500, 9000, L, seed=55)
+    dd, rr = _dev(d), _dev(r)
+    ref = _alone(n, prec, 4, d, r)
+    for use_graph in (False, True):
+        p = _plan(n, prec, 4, stream=torch.cuda.Stream())
+        p.prepare(4, _edges(n), 20000)
+        b = Batch()
+        b.add(p, dd, rr)
+        b.run(use_graph=use_graph)
+        _same(b.result(0), ref, prec, f"before re-prepare graph={use_graph}")
+        p.prepare(8, _edges(n), 20000)
+        print(f"[case] batch after re-prepare graph={use_graph}", flush=True)
+        with pytest.raises(PkmError) as e:
+            b.run(use_graph=use_graph)
+        assert e.value.status == 2 and "changed" in str(e.value)
+        with pytest.raises(PkmError) as e:   # nothing ran: no result to read
+            b.result(0)
+        assert e.value.status == 2
+        b.close()
+        p.prepare(4, _edges(n), 20000)
+        b = Batch()
+        b.add(p, dd, rr)
+        b.run(use_graph=use_graph)
+        _same(b.result(0), ref, prec, f"items added again graph={use_graph}")
+        b.close()
+        p.close()
+
+
+def test_particle_limit_rejected_before_device_work(gpu):
+    """Catalog counts above PKM_MAX_PARTICLES are refused by paint, prepare and submit with
+    PKM_EINVAL, before any array is read (the pointers here are never dereferenced)."""
+    import ctypes as C
+    from paper_1704_02357_amd import PkmError, Server
+    from paper_1704_02357_amd.pkm import Catalog, MAX_PARTICLES
+    p = _plan(32, 0, 4)
+    fake = C.c_void_p(0x1000)
+    big = Catalog(fake, None, fake, MAX_PARTICLES, 1)
+    small = Catalog(fake, None, fake, 10, 1)
+    assert p.lib.pkm_paint(p.h, C.byref(small), C.byref(big)) == 1
+    assert "PKM_MAX_PARTICLES" in p.lib.pkm_plan_last_error(p.h).decode()
+    with pytest.raises(PkmError) as e:
+        p.prepare(4, _edges(32), MAX_PARTICLES + 1)
+    assert e.value.status == 1
+    p.close()
