@@ -240,6 +240,24 @@ pkm_status pkm_compute_multipoles(pkm_plan* plan, int32_t ell_max, const double*
 pkm_status pkm_compute_multipoles_basis(pkm_plan* plan, int32_t ell_max, const double* k_edges, int32_t n_edges,
                                         int32_t basis, pkm_result* out);
 
+/* Every multipole l = 0 .. ell_max (ell_max 0..16), odd l included, through the spherical-
+ * harmonic decomposition of eq. Fell: 2l+1 transforms per l > 0, (ell_max+1)^2 - 1 in all.
+ * The paper treats even l only (odd ones vanish under a single line of sight, Sec. 1); with
+ * the local line of sight of eq. Pell-ours the odd shell averages do not vanish but are purely
+ * imaginary: a mode and its mirror contribute with L_l(-x) = -L_l(x), and their real parts
+ * cancel.  out->poles has (ell_max + 1) x (n_edges - 1) doubles, row l:
+ *   even l: P_l as pkm_compute_multipoles (shot noise subtracted at l = 0);
+ *   odd l:  R_l = Im P_l of eq. Pell-ours with the paper's exponent exp(+i k.r) in eq. Fell,
+ *           i.e. (2l+1)/(I N_i) sum_bin Im[C conj A_l] with the forward transforms exp(-i k.x)
+ *           used here; no shot-noise term.  (Eq. Pell-yama, whose second integral is
+ *           conj F_l(k) rather than F_l(-k), equals eq. Pell-ours for even l and is -i R_l for
+ *           odd l.)
+ * k_mean, n_modes, the scalars and errors as pkm_compute_multipoles; out->n_transforms counts
+ * the odd fields too.  Synchronous only (the asynchronous, batch and serving paths take even
+ * l).                                                                                       */
+pkm_status pkm_compute_multipoles_all(pkm_plan* plan, int32_t ell_max, const double* k_edges, int32_t n_edges,
+                                      pkm_result* out);
+
 /* Fixed line of sight (the plan's `los`): P(k_i, mu_j) = sum |C|^2 / (I N_ij) - S over the
  * modes with mu = |khat . los| in [mu_j, mu_{j+1}) (mu = 1 in the last bin).  Outputs are
  * (n_k_edges-1) x (n_mu_edges-1), row-major by k; either may be NULL.                      */

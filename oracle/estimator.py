@@ -15,6 +15,14 @@ Definition followed, step by step (conventions in ``oracle/__init__.py``):
 6. P_l(k_i) = (2l+1)/(I N_i) sum_{n in bin i} Re[C(n) conj(A_l(n))] - delta_{l0} S, over the
    full grid (each mode once), bin i = {T_i <= |n|^2 < T_{i+1}}, T_i = ceil((e_i L/2pi)^2),
    n = 0 and Nyquist-plane modes excluded; k_mean_i = mean of (2 pi/L)|n| over the bin.
+7. Odd l (asked for through ``ells``): the shell average of eq. Pell-ours is purely
+   imaginary, because a mode and its mirror -n contribute with L_l(-x) = -L_l(x) and their
+   real parts cancel.  The oracle returns the real number
+   R_l(k_i) = (2l+1)/(I N_i) sum_{n in bin i} Im[C(n) conj(A_l(n))], no shot-noise term.
+   With the exponent exp(-i k.x) used here for C and A_l and the paper's exp(+i k.r) in
+   eq. Fell, the complex multipole of eq. Pell-ours is i R_l, so R_l = Im P_l.  (Eq. Pell-yama,
+   whose second integral is the complex conjugate of F_l(k) rather than F_l(-k), agrees with
+   eq. Pell-ours for even l and has the opposite sign for odd l.)
 """
 from __future__ import annotations
 
@@ -104,10 +112,17 @@ def field_multipole(c: np.ndarray, dc: np.ndarray, ell: int, params, xvec=None, 
     return a * (4.0 * math.pi / (2 * ell + 1))
 
 
+def pole_term(ell: int, c: np.ndarray, a: np.ndarray) -> np.ndarray:
+    """(2l+1) Re[C conj A_l] for even l, (2l+1) Im[C conj A_l] for odd l (steps 6 and 7)."""
+    z = c * np.conj(a)
+    return (2 * ell + 1) * (np.imag(z) if ell % 2 else np.real(z))
+
+
 def multipoles(data, randoms, params, ell_max: int, k_edges, workers: int = 1, ells=None):
-    """P_l(k) for even l <= ell_max.  Returns dict with poles (n_ell, n_k), k_mean, n_modes,
-    alpha, norm_I, shot_noise and n_transforms."""
-    if ell_max % 2 or ell_max < 0:
+    """P_l(k) for even l <= ell_max (or the listed ``ells``, odd ones giving R_l of step 7).
+    Returns dict with poles (n_ell, n_k), k_mean, n_modes, alpha, norm_I, shot_noise and
+    n_transforms."""
+    if ells is None and (ell_max % 2 or ell_max < 0):
         raise ValueError("ell_max must be even and >= 0")
     n = params["nmesh"]
     L = params["box_len"]
@@ -129,7 +144,7 @@ def multipoles(data, randoms, params, ell_max: int, k_edges, workers: int = 1, e
     poles = np.empty((len(ells), nb))
     for i, ell in enumerate(ells):
         a = field_multipole(c, dc, ell, params, xvec, kvec, workers)
-        q = (2 * ell + 1) * np.real(c * np.conj(a))
+        q = pole_term(ell, c, a)
         with np.errstate(invalid="ignore", divide="ignore"):
             poles[i] = binned_sums(q, bins, nb) / (sc["norm_I"] * counts)
         if ell == 0:
@@ -139,6 +154,11 @@ def multipoles(data, randoms, params, ell_max: int, k_edges, workers: int = 1, e
     n_inv = 1 if (params["interlaced"] or params["compensated"]) else 0
     return dict(poles=poles, ells=ells, k_mean=kmean, n_modes=counts.astype(np.int64),
                 n_transforms=n_fields + n_fwd + n_inv, **sc)
+
+
+def all_multipoles(data, randoms, params, ell_max: int, k_edges, workers: int = 1):
+    """Every l = 0 .. ell_max: even rows P_l, odd rows R_l (step 7)."""
+    return multipoles(data, randoms, params, ell_max, k_edges, workers, ells=list(range(ell_max + 1)))
 
 
 def default_params(nmesh, box_len, observer=(0.0, 0.0, -1500.0), window=3, interlaced=True,

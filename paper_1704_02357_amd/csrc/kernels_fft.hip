@@ -627,11 +627,16 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
       }
       if (f + 1 == nf || fields[4 * (f + 1) + 3] != slot) {
         double* hs = h + (l0rows + slot) * nb;
+        // even l: Re[C conj acc]; odd l (spherical basis only): Im[C conj acc], the part of
+        // the shell average that survives when a mode and its mirror are summed
+        const bool odd = !CART && (fields[4 * f + 1] & 1);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          if (bin[e] >= 0)
-            lds_atomic_add<double>(&hs[bin[e]], w4pi * ((double)cv[e].x * (double)acc[e].x +
-                                                        (double)cv[e].y * (double)acc[e].y));
+          if (bin[e] >= 0) {
+            const double q = odd ? (double)cv[e].y * (double)acc[e].x - (double)cv[e].x * (double)acc[e].y
+                                 : (double)cv[e].x * (double)acc[e].x + (double)cv[e].y * (double)acc[e].y;
+            lds_atomic_add<double>(&hs[bin[e]], w4pi * q);
+          }
           acc[e] = mk<T>(T(0), T(0));
         }
       }

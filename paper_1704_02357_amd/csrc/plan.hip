@@ -37,7 +37,9 @@ struct GroupCfg {
 };
 struct ComputeCfg {
   int ell_max = -1;
-  int basis = 0;  // 0: spherical harmonics (Sec. 2.1), 1: Cartesian monomials
+  // 0: spherical harmonics, even l (Sec. 2.1); 1: Cartesian monomials, even l; 2: spherical
+  // harmonics, every l (odd l binned as Im[C conj A_l]: pkm_compute_multipoles_all)
+  int basis = 0;
   std::vector<double> edges;
   int nb = 0, total_vals = 0, nfields_total = 0;
   std::vector<GroupCfg> groups;
@@ -314,9 +316,15 @@ Frame harmonic_frame(const pkm_params& p) {
 
 // Weighted fields of a request: 2l+1 per even l >= 2 (spherical), or (p+1)(p+2)/2 monomials
 // per even degree p >= 2 (Cartesian); the l = 0 / p = 0 field is C itself.
+// Request kinds of ComputeCfg::basis.
+constexpr int BASIS_ALL_ELL = 2;
+int ell_step(int basis) { return basis == BASIS_ALL_ELL ? 1 : 2; }
+// Multipole rows of a result: every l, or the even ones.
+int ell_rows(int ell_max, int basis) { return basis == BASIS_ALL_ELL ? ell_max + 1 : ell_max / 2 + 1; }
+
 int fields_for(int ell_max, int basis = 0) {
   int f = 0;
-  for (int l = 2; l <= ell_max; l += 2) f += basis == 1 ? (l + 1) * (l + 2) / 2 : 2 * l + 1;
+  for (int l = ell_step(basis); l <= ell_max; l += ell_step(basis)) f += basis == 1 ? (l + 1) * (l + 2) / 2 : 2 * l + 1;
   return f;
 }
 
@@ -608,7 +616,7 @@ void prepare_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edg
       if (l != last_l) { ++nl; last_l = l; }
       cur.push_back({l, m, nl - 1});
     };
-    for (int l = 2; l <= ell_max; l += 2) {
+    for (int l = ell_step(basis); l <= ell_max; l += ell_step(basis)) {
       if (basis == 1) {
         for (int i = 0; i <= l; ++i)
           for (int j = 0; i + j <= l; ++j) add(l, 32 * i + j);
@@ -619,7 +627,7 @@ void prepare_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edg
     if (!cur.empty()) groups.push_back(cur);
     if (groups.empty()) groups.push_back({});  // l = 0 only
   }
-  const int rows = 3 + ell_max / 2;  // count, ksum, Q0, Q2, ...
+  const int rows = 2 + ell_rows(ell_max, basis);  // count, ksum, Q0, then Q2, Q4, ... (or Q1, Q2, ...)
   const size_t col_lds = xpost_base_bytes(pl->fs, sizeof(T) == 8) + sizeof(long long) * (size_t)n_edges;
   if (col_lds + sizeof(double) * 5 * (size_t)nb > 160 * 1024) {
     pl->err = "too many k bins for one pass";
@@ -660,7 +668,7 @@ void prepare_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edg
     int nv = 0;
     if (first) for (int r = 0; r < 3; ++r) for (int b = 0; b < nb; ++b) { maps.push_back(r * nb + b); ++nv; }
     for (size_t si = 0; si < slot_l.size(); ++si)
-      for (int b = 0; b < nb; ++b) { maps.push_back((2 + slot_l[si] / 2) * nb + b); ++nv; }
+      for (int b = 0; b < nb; ++b) { maps.push_back((2 + slot_l[si] / ell_step(basis)) * nb + b); ++nv; }
     gc.nv = nv;
     gc.nslots = (int)slot_l.size();
     cc.groups.push_back(gc);
@@ -754,7 +762,7 @@ void normalize(const pkm_plan* pl, const double* res, double norm_I, double shot
     if (out->n_modes) out->n_modes[b] = (int64_t)llround(cnt);
     if (out->k_mean) out->k_mean[b] = cnt > 0 ? res[nb + b] / cnt : NAN;
     if (out->poles) {
-      for (int il = 0; il <= cc.ell_max / 2; ++il) {
+      for (int il = 0; il < ell_rows(cc.ell_max, cc.basis); ++il) {
         double q = res[(2 + il) * nb + b];
         if (cc.basis == 1) {
           // Cartesian rows hold R_p = sum Re[C conj M_p], M_p the transform of D_c (khat.xhat)^p
@@ -1087,9 +1095,14 @@ void free_all(pkm_plan* pl) {
   if (pl->ev1) (void)hipEventDestroy(pl->ev1);
 }
 
-pkm_status validate_request(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges) {
+pkm_status validate_request(pkm_plan* pl, int ell_max, const double* k_edges, int n_edges, bool all_ell = false) {
   if (!k_edges || n_edges < 2) { pl->err = "need k_edges (n_edges >= 2)"; return PKM_EINVAL; }
-  if (ell_max < 0 || ell_max > 16 || ell_max % 2) { pl->err = "ell_max must be even and in 0..16"; return PKM_EINVAL; }
+  if (all_ell) {
+    if (ell_max < 0 || ell_max > 16) { pl->err = "ell_max must be in 0..16"; return PKM_EINVAL; }
+  } else if (ell_max < 0 || ell_max > 16 || ell_max % 2) {
+    pl->err = "ell_max must be even and in 0..16";
+    return PKM_EINVAL;
+  }
   for (int i = 0; i < n_edges; ++i) {
     if (!(k_edges[i] >= 0.0) || !std::isfinite(k_edges[i])) { pl->err = "k edges must be finite and >= 0"; return PKM_EINVAL; }
     if (i > 0 && !(k_edges[i] > k_edges[i - 1])) { pl->err = "k edges must be strictly increasing"; return PKM_EINVAL; }
@@ -1355,6 +1368,22 @@ pkm_status pkm_compute_multipoles_basis(pkm_plan* pl, int32_t ell_max, const dou
 pkm_status pkm_compute_multipoles(pkm_plan* pl, int32_t ell_max, const double* k_edges, int32_t n_edges,
                                   pkm_result* out) {
   return pkm_compute_multipoles_basis(pl, ell_max, k_edges, n_edges, PKM_BASIS_SPHERICAL, out);
+}
+
+pkm_status pkm_compute_multipoles_all(pkm_plan* pl, int32_t ell_max, const double* k_edges, int32_t n_edges,
+                                      pkm_result* out) {
+  if (!pl) return PKM_EINVAL;
+  if (!out) { pl->err = "need a result"; return PKM_EINVAL; }
+  if (validate_request(pl, ell_max, k_edges, n_edges, true) != PKM_OK) return PKM_EINVAL;
+  if (pl->pending_async) { pl->err = "an enqueued estimate has not been finished"; return PKM_EBUSY; }
+  if (!pl->painted) { pl->err = "pkm_paint must succeed before pkm_compute_multipoles_all"; return PKM_EORDER; }
+  pkm_status st = guarded(pl, [&] {
+    check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
+    if (pl->fp64) run_compute<double>(pl, ell_max, k_edges, n_edges, BASIS_ALL_ELL, out);
+    else run_compute<float>(pl, ell_max, k_edges, n_edges, BASIS_ALL_ELL, out);
+  });
+  pl->stats.device_bytes = pl->bytes;
+  return st;
 }
 
 // Arguments of the (k, mu) calls; PKM_OK when the request can run.

@@ -117,6 +117,7 @@ def load_library():
         "pkm_paint": (C.c_int, [P, C.POINTER(Catalog), C.POINTER(Catalog)]),
         "pkm_compute_multipoles": (C.c_int, [P, C.c_int32, P, C.c_int32, C.POINTER(Result)]),
         "pkm_compute_multipoles_basis": (C.c_int, [P, C.c_int32, P, C.c_int32, C.c_int32, C.POINTER(Result)]),
+        "pkm_compute_multipoles_all": (C.c_int, [P, C.c_int32, P, C.c_int32, C.POINTER(Result)]),
         "pkm_kmu_global": (C.c_int, [P, P, C.c_int32, P, C.c_int32, P, P]),
         "pkm_wedges": (C.c_int, [P, C.c_int32, C.c_int32, P, C.c_int32, P]),
         "pkm_kaiser_wedge_gamma": (C.c_int, [C.c_int32, P, C.c_int32, C.c_double, P]),
@@ -238,8 +239,8 @@ def make_params(nmesh, box_len, *, box_origin=None, observer=(0.0, 0.0, 0.0), wi
     return p
 
 
-def _result_arrays(ell_max: int, nb: int):
-    poles = np.empty((ell_max // 2 + 1, nb))
+def _result_arrays(ell_max: int, nb: int, all_ell: bool = False):
+    poles = np.empty((ell_max + 1 if all_ell else ell_max // 2 + 1, nb))
     kmean = np.empty(nb)
     nmodes = np.empty(nb, dtype=np.int64)
     r = Result()
@@ -247,9 +248,9 @@ def _result_arrays(ell_max: int, nb: int):
     return r, poles, kmean, nmodes
 
 
-def _result_dict(r, poles, kmean, nmodes, ell_max):
+def _result_dict(r, poles, kmean, nmodes, ell_max, all_ell: bool = False):
     return dict(poles=poles, k_mean=kmean, n_modes=nmodes, alpha=r.alpha, norm_I=r.norm_I, shot_noise=r.shot_noise,
-                n_transforms=r.n_transforms, ells=list(range(0, ell_max + 1, 2)))
+                n_transforms=r.n_transforms, ells=list(range(0, ell_max + 1, 1 if all_ell else 2)))
 
 
 class Plan:
@@ -327,6 +328,14 @@ class Plan:
         st = self.lib.pkm_compute_multipoles_basis(self.h, int(ell_max), _ptr(e), e.size, int(basis), C.byref(r))
         self._check(st, "pkm_compute_multipoles_basis")
         return _result_dict(r, poles, kmean, nmodes, ell_max)
+
+    def compute_multipoles_all(self, ell_max: int, k_edges) -> dict:
+        """Every l <= ell_max, odd included: even rows P_l, odd rows R_l = Im P_l (eq. Pell-ours)."""
+        e = np.ascontiguousarray(k_edges, dtype=np.float64)
+        r, poles, kmean, nmodes = _result_arrays(ell_max, e.size - 1, all_ell=True)
+        st = self.lib.pkm_compute_multipoles_all(self.h, int(ell_max), _ptr(e), e.size, C.byref(r))
+        self._check(st, "pkm_compute_multipoles_all")
+        return _result_dict(r, poles, kmean, nmodes, ell_max, all_ell=True)
 
     # -- asynchronous estimate -------------------------------------------------------------
     def prepare(self, ell_max: int, k_edges, max_particles: int):
