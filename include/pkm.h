@@ -264,6 +264,19 @@ pkm_status pkm_compute_multipoles_all(pkm_plan* plan, int32_t ell_max, const dou
 pkm_status pkm_kmu_global(pkm_plan* plan, const double* k_edges, int32_t n_k_edges, const double* mu_edges,
                           int32_t n_mu_edges, double* pkmu_out, int64_t* nmodes_out);
 
+/* pkm_kmu_global for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same (k, mu) cells,
+ * arguments, outputs and errors, but no device or pinned allocation and no free.  Its
+ * thresholds, mu edges, per-block partial sums and results live in one fixed device array
+ * of 12.7 MB per device (each device the library runs on holds it until the process ends).
+ * At most 3072 (k, mu) cells, as for pkm_kmu_global; more is PKM_EINVAL.  Every call on one
+ * device shares that array: calls that overlap on one device (from several threads, or on
+ * plans with different streams) race and must be serialised by the caller.  The cells' sums
+ * are accumulated over 256 blocks instead of pkm_kmu_global's 1024, so the two agree to
+ * FP64 rounding (counts exactly).  Synchronous, like pkm_kmu_global.                      */
+pkm_status pkm_kmu_global_noalloc(pkm_plan* plan, const double* k_edges, int32_t n_k_edges, const double* mu_edges,
+                                  int32_t n_mu_edges, double* pkmu_out, int64_t* nmodes_out);
+
 /* Sec. 2.2 eq. wedge-est with eq. Lbar, host only, FP64:
  *   wedges_out[i*(n_mu_edges-1) + j] = sum_{even l <= ell_max} poles[(l/2)*n_k + i] Lbar_l(mu_j, mu_{j+1}).
  * mu edges strictly increasing in [0, 1].                                                   */

@@ -131,6 +131,11 @@ template <typename T>
 hipError_t launch_kmu(const FftShape& fs, const void* c_in, const double* los, const BinSpec& bs,
                       const double* mu_edges, int nmu, double* partial, int nblk, hipStream_t s);
 
+// Device-side normalisation of reduced (k, mu) sums {count, sum |C|^2} per cell into
+// P = sum / (I count) - S (NaN when empty) and the integer counts.
+hipError_t launch_kmu_finish(const double* sums, int ncells, double norm_I, double shot, double* pk, long long* nm,
+                             hipStream_t s);
+
 int xpass_blocks(const FftShape& fs);
 int xpass_threads(const FftShape& fs);
 int post_blocks(const FftShape& fs);

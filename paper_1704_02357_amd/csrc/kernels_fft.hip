@@ -731,6 +731,19 @@ __global__ void k_kmu(int n, const cx<T>* __restrict__ cin, double l0, double l1
   hist_flush(hist, 1, nvals, partial + (size_t)blockIdx.x * nvals);
 }
 
+// Normalisation of reduced (k, mu) sums on the device, FP64 with explicitly rounded
+// operations (the host form of the same formula gives identical bits):
+// pk[i] = sum_i / (I cnt_i) - S (NaN for an empty cell), nm[i] = cnt_i.
+__global__ void k_kmu_finish(const double* __restrict__ sums, int ncells, double norm_I, double shot,
+                             double* __restrict__ pk, long long* __restrict__ nm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncells) return;
+  const double cnt = sums[2 * i];
+  nm[i] = __double2ll_rn(cnt);
+  pk[i] = cnt > 0.0 ? __dsub_rn(__ddiv_rn(sums[2 * i + 1], __dmul_rn(norm_I, cnt)), shot)
+                    : __longlong_as_double(0x7ff8000000000000LL);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
@@ -934,6 +947,13 @@ hipError_t launch_kmu(const FftShape& fs, const void* c_in, const double* los, c
   const size_t sm = sizeof(double) * 2 * (size_t)bs.nb * nmu;
   k_kmu<T><<<nblk, 256, sm, s>>>(fs.n, (const cx<T>*)c_in, los[0], los[1], los[2], bs.thr, bs.nb, mu_edges, nmu,
                                  partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_kmu_finish(const double* sums, int ncells, double norm_I, double shot, double* pk, long long* nm,
+                             hipStream_t s) {
+  if (ncells <= 0) return hipSuccess;
+  k_kmu_finish<<<(ncells + 255) / 256, 256, 0, s>>>(sums, ncells, norm_I, shot, pk, nm);
   return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <unordered_map>
@@ -880,6 +881,85 @@ void run_kmu(pkm_plan* pl, const double* k_edges, int nke, const double* mu_edge
   dfree(pl, thr_d); dfree(pl, mue_d); dfree(pl, part); dfree(pl, outd);
 }
 
+// ------------------------------------------------------------------------------------------
+// Allocation-free (k, mu) binning.  Its thresholds, mu edges, per-block partial sums, reduced
+// sums and normalised outputs live in one file-scope device array, `scratch`, sized for the
+// largest request the (k, mu) kernel takes (KMU_MAX_CELLS cells, the limit of its LDS
+// histogram).  Each device holds its own copy until the process ends; host code reaches it
+// only through the address hipGetSymbolAddress returns for the current device.
+// ------------------------------------------------------------------------------------------
+constexpr int KMU_NOALLOC_BLOCKS = 256;    // k_kmu grid of the allocation-free path
+constexpr size_t kmu_align(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t KMU_OFF_THR = 0;
+constexpr size_t KMU_OFF_MU = KMU_OFF_THR + kmu_align(sizeof(long long) * (KMU_MAX_CELLS + 1));
+constexpr size_t KMU_OFF_PART = KMU_OFF_MU + kmu_align(sizeof(double) * (KMU_MAX_CELLS + 1));
+constexpr size_t KMU_OFF_SUMS = KMU_OFF_PART + kmu_align(sizeof(double) * 2 * (size_t)KMU_MAX_CELLS * KMU_NOALLOC_BLOCKS);
+constexpr size_t KMU_OFF_PK = KMU_OFF_SUMS + kmu_align(sizeof(double) * 2 * KMU_MAX_CELLS);
+constexpr size_t KMU_OFF_NM = KMU_OFF_PK + kmu_align(sizeof(double) * KMU_MAX_CELLS);
+constexpr size_t KMU_SCRATCH_BYTES = KMU_OFF_NM + kmu_align(sizeof(long long) * KMU_MAX_CELLS);  // 12.7 MB
+
+static __device__ __align__(256) unsigned char scratch[KMU_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the plan's device (current: the entry point set it), looked
+// up once per device.
+unsigned char* scratch_of(pkm_plan* pl) {
+  const int dev = pl->dev.device_id;
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    pl->err = "device id out of range";
+    throw Fail{PKM_EINVAL};
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      pl->err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+      throw Fail{PKM_EDEVICE};
+    }
+    g_scratch_ptr[dev] = (unsigned char*)ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+template <typename T>
+void run_kmu_noalloc(pkm_plan* pl, const double* k_edges, int nke, const double* mu_edges, int nme, double* pk,
+                     int64_t* nm) {
+  hipStream_t s = pl->stream;
+  const int nb = nke - 1, nmu = nme - 1, ncells = nb * nmu;
+  unsigned char* base = scratch_of(pl);
+  long long* thr_d = (long long*)(base + KMU_OFF_THR);
+  double* mue_d = (double*)(base + KMU_OFF_MU);
+  double* part = (double*)(base + KMU_OFF_PART);
+  double* sums = (double*)(base + KMU_OFF_SUMS);
+  double* pk_d = (double*)(base + KMU_OFF_PK);
+  long long* nm_d = (long long*)(base + KMU_OFF_NM);
+  long long thr[KMU_MAX_CELLS + 1];  // host stack: the same thresholds as the allocating path
+  for (int i = 0; i < nke; ++i) {
+    const double t = (k_edges[i] * pl->p.box_len) / (2.0 * M_PI);
+    const double t2 = t * t;
+    thr[i] = t2 >= 9.0e18 ? (long long)9.0e18 : (long long)std::ceil(t2);
+  }
+  check_hip(pl, hipMemcpyAsync(thr_d, thr, sizeof(long long) * nke, hipMemcpyHostToDevice, s), "thr");
+  check_hip(pl, hipMemcpyAsync(mue_d, mu_edges, sizeof(double) * nme, hipMemcpyHostToDevice, s), "mu edges");
+  double l[3] = {pl->p.los[0], pl->p.los[1], pl->p.los[2]};
+  const double ln = std::sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]);
+  for (double& v : l) v /= ln;
+  // every block writes all 2 ncells of its partial row, the reduction and the normalisation
+  // write every cell: nothing of an earlier call is read
+  check_hip(pl, launch_kmu<T>(pl->fs, pl->c, l, BinSpec{thr_d, nb, 1}, mue_d, nmu, part, KMU_NOALLOC_BLOCKS, s),
+            "kmu");
+  check_hip(pl, launch_reduce(part, KMU_NOALLOC_BLOCKS, 2 * ncells, sums, nullptr, 0, s), "reduce");
+  check_hip(pl, launch_kmu_finish(sums, ncells, pl->norm_I, pl->shot, pk_d, nm_d, s), "kmu finish");
+  if (pk) check_hip(pl, hipMemcpyAsync(pk, pk_d, sizeof(double) * ncells, hipMemcpyDeviceToHost, s), "download");
+  if (nm) check_hip(pl, hipMemcpyAsync(nm, nm_d, sizeof(long long) * ncells, hipMemcpyDeviceToHost, s), "download");
+  check_hip(pl, hipStreamSynchronize(s), "sync");
+}
+
 template <typename T> void run_fft_forward(pkm_plan* pl, const void* in, void* out) {
   hipStream_t s = pl->stream;
   check_hip(pl, launch_zfwd<T>(pl->fs, (const T*)in, nullptr, out, nullptr, 1, pl->tw, s), "zfwd");
@@ -1416,6 +1496,18 @@ pkm_status pkm_kmu_global(pkm_plan* pl, const double* k_edges, int32_t n_k_edges
     check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
     if (pl->fp64) run_kmu<double>(pl, k_edges, n_k_edges, mu_edges, n_mu_edges, pkmu_out, nmodes_out);
     else run_kmu<float>(pl, k_edges, n_k_edges, mu_edges, n_mu_edges, pkmu_out, nmodes_out);
+  });
+}
+
+pkm_status pkm_kmu_global_noalloc(pkm_plan* pl, const double* k_edges, int32_t n_k_edges, const double* mu_edges,
+                                  int32_t n_mu_edges, double* pkmu_out, int64_t* nmodes_out) {
+  if (!pl) return PKM_EINVAL;
+  const pkm_status v = validate_kmu(pl, k_edges, n_k_edges, mu_edges, n_mu_edges);
+  if (v != PKM_OK) return v;
+  return guarded(pl, [&] {
+    check_hip(pl, hipSetDevice(pl->dev.device_id), "hipSetDevice");
+    if (pl->fp64) run_kmu_noalloc<double>(pl, k_edges, n_k_edges, mu_edges, n_mu_edges, pkmu_out, nmodes_out);
+    else run_kmu_noalloc<float>(pl, k_edges, n_k_edges, mu_edges, n_mu_edges, pkmu_out, nmodes_out);
   });
 }
 

@@ -119,6 +119,7 @@ def load_library():
         "pkm_compute_multipoles_basis": (C.c_int, [P, C.c_int32, P, C.c_int32, C.c_int32, C.POINTER(Result)]),
         "pkm_compute_multipoles_all": (C.c_int, [P, C.c_int32, P, C.c_int32, C.POINTER(Result)]),
         "pkm_kmu_global": (C.c_int, [P, P, C.c_int32, P, C.c_int32, P, P]),
+        "pkm_kmu_global_noalloc": (C.c_int, [P, P, C.c_int32, P, C.c_int32, P, P]),
         "pkm_wedges": (C.c_int, [P, C.c_int32, C.c_int32, P, C.c_int32, P]),
         "pkm_kaiser_wedge_gamma": (C.c_int, [C.c_int32, P, C.c_int32, C.c_double, P]),
         "pkm_nonuniform_mu_edges": (C.c_int, [C.c_int32, P]),
