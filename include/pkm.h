@@ -169,11 +169,12 @@ typedef struct pkm_plan pkm_plan;
 /* Launch shape of the passes.  A zero field keeps the built-in choice for the mesh size and
  * precision.  e_col / e_z / e_post are elements per thread of the length-N column passes,
  * the length-N/2 z passes and the post-pass (4, 6, 8, 12 or 16 with a radix schedule for
- * the length); tile / tile_post are kz columns per block of the column passes and the
- * post-pass; zlines is z lines per block; paint_tile is the painting tile side (4, 8, 16);
- * post_axis chooses the last transform axis of the weighted fields (1: along x, 2: along y,
- * i.e. the stored value is the axis + 1 so that zero keeps the default).  A shape that breaks
- * a kernel limit (threads per block, LDS bytes, divisibility) is rejected with PKM_EINVAL.  */
+ * the length); tile is columns per block of the column passes; tile_post is y lines (one per
+ * kz) per post-pass tile; zlines is z lines per block (a divisor of N); paint_tile is the
+ * painting tile side (4, 8, 16); post_axis names the last transform axis of the weighted
+ * fields, the axis + 1: the fields are stored kz-major ([kz][x][y]) and finish along y, so
+ * only 0 (default) and 2 are accepted.  A shape that breaks a kernel limit (threads per
+ * block, LDS bytes, divisibility) is rejected with PKM_EINVAL.                             */
 typedef struct {
   int32_t e_col, tile, e_z, zlines, e_post, tile_post, paint_tile, post_axis;
 } pkm_shape;

@@ -22,9 +22,8 @@ struct FftShape {
   int nst_post;
   int tile_post;    // columns per post-pass tile
   int cus;          // compute units of the device (0: unknown)
-  int post_axis;    // last transform axis of the weighted fields: 0 = x, 1 = y
-  int fpad;         // extra elements per x plane of a field buffer: the plane stride
-                    // n n/2 + fpad is then not a power of two
+  int fpad;         // extra elements per kz plane of a field buffer [kz][x][y]: the plane
+                    // stride n n + fpad is then not a power of two
 };
 
 // Bytes of LDS of the z-pass and column-pass blocks of a shape.
@@ -88,8 +87,9 @@ template <typename T>
 hipError_t launch_zfwd(const FftShape& fs, const T* in0, const T* in1, void* out0, void* out1, int nbuf,
                        const void* tw, hipStream_t s);
 
-// Column transform along y (axis = 1) or x (axis = 0) of nbuf half-spectra in place.
-// fields = true: the buffers are field buffers (x planes fs.fpad elements apart beyond n n/2).
+// Column transform of nbuf buffers in place: half spectra [x][y][kz] along y (axis = 1) or x
+// (axis = 0); fields = true: kz-major field buffers [kz][x][y] (kz planes of n n + fs.fpad
+// elements) along x.
 template <typename T>
 hipError_t launch_col(const FftShape& fs, void* const* bufs_dev, int nbuf, int axis, bool inverse,
                       const void* tw, hipStream_t s, bool fields = false);
@@ -102,7 +102,8 @@ hipError_t launch_xcombine(const FftShape& fs, void* s1, void* s2, void* c_out, 
                            int compensated, const void* invw, const void* phase, const void* tw, hipStream_t s);
 
 // Inverse z (half-complex to real) of G, scaled to D_c, then for every field f in the group
-// the Y_lm(xhat)-weighted forward transform along z into bufs[f].  If real_in != null the
+// the Y_lm(xhat)-weighted forward transform along z into the kz-major field buffer bufs[f]
+// ([kz][x][y], kz planes of n n + fs.fpad elements).  Needs fs.zlines to divide n.  If real_in != null the
 // field D_c is read directly from that real mesh instead.  If real_out != null D_c is also
 // written there.  basis 1 (Cartesian decomposition): field f is weighted by the monomial
 // xhat^a of degree fields[4f+1] and index code fields[4f+2] instead of Y_lm(xhat).
@@ -111,15 +112,16 @@ hipError_t launch_zpre(const FftShape& fs, const void* g_in, const T* real_in, T
                        int nf, const int* fields_dev, double scale, const double* off, double h, const void* ytab,
                        const void* tw, const Frame& frame, int basis, hipStream_t s);
 
-// Last transform pass of every field of the group (along x for axis 0, along y for axis 1),
-// sum over m of Y_lm(khat) B_lm per multipole slot, product with C and binning.  Per block the partial sums are rows of nb bins:
+// Last transform pass of every field of the group (along y over the kz-major field buffers),
+// sum over m of Y_lm(khat) B_lm per multipole slot, product with C and binning.  Odd l
+// (spherical basis) are binned as Im[C conj (sum)] instead of Re.  Per block the partial sums are rows of nb bins:
 // [count, sum |k|, sum |C|^2] when with_l0, then one row of sum 4 pi Y Re[C conj B] per slot.
 // basis 1: the slot sums (p!/a!) khat^a B_a over the monomials a of one degree p, and its row
 // holds sum Re[C conj (that sum)] without the 4 pi.
 template <typename T>
 hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const int* fields_dev, int nslots,
                         int with_l0, const void* c_in, const void* ytab, const BinSpec& bs, double kf,
-                        double* partial, int* nblocks_out, const void* tw, int axis, const Frame& frame, int basis,
+                        double* partial, int* nblocks_out, const void* tw, const Frame& frame, int basis,
                         hipStream_t s);
 
 // out[map[v]] (+)= sum_b partial[b*nvals + v] (map null -> identity), fixed order.

@@ -12,9 +12,11 @@
 //   column   : length-N transforms along y or x over tiles of `tile` adjacent kz columns.
 //   xcombine : forward x of both painted meshes + interlace combine + compensation +
 //              Nyquist zero, then inverse x of C.
-//   xpost    : last transform of every field of a group (along x for FP32, along y for
-//              FP64), sum_m Y_lm(khat) B_lm, product with C, and binning into per-block
-//              partial sums.
+//   xpost    : last transform of every field of a group (along y), sum_m Y_lm(khat) B_lm,
+//              product with C, and binning into per-block partial sums.
+// The weighted fields are kz-major, [kz][x][y] (kz planes of n n + fpad elements): the
+// pre-pass writes them transposed, the field column pass runs along x within each kz plane,
+// and the post-pass reads whole contiguous y lines.
 // Both harmonic passes evaluate Y_lm for the direction turned by the plan's Frame (any
 // orthogonal frame gives the same sums over m), or, with the CART flag, the monomials of
 // the Cartesian decomposition.
@@ -35,9 +37,12 @@ namespace {
 constexpr double FOUR_PI = 12.566370614359172953850573533118;
 constexpr int ZPAD = 3;  // z-line LDS layout: one spare slot per 8 complex
 __host__ __device__ constexpr int zpitch(int nh) { return nh + (nh >> ZPAD) + 1; }
-constexpr int XPAD = 3;  // post-pass tile: one spare row per 8 rows
+constexpr int XPAD = 3;  // post-pass line exchange: one spare slot per 8 elements
 __host__ __device__ constexpr int xrows(int n) { return n + (n >> XPAD) + 1; }
-constexpr int ZMAX_THREADS = 256;
+// z-pass blocks: up to 512 threads in FP32 (16 lines of 512: the pre-pass then writes
+// 128-byte runs of y), 256 in FP64, whose pre-pass needs more than 256 registers per thread
+// and so cannot hold two waves per SIMD
+template <typename T> __host__ __device__ constexpr int zmax_threads() { return sizeof(T) == 4 ? 512 : 256; }
 constexpr int XMAX_THREADS = 512;
 constexpr int XPOST_THREADS = 256;
 
@@ -196,7 +201,7 @@ __device__ __forceinline__ void hist_flush(const double* h, int copies, int nval
 // LDS of the z passes: G padded lines, the W_N^j table (N entries; the splits read the
 // first N/2), and on the compile-time path the per-stage table of the length-N/2 transform.
 template <typename T, int E, int NC, int TC>
-__global__ void __launch_bounds__(ZMAX_THREADS) k_zfwd(int n_rt, int g_rt, uint32_t sched, int nst,
+__global__ void __launch_bounds__(zmax_threads<T>()) k_zfwd(int n_rt, int g_rt, uint32_t sched, int nst,
                                                         const T* __restrict__ in0, const T* __restrict__ in1,
                                                         void* __restrict__ out0, void* __restrict__ out1,
                                                         const cx<T>* __restrict__ tw) {
@@ -240,25 +245,26 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zfwd(int n_rt, int g_rt, uint3
 // ------------------------------------------------------------------------------------------
 // column pass (length N along y or x), in place.  Lane c = tid % tile, t = tid / tile: the
 // tile load leaves rows t + pt*e of column c in the thread's registers, which is the
-// transform's own register layout, so LDS is used only between radix stages.
+// transform's own register layout, so LDS is used only between radix stages.  Tiles run over
+// the contiguous axis (clen elements: N/2 kz of a half spectrum, N y of a kz-major field
+// buffer) within each outer plane.
 // ------------------------------------------------------------------------------------------
 template <typename T, int E, bool INV, int NC, int TC>
 __global__ void __launch_bounds__(XMAX_THREADS) k_col(int n_rt, int tile_rt, uint32_t sched, int nst,
                                                        void* const* __restrict__ bufs, size_t row_stride,
-                                                       size_t outer_stride, const cx<T>* __restrict__ tw) {
+                                                       size_t outer_stride, int clen, const cx<T>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
   const int n = NC > 0 ? NC : n_rt;
   const int tile = TC > 0 ? TC : tile_rt;
-  const int nh = n >> 1;
   const int pt = n / E;
   const int bs = pt * tile;
-  const int tiles = nh / tile;
+  const int tiles = clen / tile;
   const int blk = xcd_tile(blockIdx.x, gridDim.x);
   const int outer = blk / tiles;
-  const int kz0 = (blk % tiles) * tile;
+  const int c0 = (blk % tiles) * tile;
   cx<T>* buf = reinterpret_cast<cx<T>*>(bufs[blockIdx.y]);
-  const size_t base = (size_t)outer * outer_stride + kz0;
+  const size_t base = (size_t)outer * outer_stride + c0;
   const int pitch = tile + 1;
   const int tid = threadIdx.x;
   const int c = tid % tile, t = tid / tile;
@@ -341,11 +347,13 @@ __global__ void __launch_bounds__(XMAX_THREADS) k_xcombine(int n_rt, int tile_rt
 // ------------------------------------------------------------------------------------------
 // z pre-pass: D_c from G (inverse z), then weighted forward z for every field of the group.
 // Fields come |m|-major (the table order) so the harmonic recurrence continues across them.
-// Each line is handled by the threads of one wavefront (compile-time path), so the field
-// loop needs no block barrier.
+// Each line is transformed by the threads of one wavefront (compile-time path).  A block holds
+// G lines of one x plane (consecutive y); the finished lines of a field are parked in a second
+// LDS region and written transposed into the kz-major field buffer [kz][x][y], G consecutive
+// y per piece (the post-pass then reads whole y lines).
 // ------------------------------------------------------------------------------------------
 template <typename T, int E, int NC, int TC, bool CART = false>
-__global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n_rt, int g_rt, uint32_t sched, int nst,
+__global__ void __launch_bounds__(zmax_threads<T>()) k_zpre(int n_rt, int g_rt, uint32_t sched, int nst,
                                                         const cx<T>* __restrict__ gin, const T* __restrict__ real_in,
                                                         T* __restrict__ real_out, void* const* __restrict__ bufs,
                                                         int nf, const int* __restrict__ fields, T scale, double off0,
@@ -366,7 +374,10 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n_rt, int g_rt, uint3
   const int t = tid % pt, g = tid / pt;
   const size_t lineg = line0 + g;
   cx<T>* line = lds + g * lp;
-  cx<T>* twl = stage_twiddles<T>(lds + (size_t)G * lp, tw, n);
+  // two line regions alternate between fields: field f is transformed and parked in region
+  // f mod 2 while the transposed writes of field f - 1 may still read the other one
+  const size_t region = (size_t)G * lp;
+  cx<T>* twl = stage_twiddles<T>(lds + 2 * region, tw, n);
   cx<T>* twst = twl + n;
   if constexpr (NC > 0) ct_twiddles<T, E, NC / 2, NC>(twst, tw);
   const LineRt rt{nh, sched, nst, pt, n};
@@ -420,6 +431,10 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n_rt, int g_rt, uint3
     uz[q] = (T)(fr.r[6] * vx + fr.r[7] * vy + fr.r[8] * vz);
     if (zero) r[q] = T(0);
   }
+  // the block's lines: x plane bx, y = by0 .. by0 + G - 1 (G divides n)
+  const int bx = (int)(line0 / n), by0 = (int)(line0 % n);
+  const size_t fplane = (size_t)n * n + fpad;
+  const size_t fo = (size_t)bx * n + by0;
   YRun<T, 2 * E> yr;
   yrun_init(yr);
   for (int f = 0; f < nf; ++f) {
@@ -431,32 +446,41 @@ __global__ void __launch_bounds__(ZMAX_THREADS) k_zpre(int n_rt, int g_rt, uint3
     cx<T> u[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) u[e] = mk<T>(r[2 * e] * yv[2 * e], r[2 * e + 1] * yv[2 * e + 1]);
-    xf_regs<T, E, false, ZPAD, NC / 2, WAVE>(lds, g * lp, 1, rt, t, u, twst, twl);
-    // the split needs X_k and X_{nh-k}: park the line in LDS (own slots), then read
+    cx<T>* park = lds + (f & 1) * region;
+    xf_regs<T, E, false, ZPAD, NC / 2, WAVE>(park, g * lp, 1, rt, t, u, twst, twl);
+    // park the line where its transform ran (the threads of the line have finished reading
+    // those slots), then every thread writes G consecutive y of one kz: the split needs X_k
+    // and X_{nh-k} of a line.  The barrier also orders the last reads of this region by the
+    // transposed writes of field f - 2 before this field's transform reused it.
+    if constexpr (WAVE) ct_sync<true>(); else __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) line[padi<ZPAD>(t + pt * e)] = u[e];
-    if constexpr (NC > 0) ct_sync<WAVE>(); else __syncthreads();
+    for (int e = 0; e < E; ++e) park[g * lp + padi<ZPAD>(t + pt * e)] = u[e];
+    __syncthreads();
     cx<T>* out = reinterpret_cast<cx<T>*>(bufs[fields[4 * f]]);
-    const size_t ob = (size_t)ix * ((size_t)n * nh + fpad) + (size_t)iy * nh;  // padded x planes
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int k = t + pt * e;
-      gstore<T>(out, ob + k, r2c_split<T>(line, k, nh, twl));
+      const int o = tid + e * bs;
+      const int gg = tmod(o, G), k = tdiv(o, G);
+      gstore<T>(out, (size_t)k * fplane + fo + gg, r2c_split<T>(park + gg * lp, k, nh, twl));
     }
   }
 }
 
 // ------------------------------------------------------------------------------------------
-// x post-pass: forward x of each field, sum_m Y_lm(khat) B, product with C, binning.
-// Fields come l-major (slots contiguous).  One complex accumulator per element holds
-// sum_m Y_lm(khat) B_lm of the current slot; at the last field of a slot it is folded
-// against C (held in registers for the whole tile) into the FP64 bin histogram.  Two tile
-// buffers alternate between fields, so one block barrier per field suffices; the transform
-// itself runs within one wavefront per column on the compile-time path.
+// post-pass: the last transform of every field, along y (kz-major field buffers hold whole y
+// lines), sum_m Y_lm(khat) B, product with C, binning.  A tile is TP lines of one x plane,
+// kz = kz0 .. kz0 + TP - 1; thread (t, c) transforms line c and holds y = t + pt e, the
+// transform's own register layout, so each line is loaded straight into registers (whole
+// contiguous lines, the next field prefetched during the current one) and LDS carries only the
+// stage exchanges (within one wavefront on the compile-time path), the tile's C and the
+// histograms.  Fields come l-major (slots contiguous): one complex accumulator per element holds
+// sum_m Y_lm(khat) B_lm of the current slot and is folded against C into the FP64 bins at the
+// slot's last field.
 // ------------------------------------------------------------------------------------------
+// LDS entries (complex) before the histograms: exchanges, the tile's C, twiddles.
 template <typename T, int E, int NC>
-__host__ __device__ constexpr size_t xpost_elems(int n, int tile) {
-  return 2 * (size_t)xrows(n) * (tile + 1) + (NC > 0 ? twst_size<E, NC>() : n);
+__host__ __device__ constexpr size_t xpost_elems(int n, int tp) {
+  return (size_t)tp * xrows(n) + (size_t)tp * n + (NC > 0 ? twst_size<E, NC>() : n);
 }
 
 // Tiles of a persistent post-pass block.  When the tile count and the grid are multiples of
@@ -510,86 +534,88 @@ __device__ __forceinline__ void kbins_lds(const long long* thr, int nb, const in
 }
 
 template <typename T, int E, int NC, int TC, bool CART = false>
-__global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, uint32_t sched, int nst,
+__global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tp_rt, uint32_t sched, int nst,
                                                           void* const* __restrict__ bufs, int nf,
                                                           const int* __restrict__ fields, int nslots, int with_l0,
                                                           double kf, const cx<T>* __restrict__ cin,
                                                           const T* __restrict__ ytab,
                                                           const long long* __restrict__ thr, int nb, int copies,
                                                           double* __restrict__ partial,
-                                                          const cx<T>* __restrict__ tw, int axis, Frame frm,
-                                                          int fpad) {
+                                                          const cx<T>* __restrict__ tw, Frame frm, int fpad) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = NC > 0 ? NC : n_rt;
-  const int tile = TC > 0 ? TC : tile_rt;
+  const int TP = TC > 0 ? TC : tp_rt;
   const int nh = n >> 1;
-  const int pitch = tile + 1;
   const int pt = n / E;
-  const int bs = pt * tile;
+  const int bs = pt * TP;
   constexpr bool WAVE = NC > 0 && NC / E <= 64;
-  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
-  const size_t tsz = (size_t)xrows(n) * pitch;
-  cx<T>* twl = lds + 2 * tsz;
+  const int lx = xrows(n);  // padded length of a line's exchange region
+  cx<T>* exch = reinterpret_cast<cx<T>*>(smem);
+  cx<T>* cst = exch + (size_t)TP * lx;  // C of the tile, [line][y]
+  cx<T>* twl = cst + (size_t)TP * n;
   cx<T>* twst = twl;
-  double* hist = reinterpret_cast<double*>(smem + sizeof(cx<T>) * xpost_elems<T, E, NC>(n, tile));
+  double* hist = reinterpret_cast<double*>(smem + sizeof(cx<T>) * xpost_elems<T, E, NC>(n, TP));
   const int l0rows = with_l0 ? 3 : 0;
   const int nvals = (l0rows + nslots) * nb;
   long long* thr_l = reinterpret_cast<long long*>(hist + (size_t)copies * nvals);
   hist_zero(hist, copies * nvals);
   for (int i = threadIdx.x; i <= nb; i += blockDim.x) thr_l[i] = thr[i];
   if constexpr (NC > 0) ct_twiddles<T, E, NC, NC>(twst, tw); else stage_twiddles<T>(twl, tw, n);
-  // axis 0: the transform runs along x (rows x, tiles over y); axis 1: along y (rows y, tiles
-  // over x).  Rows are n*nh (axis 0) or nh (axis 1) elements apart.
-  const int tiles_x = nh / tile;
-  const size_t rs = axis ? (size_t)nh : (size_t)n * nh;
-  const size_t os = axis ? (size_t)n * nh : (size_t)nh;
+  const int kgroups = nh / TP;
+  const size_t fplane = (size_t)n * n + fpad;   // kz plane of a field buffer
+  const size_t cplane = (size_t)n * nh;         // x plane of C
   const int tid = threadIdx.x;
-  // rows fastest across the lanes of a wave: a column's transform stays inside one wave
+  // rows fastest across the lanes of a wave: a line's transform stays inside one wave
   const int t = tid % pt, c = tid / pt;
   double* h = hist + ((tid >> 6) % copies) * nvals;
   const LineRt rt{n, sched, nst, pt, n};
-  const TileWalk walk(n * tiles_x);
-  __syncthreads();  // histogram zeroed, thresholds and twiddles staged
-  auto base_of = [&](int tl) { return (size_t)(tl / tiles_x) * os + (size_t)(tl % tiles_x) * tile; };
-  // x planes of the field buffers are fpad elements further apart than those of C: the
-  // field rows (axis 0) or the field tiles' planes (axis 1)
-  const size_t frs = axis ? rs : rs + fpad;
-  auto fbase_of = [&](int tl) {
-    return axis ? (size_t)(tl / tiles_x) * (os + fpad) + (size_t)(tl % tiles_x) * tile : base_of(tl);
+  const TileWalk walk(n * kgroups);
+  // first element of this thread's line in a field buffer: kz = kz0 + c of x plane x
+  auto fline = [&](int tl) {
+    return (size_t)((tl % kgroups) * TP + c) * fplane + (size_t)(tl / kgroups) * n + t;
   };
   cx<T> nxt[E];
   int j = walk.first;
-  if (j < walk.end && nf > 0)
-    tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[0]]), fbase_of(walk.tile(j)), frs, tile, bs);
-  int parity = 0;
+  if (j < walk.end && nf > 0) {
+    const cx<T>* b0 = reinterpret_cast<const cx<T>*>(bufs[fields[0]]);
+    const size_t fb0 = fline(walk.tile(j));
+#pragma unroll
+    for (int e = 0; e < E; ++e) nxt[e] = gload<T>(b0, fb0 + pt * e);
+  }
   for (; j < walk.end; j += walk.step) {
     const int tl = walk.tile(j);
-    const int o = tl / tiles_x;  // the tile's fixed x (axis 1) or y (axis 0) index
-    const int kz = (tl % tiles_x) * tile + c;
-    const size_t base = base_of(tl);
-    const size_t fbase = fbase_of(tl);
-    const int fo = sfreq(o, n);
-    const bool onyq = (o == nh);
+    const int x = tl / kgroups, kz0 = (tl % kgroups) * TP;
+    const int kz = kz0 + c;
+    const size_t fb = fline(tl);
+    // C of the tile: TP consecutive kz per y row (coalesced), kept in LDS for the whole tile
+    __syncthreads();  // previous tile's reads of cst done; first tile: histograms, thresholds, twiddles staged
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int i = tid + q * bs;
+      const int y = tdiv(i, TP), cc = tmod(i, TP);
+      cst[cc * n + y] = gload<T>(cin, (size_t)x * cplane + (size_t)y * nh + kz0 + cc);
+    }
+    __syncthreads();
+    const int fx = sfreq(x, n);
+    const bool xnyq = (x == nh);
     // Hermitian weight; the spherical sum also carries the 4 pi of the addition theorem
     const double w4pi = ((kz == 0) ? 1.0 : 2.0) * (CART ? 1.0 : FOUR_PI);
-    // per element: k bin (-1 when the mode is excluded), C, unit wave vector
+    // per element: k bin (-1 when the mode is excluded) and unit wave vector
     int bin[E];
-    cx<T> cv[E];
     T ux[E], uy[E], uz[E];
     {
       int n2[E];
       bool excl[E];
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const int x = t + pt * e;  // row index along the transform axis
-        const int fr = sfreq(x, n);
-        n2[e] = fr * fr + fo * fo + kz * kz;
-        excl[e] = onyq || x == nh || n2[e] == 0;
-        cv[e] = gload<T>(cin, base + c + (size_t)x * rs);
+        const int y = t + pt * e;
+        const int fy = sfreq(y, n);
+        n2[e] = fx * fx + fy * fy + kz * kz;
+        excl[e] = xnyq || y == nh || n2[e] == 0;
         // wave vectors cover every direction, so their rounding is not correlated: the
         // rotation runs in the working precision
         const T ki = n2[e] > 0 ? T(1) / sqrt((T)n2[e]) : T(0);
-        const T vx = (T)(axis ? fo : fr) * ki, vy = (T)(axis ? fr : fo) * ki, vz = (T)kz * ki;
+        const T vx = (T)fx * ki, vy = (T)fy * ki, vz = (T)kz * ki;
         ux[e] = frm.at<T>(0) * vx + frm.at<T>(1) * vy + frm.at<T>(2) * vz;
         uy[e] = frm.at<T>(3) * vx + frm.at<T>(4) * vy + frm.at<T>(5) * vz;
         uz[e] = frm.at<T>(6) * vx + frm.at<T>(7) * vy + frm.at<T>(8) * vz;
@@ -602,18 +628,21 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
     YRun<T, E> yr;
     yrun_init(yr);
     for (int f = 0; f < nf; ++f) {
-      cx<T>* tb = lds + parity * tsz;
-      parity ^= 1;
-      tile_to_lds<T, E, XPAD>(tb, nxt, tile, pitch, bs);
-      // prefetch the next field's tile (or the next tile's first field) during this one
-      if (f + 1 < nf)
-        tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[4 * (f + 1)]]), fbase, frs, tile, bs);
-      else if (j + walk.step < walk.end)
-        tile_load<T, E>(nxt, reinterpret_cast<const cx<T>*>(bufs[fields[0]]), fbase_of(walk.tile(j + walk.step)),
-                        frs, tile, bs);
-      __syncthreads();
       cx<T> u[E];
-      xf_lds_in<T, E, false, XPAD, NC, WAVE>(tb, c, pitch, rt, t, u, twst, twl);
+#pragma unroll
+      for (int e = 0; e < E; ++e) u[e] = nxt[e];
+      // prefetch the next field's line (or the next tile's first field) during this one
+      if (f + 1 < nf) {
+        const cx<T>* bn = reinterpret_cast<const cx<T>*>(bufs[fields[4 * (f + 1)]]);
+#pragma unroll
+        for (int e = 0; e < E; ++e) nxt[e] = gload<T>(bn, fb + pt * e);
+      } else if (j + walk.step < walk.end) {
+        const cx<T>* bn = reinterpret_cast<const cx<T>*>(bufs[fields[0]]);
+        const size_t fbn = fline(walk.tile(j + walk.step));
+#pragma unroll
+        for (int e = 0; e < E; ++e) nxt[e] = gload<T>(bn, fbn + pt * e);
+      }
+      xf_regs<T, E, false, XPAD, NC, WAVE>(exch, c * lx, 1, rt, t, u, twst, twl);
       const int slot = fields[4 * f + 3];
       {
         T yv[E];
@@ -633,8 +662,9 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           if (bin[e] >= 0) {
-            const double q = odd ? (double)cv[e].y * (double)acc[e].x - (double)cv[e].x * (double)acc[e].y
-                                 : (double)cv[e].x * (double)acc[e].x + (double)cv[e].y * (double)acc[e].y;
+            const cx<T> cv = cst[c * n + t + pt * e];
+            const double q = odd ? (double)cv.y * (double)acc[e].x - (double)cv.x * (double)acc[e].y
+                                 : (double)cv.x * (double)acc[e].x + (double)cv.y * (double)acc[e].y;
             lds_atomic_add<double>(&hs[bin[e]], w4pi * q);
           }
           acc[e] = mk<T>(T(0), T(0));
@@ -646,12 +676,13 @@ __global__ void __launch_bounds__(XPOST_THREADS) k_xpost(int n_rt, int tile_rt, 
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         if (bin[e] < 0) continue;
-        const int fr = sfreq(t + pt * e, n);
-        const int n2 = fr * fr + fo * fo + kz * kz;
+        const int y = t + pt * e;
+        const int fy = sfreq(y, n);
+        const int n2 = fx * fx + fy * fy + kz * kz;
+        const cx<T> cv = cst[c * n + y];
         lds_atomic_add<double>(&h[bin[e]], w);
         lds_atomic_add<double>(&h[nb + bin[e]], w * kf * sqrt((double)n2));
-        lds_atomic_add<double>(&h[2 * nb + bin[e]],
-                               w * ((double)cv[e].x * (double)cv[e].x + (double)cv[e].y * (double)cv[e].y));
+        lds_atomic_add<double>(&h[2 * nb + bin[e]], w * ((double)cv.x * (double)cv.x + (double)cv.y * (double)cv.y));
       }
     }
   }
@@ -755,6 +786,10 @@ static int zthreads(const FftShape& fs) { return (fs.n / 2 / fs.e_z) * fs.zlines
 static size_t zsmem(const FftShape& fs, size_t cs) {
   return cs * ((size_t)fs.zlines * zpitch(fs.n / 2) + fs.n + fs.n / 2);
 }
+// the pre-pass keeps a second line region for the finished lines of a field
+static size_t zpresmem(const FftShape& fs, size_t cs) {
+  return cs * (2 * (size_t)fs.zlines * zpitch(fs.n / 2) + fs.n + fs.n / 2);
+}
 int xpass_threads(const FftShape& fs) { return (fs.n / fs.e_col) * fs.tile; }
 int xpass_blocks(const FftShape& fs) { return fs.n * ((fs.n / 2) / fs.tile); }
 // Persistent post-pass grid: two blocks per compute unit (the register budget allows no
@@ -765,13 +800,15 @@ int post_blocks(const FftShape& fs) {
   return std::min(tiles, 2 * cus);
 }
 static size_t colsmem(const FftShape& fs, size_t cs) { return cs * ((size_t)fs.n * (fs.tile + 1) + fs.n); }
-size_t zpass_smem_bytes(const FftShape& fs, bool fp64) { return zsmem(fs, fp64 ? sizeof(double2) : sizeof(float2)); }
+size_t zpass_smem_bytes(const FftShape& fs, bool fp64) {
+  return zpresmem(fs, fp64 ? sizeof(double2) : sizeof(float2));
+}
 size_t colpass_smem_bytes(const FftShape& fs, bool fp64) {
   return colsmem(fs, fp64 ? sizeof(double2) : sizeof(float2));
 }
 size_t xpost_base_bytes(const FftShape& fs, bool fp64) {
   const size_t cs = fp64 ? sizeof(double2) : sizeof(float2);
-  return cs * (2 * (size_t)xrows(fs.n) * (fs.tile_post + 1) + fs.n);
+  return cs * ((size_t)fs.tile_post * xrows(fs.n) + (size_t)fs.tile_post * fs.n + fs.n);
 }
 
 #define PKM_DISPATCH_E(EVAL, CALL)                  \
@@ -797,7 +834,9 @@ size_t xpost_base_bytes(const FftShape& fs, bool fp64) {
   PKM_TRY(64, 8, 64, fs.e_z, fs.zlines, CALL)  \
   PKM_TRY(128, 8, 32, fs.e_z, fs.zlines, CALL) \
   PKM_TRY(256, 8, 16, fs.e_z, fs.zlines, CALL) \
+  PKM_TRY(512, 8, 16, fs.e_z, fs.zlines, CALL) \
   PKM_TRY(512, 8, 8, fs.e_z, fs.zlines, CALL)  \
+  PKM_TRY(1024, 8, 8, fs.e_z, fs.zlines, CALL) \
   PKM_TRY(1024, 8, 4, fs.e_z, fs.zlines, CALL)
 
 #define PKM_TRY_COL(CALL)                         \
@@ -835,23 +874,34 @@ hipError_t launch_zfwd(const FftShape& fs, const T* in0, const T* in1, void* out
 template <typename T>
 hipError_t launch_col(const FftShape& fs, void* const* bufs_dev, int nbuf, int axis, bool inverse, const void* tw,
                       hipStream_t s, bool fields) {
-  const size_t nh = fs.n / 2;
-  const size_t plane = (size_t)fs.n * nh + (fields ? fs.fpad : 0);
-  const size_t row_stride = axis == 1 ? nh : plane;
-  const size_t outer_stride = axis == 1 ? plane : nh;
+  const size_t n = fs.n, nh = fs.n / 2;
+  // half spectra [x][y][kz]: rows along y (axis 1) or x (axis 0), tiles over kz;
+  // kz-major field buffers [kz][x][y]: rows along x within a kz plane, tiles over y
+  size_t row_stride, outer_stride;
+  int clen;
+  if (fields) {
+    row_stride = n;
+    outer_stride = n * n + fs.fpad;
+    clen = fs.n;
+  } else {
+    const size_t plane = n * nh;
+    row_stride = axis == 1 ? nh : plane;
+    outer_stride = axis == 1 ? plane : nh;
+    clen = fs.n / 2;
+  }
   dim3 grid(xpass_blocks(fs), nbuf);
   const size_t sm = colsmem(fs, sizeof(cx<T>));
   if (inverse) {
     PKM_TRY_COL((k_col<T, E, true, NC, TC><<<grid, xpass_threads(fs), sm, s>>>(
-        fs.n, fs.tile, fs.sched_col, fs.nst_col, bufs_dev, row_stride, outer_stride, (const cx<T>*)tw)));
+        fs.n, fs.tile, fs.sched_col, fs.nst_col, bufs_dev, row_stride, outer_stride, clen, (const cx<T>*)tw)));
     PKM_DISPATCH_E(fs.e_col, (k_col<T, E, true, 0, 0><<<grid, xpass_threads(fs), sm, s>>>(
-                                  fs.n, fs.tile, fs.sched_col, fs.nst_col, bufs_dev, row_stride, outer_stride,
+                                  fs.n, fs.tile, fs.sched_col, fs.nst_col, bufs_dev, row_stride, outer_stride, clen,
                                   (const cx<T>*)tw)));
   } else {
     PKM_TRY_COL((k_col<T, E, false, NC, TC><<<grid, xpass_threads(fs), sm, s>>>(
-        fs.n, fs.tile, fs.sched_col, fs.nst_col, bufs_dev, row_stride, outer_stride, (const cx<T>*)tw)));
+        fs.n, fs.tile, fs.sched_col, fs.nst_col, bufs_dev, row_stride, outer_stride, clen, (const cx<T>*)tw)));
     PKM_DISPATCH_E(fs.e_col, (k_col<T, E, false, 0, 0><<<grid, xpass_threads(fs), sm, s>>>(
-                                  fs.n, fs.tile, fs.sched_col, fs.nst_col, bufs_dev, row_stride, outer_stride,
+                                  fs.n, fs.tile, fs.sched_col, fs.nst_col, bufs_dev, row_stride, outer_stride, clen,
                                   (const cx<T>*)tw)));
   }
   return hipGetLastError();
@@ -876,7 +926,7 @@ hipError_t launch_zpre_basis(const FftShape& fs, const void* g_in, const T* real
                              void* const* bufs_dev, int nf, const int* fields_dev, double scale, const double* off,
                              double h, const void* ytab, const void* tw, const Frame& frame, hipStream_t s) {
   const int lines = fs.n * fs.n;
-  const size_t sm = zsmem(fs, sizeof(cx<T>));
+  const size_t sm = zpresmem(fs, sizeof(cx<T>));
   PKM_TRY_Z((k_zpre<T, E, NC, TC, CART><<<lines / fs.zlines, zthreads(fs), sm, s>>>(
       fs.n, fs.zlines, fs.sched_z, fs.nst_z, (const cx<T>*)g_in, real_in, real_out, bufs_dev, nf, fields_dev,
       (T)scale, off[0], off[1], off[2], h, (const T*)ytab, (const cx<T>*)tw, frame, fs.fpad)));
@@ -901,8 +951,7 @@ hipError_t launch_zpre(const FftShape& fs, const void* g_in, const T* real_in, T
 template <typename T, bool CART>
 hipError_t launch_xpost_basis(const FftShape& fs, void* const* bufs_dev, int nf, const int* fields_dev, int nslots,
                               int with_l0, const void* c_in, const void* ytab, const BinSpec& bs, double kf,
-                              double* partial, int* nblocks_out, const void* tw, int axis, const Frame& frame,
-                              hipStream_t s) {
+                              double* partial, int* nblocks_out, const void* tw, const Frame& frame, hipStream_t s) {
   if (nslots < 0) return hipErrorInvalidValue;
   const int rows = (with_l0 ? 3 : 0) + nslots;
   const size_t sm = xpost_base_bytes(fs, sizeof(T) == 8) + sizeof(double) * (size_t)bs.hist_copies * rows * bs.nb +
@@ -913,25 +962,25 @@ hipError_t launch_xpost_basis(const FftShape& fs, void* const* bufs_dev, int nf,
   *nblocks_out = nblk;
   PKM_TRY_POST((k_xpost<T, E, NC, TC, CART><<<nblk, nthr, sm, s>>>(
       fs.n, fs.tile_post, fs.sched_post, fs.nst_post, bufs_dev, nf, fields_dev, nslots, with_l0, kf,
-      (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies, partial, (const cx<T>*)tw, axis, frame,
+      (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies, partial, (const cx<T>*)tw, frame,
       fs.fpad)));
   PKM_DISPATCH_E(fs.e_post, (k_xpost<T, E, 0, 0, CART><<<nblk, nthr, sm, s>>>(
                                 fs.n, fs.tile_post, fs.sched_post, fs.nst_post, bufs_dev, nf, fields_dev, nslots,
                                 with_l0, kf, (const cx<T>*)c_in, (const T*)ytab, bs.thr, bs.nb, bs.hist_copies,
-                                partial, (const cx<T>*)tw, axis, frame, fs.fpad)));
+                                partial, (const cx<T>*)tw, frame, fs.fpad)));
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_xpost(const FftShape& fs, void* const* bufs_dev, int nf, const int* fields_dev, int nslots,
                         int with_l0, const void* c_in, const void* ytab, const BinSpec& bs, double kf,
-                        double* partial, int* nblocks_out, const void* tw, int axis, const Frame& frame, int basis,
+                        double* partial, int* nblocks_out, const void* tw, const Frame& frame, int basis,
                         hipStream_t s) {
   if (basis == 1)
     return launch_xpost_basis<T, true>(fs, bufs_dev, nf, fields_dev, nslots, with_l0, c_in, ytab, bs, kf, partial,
-                                       nblocks_out, tw, axis, frame, s);
+                                       nblocks_out, tw, frame, s);
   return launch_xpost_basis<T, false>(fs, bufs_dev, nf, fields_dev, nslots, with_l0, c_in, ytab, bs, kf, partial,
-                                      nblocks_out, tw, axis, frame, s);
+                                      nblocks_out, tw, frame, s);
 }
 
 hipError_t launch_reduce(const double* partial, int nblocks, int nvals, double* out, const int* map, int accumulate,
@@ -968,7 +1017,7 @@ hipError_t launch_kmu_finish(const double* sums, int ncells, double norm_I, doub
                                      double, const double*, double, const void*, const void*, const Frame&, int,   \
                                      hipStream_t);                                                                 \
   template hipError_t launch_xpost<T>(const FftShape&, void* const*, int, const int*, int, int, const void*,     \
-                                      const void*, const BinSpec&, double, double*, int*, const void*, int,      \
+                                      const void*, const BinSpec&, double, double*, int*, const void*,           \
                                       const Frame&, int, hipStream_t);                                           \
   template hipError_t launch_kmu<T>(const FftShape&, const void*, const double*, const BinSpec&, const double*,   \
                                     int, double*, int, hipStream_t);

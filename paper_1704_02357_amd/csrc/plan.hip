@@ -346,8 +346,10 @@ std::vector<double> legendre_coeffs(int l) {
   return b;
 }
 
-// Bytes of one field buffer: n x planes of n n/2 + fpad complex values.
-size_t field_bytes(const pkm_plan* pl) { return pl->mesh_bytes + (size_t)pl->p.nmesh * pl->fs.fpad * 2 * pl->es; }
+// Bytes of one kz-major field buffer [kz][x][y]: n/2 kz planes of n n + fpad complex values.
+size_t field_bytes(const pkm_plan* pl) {
+  return pl->mesh_bytes + (size_t)(pl->p.nmesh / 2) * pl->fs.fpad * 2 * pl->es;
+}
 
 void ensure_fields(pkm_plan* pl, int want) {
   while ((int)pl->fields.size() < want) pl->fields.push_back(dalloc(pl, field_bytes(pl)));
@@ -722,7 +724,6 @@ template <typename T> void enqueue_compute(pkm_plan* pl) {
                          pl->p.box_origin[2] - pl->p.observer[2]};
   const double h = pl->p.box_len / n;
   const double dc_scale = 2.0 / ((double)n * n * n);
-  const int post_axis = pl->fs.post_axis;
   for (size_t gi = 0; gi < cc.groups.size(); ++gi) {
     const GroupCfg& gc = cc.groups[gi];
     const int* ft = pl->ftab_dev + 4 * gc.fofs;
@@ -734,19 +735,17 @@ template <typename T> void enqueue_compute(pkm_plan* pl) {
                                      gc.nf, ft, dc_scale, off, h, pl->ytab, pl->tw, pl->frame, cc.basis, s),
                   "zpre");
       }
-      // the column pass takes the axis the post-pass does not: FP64 fields take their x pass
-      // here and their y pass in the post-pass (whose rows are then nh, not n nh, elements
-      // apart: measured faster for FP64, slower for FP32)
+      // kz-major fields: the column pass runs along x within each kz plane, the post-pass
+      // along the contiguous y lines
       StageScope ss(pl, PKM_STAGE_YCOL);
-      check_hip(pl, launch_col<T>(pl->fs, pl->ptrs_dev, gc.nf, post_axis == 1 ? 0 : 1, false, pl->tw, s, true),
-                "field column pass");
+      check_hip(pl, launch_col<T>(pl->fs, pl->ptrs_dev, gc.nf, 0, false, pl->tw, s, true), "field column pass");
     }
     int nblocks = 0;
     {
       StageScope ss(pl, PKM_STAGE_XPOST);
       check_hip(pl, launch_xpost<T>(pl->fs, pl->ptrs_dev, gc.nf, ftp, gc.nslots, gi == 0 ? 1 : 0, pl->c, pl->ytab,
                                     BinSpec{pl->thr_dev, cc.nb, gc.copies}, (double)(2.0 * M_PI / pl->p.box_len),
-                                    pl->partial, &nblocks, pl->tw, post_axis, pl->frame, cc.basis, s),
+                                    pl->partial, &nblocks, pl->tw, pl->frame, cc.basis, s),
                 "post-pass");
     }
     StageScope ss(pl, PKM_STAGE_REDUCE);
@@ -1000,11 +999,10 @@ template <typename T> void read_dc(pkm_plan* pl, void* host, size_t bytes) {
 }
 
 // Launch shape of the transform passes for one mesh size and precision.
-// Field buffers get x planes of n n/2 complex values plus 256 bytes (32 FP32 or 16 FP64
-// values): with the plain power-of-two plane stride, the passes that step from plane to
-// plane (the FP32 post-pass, the FP64 column pass) fall on few HBM channels.  Measured at
-// 512^3: 256 bytes best in both precisions; 512 bytes close in FP32 and slower in FP64;
-// 1 and 2 KB slower than none in FP32.
+// Field buffers are kz-major, [kz][x][y], with kz planes of n n complex values plus 256
+// bytes (32 FP32 or 16 FP64 values): the column pass steps from row to row within a plane and
+// the pre-pass writes across planes; a plain power-of-two plane stride puts those accesses on
+// few HBM channels.
 int field_pad(bool fp64) { return fp64 ? 16 : 32; }
 
 bool make_shape(const pkm_params& p, FftShape* out) {
@@ -1045,12 +1043,19 @@ bool make_shape(const pkm_params& p, FftShape* out) {
     while (tp > 1 && (n / 2) % tp) tp /= 2;
     fs.tile_post = tp;
   }
+  // z lines per block: a power of two dividing n (a block's lines share one x plane, and the
+  // pre-pass writes them as runs of consecutive y into the kz-major field buffers)
   const int pt_z = (n / 2) / fs.e_z;
-  int zl = 1;
-  while (zl * 2 * pt_z <= 256 && ((size_t)n * n) % (zl * 2) == 0) zl *= 2;
-  fs.zlines = zl;
-  // FP64 fields finish along y (rows nh apart): measured faster; FP32 along x
-  fs.post_axis = fp64 ? 1 : 0;
+  // At most 256 threads per block, or 512 for FP32 from N = 512 up (16 lines of 512: the
+  // pre-pass then writes 128-byte runs, measured faster than the 64-byte runs of 8 lines).
+  const int zmax = (fp64 || n < 512) ? 256 : 512;
+  fs.zlines = 1;
+  for (;;) {
+    FftShape next = fs;
+    next.zlines = fs.zlines * 2;
+    if (next.zlines * pt_z > zmax || n % next.zlines || zpass_smem_bytes(next, fp64) > 160 * 1024) break;
+    fs = next;
+  }
   fs.fpad = field_pad(fp64);
   *out = fs;
   return true;
@@ -1076,7 +1081,7 @@ bool apply_shape(const pkm_params& p, const pkm_shape& sh, FftShape* fs, int* ts
     f.e_z = sh.e_z;
   }
   if (sh.zlines) f.zlines = sh.zlines;
-  if (f.zlines < 1 || ((size_t)n * n) % f.zlines || (nh / f.e_z) * f.zlines > 256 ||
+  if (f.zlines < 1 || n % f.zlines || (nh / f.e_z) * f.zlines > (fp64 ? 256 : 512) ||
       zpass_smem_bytes(f, fp64) > 160 * 1024)
     return fail("z-pass lines break a kernel limit");
   if (sh.e_post) {
@@ -1087,10 +1092,8 @@ bool apply_shape(const pkm_params& p, const pkm_shape& sh, FftShape* fs, int* ts
   if (f.tile_post < 1 || nh % f.tile_post || (n / f.e_post) * f.tile_post > 256 ||
       xpost_base_bytes(f, fp64) > 150 * 1024)
     return fail("post-pass tile breaks a kernel limit");
-  if (sh.post_axis) {
-    if (sh.post_axis != 1 && sh.post_axis != 2) return fail("post_axis must be 1 (x) or 2 (y)");
-    f.post_axis = sh.post_axis - 1;
-  }
+  if (sh.post_axis && sh.post_axis != 2)
+    return fail("post_axis must be 0 or 2: the post-pass runs along y over kz-major field buffers");
   if (sh.paint_tile) {
     if ((sh.paint_tile != 4 && sh.paint_tile != 8 && sh.paint_tile != 16) || n % sh.paint_tile)
       return fail("paint_tile must be 4, 8 or 16 and divide nmesh");
@@ -1109,7 +1112,7 @@ pkm_shape shape_of(const FftShape& fs, int ts) {
   sh.e_post = fs.e_post;
   sh.tile_post = fs.tile_post;
   sh.paint_tile = ts;
-  sh.post_axis = fs.post_axis + 1;
+  sh.post_axis = 2;  // y
   return sh;
 }
 
@@ -1304,7 +1307,7 @@ int64_t footprint(const pkm_params* p, int ell_max, int n_edges, int64_t n_parti
   if (p->max_group > 0) nf = std::min(nf, p->max_group);
   nf = std::max(nf, 1);
   const int64_t meshes = (p->interlaced ? 6 : 4) + nf;
-  const int64_t pads = (int64_t)nf * n * fs.fpad * 2 * (p->precision == PKM_FP64 ? 8 : 4);
+  const int64_t pads = (int64_t)nf * (n / 2) * fs.fpad * 2 * (p->precision == PKM_FP64 ? 8 : 4);
   const int64_t nb = std::max(1, n_edges - 1);
   const int64_t partial = (int64_t)post_blocks(fs) * (3 + ell_max / 2) * nb * 8;
   const int64_t ts = 8;
@@ -1671,7 +1674,7 @@ pkm_status pkm_autotune(const pkm_params* p, const pkm_device* dev, int32_t ell_
     std::vector<pkm_shape> c;
     for (int e : {4, 8, 16})
       for (int zl = 1; zl <= 64; zl *= 2) {
-        if ((nh / e) * zl > 256 || (nh / e) * zl < 64) continue;
+        if ((nh / e) * zl > (p->precision == PKM_FP64 ? 256 : 512) || (nh / e) * zl < 64) continue;
         pkm_shape s2 = cur; s2.e_z = e; s2.zlines = zl; c.push_back(s2);
       }
     tune(c, {PKM_STAGE_ZFWD, PKM_STAGE_ZPRE});
@@ -1688,11 +1691,10 @@ pkm_status pkm_autotune(const pkm_params* p, const pkm_device* dev, int32_t ell_
   {
     std::vector<pkm_shape> c;
     for (int e : {4, 8})
-      for (int tl : {1, 2, 4, 8, 16})
-        for (int ax : {1, 2}) {
-          if ((n / e) * tl > 256 || (n / e) * tl < 64) continue;
-          pkm_shape s2 = cur; s2.e_post = e; s2.tile_post = tl; s2.post_axis = ax; c.push_back(s2);
-        }
+      for (int tl : {1, 2, 4, 8, 16}) {
+        if ((n / e) * tl > 256 || (n / e) * tl < 64) continue;
+        pkm_shape s2 = cur; s2.e_post = e; s2.tile_post = tl; c.push_back(s2);
+      }
     tune(c, {PKM_STAGE_YCOL, PKM_STAGE_XPOST});
   }
   double m[PKM_NSTAGES];

@@ -1,8 +1,8 @@
 """GPU tests of the asynchronous estimate, the batch runtime (uneven mock sizes, HIP graph
 capture and replay) and the serving loop (mixed requests admitted while others run).
 
-Every batched or served result is compared with the same estimate run alone through the
-synchronous calls, to the precision form's tolerance."""
+Every batched or served result is compared with the FP64 oracle and with the same estimate
+run alone through the synchronous calls, each to the precision form's tolerance."""
 from __future__ import annotations
 
 import math
@@ -55,6 +55,12 @@ def _alone(n, prec, lmax, d, r, **kw):
     out = p.compute_multipoles(lmax, _edges(n))
     p.close()
     return out
+
+
+def _oracle(n, lmax, d, r):
+    from oracle.estimator import multipoles
+    from tests.parity_util import oracle_params
+    return multipoles(d, r, oracle_params(n, L, OBS, 3, True, True), lmax, _edges(n))
 
 
 def _dev(cat):
@@ -197,16 +203,20 @@ def test_batch_uneven_mocks_graph_replays(gpu):
         dd, rr = _dev(d), _dev(r)
         dev.append((dd, rr))
         b.add(plans[(n, i % 2)], dd, rr)
+    from tests.parity_util import assert_pole_parity
     refs = [_alone(n, prec, lmax, *mocks[i]) for i, n in enumerate(sizes)]
+    orcs = [_oracle(n, lmax, *mocks[i]) for i, n in enumerate(sizes)]
     ms = b.run(use_graph=False)
     print(f"[batch] direct {ms:.2f} ms", flush=True)
     for i in range(6):
         _same(b.result(i), refs[i], prec, f"direct item {i}")
+        assert_pole_parity(b.result(i), orcs[i], prec, f"direct item {i} vs oracle")
     for rep in range(3):
         ms = b.run(use_graph=True)
         print(f"[batch] graph replay {rep} {ms:.2f} ms", flush=True)
         for i in range(6):
             _same(b.result(i), refs[i], prec, f"graph replay {rep} item {i}")
+            assert_pole_parity(b.result(i), orcs[i], prec, f"graph replay {rep} item {i} vs oracle")
         # eager work and synchronisation between replays
         x = torch.randn(1 << 20, device="cuda")
         torch.cuda.synchronize()
@@ -248,8 +258,10 @@ def test_server_mixed_stream_matches_alone(gpu):
     assert st["completed"] == len(reqs) and st["failed"] == 0
     assert st["max_concurrent"] >= 2
     assert st["resident_plans"] >= 3
+    from tests.parity_util import assert_pole_parity
     for (n, lmax, prec, d, r), g in zip(reqs, got):
         _same(g, _alone(n, prec, lmax, d, r), prec, f"server n={n} l={lmax} prec={prec} randoms={r is not None}")
+        assert_pole_parity(g, _oracle(n, lmax, d, r), prec, f"server n={n} l={lmax} prec={prec} vs oracle")
     sv.close()
 
 
@@ -279,10 +291,10 @@ def test_server_budget_admission(gpu):
 
 SHAPES = {  # per mesh size: power-of-two and 3-smooth schedules
     64: [dict(e_col=4, tile=4, e_z=4, zlines=4, e_post=4, tile_post=2, paint_tile=4, post_axis=2),
-         dict(e_col=8, tile=8, e_z=8, zlines=2, e_post=8, tile_post=4, paint_tile=16, post_axis=1),
+         dict(e_col=8, tile=8, e_z=8, zlines=2, e_post=8, tile_post=4, paint_tile=16),
          dict(e_col=16, tile=2, e_post=4, tile_post=8, post_axis=2)],
     48: [dict(e_col=12, tile=4, e_z=6, zlines=8, e_post=6, tile_post=4, paint_tile=8, post_axis=2),
-         dict(e_col=6, tile=8, e_z=12, zlines=2, e_post=12, tile_post=2, paint_tile=4, post_axis=1),
+         dict(e_col=6, tile=8, e_z=12, zlines=2, e_post=12, tile_post=2, paint_tile=4),
          dict(e_col=6, tile=2, e_z=6, zlines=16, e_post=6, tile_post=8, post_axis=2)],
 }
 
@@ -299,11 +311,19 @@ def test_shaped_plan_matches_oracle(gpu, prec, n, si):
     d, r = small_catalogs(3000, 20000, L, seed=400 + si)
     p = _plan(n, prec, 4, shape=shape)
     print(f"[shape] n={n} prec={prec} {p.shape()}", flush=True)
+    assert p.shape()["post_axis"] == 2
     p.paint(d, r)
     got = p.compute_multipoles(4, _edges(n))
     ref = multipoles(d, r, oracle_params(n, L, OBS, 3, True, True), 4, _edges(n))
     assert_pole_parity(got, ref, prec, f"shape {si} n={n}")
     p.close()
+
+
+def test_retired_post_axis_rejected(gpu):
+    """The post-pass runs along y over kz-major field buffers: post_axis 1 (x) is refused."""
+    from paper_1704_02357_amd import PkmError
+    with pytest.raises(PkmError):
+        _plan(64, 0, 4, shape=dict(post_axis=1))
 
 
 def test_autotune_picks_valid_shape_and_caches(gpu, tmp_path):
