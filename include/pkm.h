@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define PKM_ABI_VERSION 3
+#define PKM_ABI_VERSION 4
 
 typedef enum {
   PKM_OK = 0,
@@ -198,6 +198,12 @@ pkm_status pkm_plan_create(const pkm_params* p, const pkm_device* dev, pkm_plan*
 pkm_status pkm_plan_create_shaped(const pkm_params* p, const pkm_device* dev, const pkm_shape* shape,
                                   pkm_plan** out);
 pkm_status pkm_plan_shape(const pkm_plan* plan, pkm_shape* out);
+
+/* Device bytes a plan with these parameters would hold for one estimate of ell_max over
+ * n_edges k edges with n_particles objects (meshes, weighted fields, particle sort buffers,
+ * partial sums; an upper estimate, the figure the serving loop admits requests by).  Host
+ * only; -1 when the parameters are invalid.                                                 */
+int64_t pkm_plan_footprint(const pkm_params* p, int32_t ell_max, int32_t n_edges, int64_t n_particles);
 
 /* Autotuner: times candidate launch shapes on a seeded synthetic catalog of n_particles
  * objects (1/21 data, 20/21 randoms, uniform in the box) for estimates up to ell_max, one
@@ -385,14 +391,27 @@ const char* pkm_batch_last_error(const pkm_batch* batch);
 void pkm_batch_destroy(pkm_batch* batch);
 
 /* ---------------------------------------------------------------------------------------
- * Serving: a request loop on one device.  Requests (mesh parameters, ell_max, k edges and
- * host catalogs, copied at submit) are admitted in arrival order as soon as fewer than
- * max_inflight estimates run and the device bytes of resident plans plus the request's
- * footprint fit hbm_budget_bytes (idle plans are evicted least recently used first; a
- * request that cannot fit even alone fails with PKM_ENOMEM).  Admitted requests run on
- * separate streams and overlap on the device; plans (meshes, tables, staging) stay resident
- * and are reused by later requests with the same mesh, box, observer, window and precision.
- * Results are computed exactly as by pkm_paint + pkm_compute_multipoles.
+ * Serving: a request loop on one device.  A request names mesh parameters, ell_max, k edges
+ * and its catalogs: host arrays copied at submit, or a catalog registered with the server
+ * (device copies that stay resident until unregistered).  Requests are admitted from the first
+ * 8 queued ones in arrival order: the first whose footprint fits hbm_budget_bytes (idle plans
+ * evicted least recently used first) while fewer than max_inflight estimates run, so a request
+ * blocked on memory does not hold back smaller ones behind it; once the oldest request has been
+ * passed 16 times, nothing else is admitted before it.  A request that cannot fit even with no
+ * plan resident fails with PKM_ENOMEM.  Admitted requests run on separate streams and overlap
+ * on the device; plans (meshes, tables, staging) stay resident and are reused by later requests
+ * with the same mesh, box, observer, window, precision and max_group.  A plan keeps the painted
+ * field of the registered catalog it served last: a later request for that catalog on that plan
+ * skips the paint and the catalog copy and computes the multipoles of the field it holds (Sec.
+ * 2.1: every F_l is built from the one painted field by 2l+1 transforms).  Results are computed exactly as by
+ * pkm_paint + pkm_compute_multipoles.  Plan memory comes from the device's stream-ordered pool
+ * (hipMallocAsync/hipFreeAsync on the plan's stream).
+ *   pkm_server_register_catalog   copies data (and randoms, NULL for none) to the device and
+ *                      returns an id > 0 (PKM_EINVAL as pkm_check_catalogs; PKM_ENOMEM when
+ *                      it does not fit the budget next to the running plans).  Its bytes
+ *                      count in resident_bytes until it is unregistered.
+ *   pkm_server_unregister_catalog frees it; PKM_EBUSY while queued or running requests name
+ *                      it, PKM_EINVAL for an unknown id.  Ids are never reused.
  *   pkm_server_submit  queues a request and returns its ticket (PKM_EINVAL on bad input).
  *   pkm_server_poll    PKM_EBUSY until the request has finished, then copies the result
  *                      into `out` (arrays sized as for pkm_compute_multipoles) once.  A
@@ -400,24 +419,34 @@ void pkm_batch_destroy(pkm_batch* batch);
  *   pkm_server_wait    blocks until then.
  *   pkm_server_stats   completed / failed / queued / in-flight counts, resident and peak
  *                      device bytes, the largest number of concurrent estimates seen,
- *                      latency percentiles (submit to completion, ms) and throughput.
- *   pkm_server_destroy finishes the requests in flight, cancels queued ones, frees all.
+ *                      latency percentiles (submit to completion, ms) over all requests and
+ *                      per precision, throughput, requests served from a held painted field,
+ *                      registered catalogs and their bytes.
+ *   pkm_server_destroy finishes the requests in flight, cancels queued ones, frees all
+ *                      (registered catalogs included).
  * The server functions are thread safe.
  * ------------------------------------------------------------------------------------- */
 typedef struct {
   int32_t device_id;
   int64_t hbm_budget_bytes;  /* admission budget; <= 0 selects 80% of the free memory */
   int32_t max_inflight;      /* concurrent estimates, 1..32 */
+  /* Device allocations of plans and catalog buffers (not of registered catalogs), as in
+   * pkm_device, called on the worker thread with the plan's stream.  Both NULL selects the
+   * stream-ordered pool; a NULL return fails that request alone with PKM_ENOMEM. */
+  void* (*alloc)(size_t bytes, void* stream, void* ctx);
+  void (*free)(void* ptr, void* stream, void* ctx);
+  void* alloc_ctx;
 } pkm_server_config;
 
 typedef struct {
   pkm_params params;         /* ell_max_hint and max_group are taken from here */
-  int32_t ell_max;
+  int32_t ell_max;           /* even, 0..16 */
   const double* k_edges;
   int32_t n_edges;
-  pkm_catalog data;          /* host arrays (on_device = 0) */
+  pkm_catalog data;          /* host arrays (on_device = 0); ignored when catalog_id != 0 */
   pkm_catalog randoms;       /* host arrays, used when has_randoms = 1 (nbar required) */
-  int32_t has_randoms;
+  int32_t has_randoms;       /* ignored when catalog_id != 0 */
+  uint64_t catalog_id;       /* a registered catalog, or 0 for the host catalogs above */
 } pkm_request;
 
 typedef struct {
@@ -426,10 +455,17 @@ typedef struct {
   int32_t max_concurrent;
   double latency_p50_ms, latency_p99_ms, latency_mean_ms;
   double throughput_per_s;   /* completed requests / (last completion - first submit) */
+  int64_t completed_fp32, completed_fp64;
+  double latency_p50_ms_fp32, latency_p99_ms_fp32, latency_p50_ms_fp64, latency_p99_ms_fp64;
+  int64_t mesh_reuses;       /* requests served from a painted field their plan held */
+  int64_t registered_catalogs, registered_bytes;
 } pkm_server_stats_t;
 
 typedef struct pkm_server pkm_server;
 pkm_status pkm_server_create(const pkm_server_config* cfg, pkm_server** out);
+pkm_status pkm_server_register_catalog(pkm_server* server, const pkm_catalog* data, const pkm_catalog* randoms,
+                                       uint64_t* catalog_id);
+pkm_status pkm_server_unregister_catalog(pkm_server* server, uint64_t catalog_id);
 pkm_status pkm_server_submit(pkm_server* server, const pkm_request* request, int64_t* ticket);
 pkm_status pkm_server_poll(pkm_server* server, int64_t ticket, pkm_result* out);
 pkm_status pkm_server_wait(pkm_server* server, int64_t ticket, pkm_result* out);

@@ -6,5 +6,5 @@ this package only marshals arguments (``pkm.py``) and builds the library (``buil
 """
 from .pkm import (  # noqa: F401
     ABI_VERSION, CIC, NGP, TSC, FP32, FP64, SPHERICAL, CARTESIAN, Batch, Plan, PkmError, Server, autotune, lib_path, load_library,
-    kaiser_wedge_gamma, nonuniform_mu_edges, wedges,
+    kaiser_wedge_gamma, nonuniform_mu_edges, plan_footprint, wedges,
 )

@@ -26,6 +26,10 @@ std::string& error_of(pkm_plan* pl);
 // `timed`: record the plan's per-launch timing events when stage timing is on (never inside
 // a graph capture).
 pkm_status enqueue(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* randoms, double* slot, bool timed);
+// Multipoles only, of the painted field the plan holds from its last estimate (the same
+// catalog, mesh and precision), for the prepared request; the slot gets that estimate's
+// catalog sums again.  No allocation, no host wait.
+pkm_status enqueue_compute_only(pkm_plan* pl, double* slot);
 // Normalise a completed slot into `out` (the prepared ell_max and edges).  PKM_EINVAL
 // (reason in *why, `out` untouched) when the normalisation I is not positive.
 pkm_status finish(pkm_plan* pl, const double* slot, int64_t nd, int64_t nr, pkm_result* out, std::string* why);

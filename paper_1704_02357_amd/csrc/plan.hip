@@ -826,6 +826,17 @@ template <typename T> void enqueue_estimate(pkm_plan* pl, const DevCats& dc, dou
             "download bins");
 }
 
+// Multipoles of the painted field the plan already holds (its last paint or estimate), for the
+// prepared request, with that paint's catalog sums copied again: the same slot layout as
+// enqueue_estimate.  Allocates nothing and does not wait.
+template <typename T> void enqueue_compute_copy(pkm_plan* pl, double* slot) {
+  hipStream_t s = pl->stream;
+  enqueue_compute<T>(pl);
+  check_hip(pl, hipMemcpyAsync(slot, pl->sums_dev, 4 * sizeof(double), hipMemcpyDeviceToHost, s), "download sums");
+  check_hip(pl, hipMemcpyAsync(slot + 4, pl->out_dev, sizeof(double) * pl->cc.total_vals, hipMemcpyDeviceToHost, s),
+            "download bins");
+}
+
 // PKM_EINVAL, with `out` untouched, when the normalisation has no value.
 pkm_status finish_from_slot(const pkm_plan* pl, const double* slot, int64_t nd, int64_t nr, pkm_result* out) {
   double alpha, norm_I, shot;
@@ -1292,6 +1303,20 @@ pkm_status enqueue(pkm_plan* pl, const pkm_catalog* data, const pkm_catalog* ran
   return st;
 }
 
+pkm_status enqueue_compute_only(pkm_plan* pl, double* slot) {
+  if (!prepared(pl)) {
+    pl->err = "plan not prepared for this request";
+    return PKM_EORDER;
+  }
+  const bool timing = pl->stage_timing;
+  pl->stage_timing = false;
+  pkm_status st = guarded(pl, [&] {
+    if (pl->fp64) enqueue_compute_copy<double>(pl, slot); else enqueue_compute_copy<float>(pl, slot);
+  });
+  pl->stage_timing = timing;
+  return st;
+}
+
 pkm_status finish(pkm_plan* pl, const double* slot, int64_t nd, int64_t nr, pkm_result* out, std::string* why) {
   const pkm_status st = finish_from_slot(pl, slot, nd, nr, out);
   if (st != PKM_OK) *why = ZERO_NORM;
@@ -1323,6 +1348,13 @@ int64_t footprint(const pkm_params* p, int ell_max, int n_edges, int64_t n_parti
 extern "C" {
 
 int pkm_abi_version(void) { return PKM_ABI_VERSION; }
+
+int64_t pkm_plan_footprint(const pkm_params* p, int32_t ell_max, int32_t n_edges, int64_t n_particles) {
+  if (!p || ell_max < 0 || ell_max > 16 || n_edges < 2 || n_particles < 0) return -1;
+  std::string why;
+  if (validate_params(p, &why) != PKM_OK) return -1;
+  return pkm_internal::footprint(p, ell_max, n_edges, n_particles);
+}
 
 pkm_status pkm_check_catalogs(const pkm_catalog* data, const pkm_catalog* randoms) {
   std::string why;

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -272,6 +273,8 @@ void pkm_batch_destroy(pkm_batch* b) {
 namespace {
 
 using Clock = std::chrono::steady_clock;
+constexpr size_t ADMIT_WINDOW = 8;  // queued requests considered for admission, in arrival order
+constexpr int MAX_PASSES = 16;      // times the oldest request may be passed before others wait for it
 
 // Plans are interchangeable when these parameters agree (l_max only sizes the buffers).
 struct PlanKey {
@@ -295,21 +298,49 @@ PlanKey key_of(const pkm_params& p) {
   k.p.max_group = p.max_group;
   return k;  // ell_max_hint excluded: a slot serves any l_max up to its own hint
 }
+bool same_key(const PlanKey& a, const PlanKey& b) { return !(a < b) && !(b < a); }
 
-// One resident plan with its stream and grow-only staging buffers (device frees and pinned
-// host frees synchronise the device, so they are avoided on the request path).
+// Device memory of the serving loop comes from the device's stream-ordered pool: frees are
+// ordered on the slot's stream and do not synchronise the device, so evicting a plan or growing
+// a catalog buffer does not wait for the estimates in flight on other streams.  An allocation
+// waits for its own stream only (idle when a plan is created or grown), so the memory is ready
+// for the plan's table uploads, which are not ordered on that stream.
+void* pool_alloc(size_t bytes, void* stream, void*) {
+  void* p = nullptr;
+  if (hipMallocAsync(&p, bytes, (hipStream_t)stream) != hipSuccess ||
+      hipStreamSynchronize((hipStream_t)stream) != hipSuccess) {
+    (void)hipGetLastError();
+    if (p) (void)hipFreeAsync(p, (hipStream_t)stream);
+    return nullptr;
+  }
+  return p;
+}
+void pool_free(void* p, void* stream, void*) { (void)hipFreeAsync(p, (hipStream_t)stream); }
+
+// A catalog registered with the server: device copies of data (and randoms), resident until
+// unregistered.
+struct RegCat {
+  double* dev = nullptr;  // pos, w, nbar of data then of randoms
+  int64_t nd = 0, nr = 0;
+  bool has_rand = false, dw = false, dn = false, rw = false;
+  int64_t bytes = 0;
+  int refs = 0;           // queued or running requests that name it
+};
+
+// One resident plan with its stream and grow-only staging buffers.
 struct Slot {
   pkm_plan* plan = nullptr;
   hipStream_t stream = nullptr;
   PlanKey key;
-  int hint = 0;            // largest l_max the plan's field buffers were sized for
-  int64_t bytes = 0;       // plan bytes + catalog buffer
+  int hint = 0;              // largest l_max the plan's field buffers were sized for
+  int64_t bytes = 0;         // plan bytes + catalog buffer, as counted in the server's resident bytes
   bool busy = false;
+  uint64_t painted_cat = 0;  // registered catalog whose painted field the plan holds (0: none)
   Clock::time_point last_used;
-  PinnedBuf stage;         // host catalog staging
-  PinnedBuf result;        // bin sums of the estimate in flight
+  std::unique_ptr<PinnedBuf> stage;   // host catalog staging
+  std::unique_ptr<PinnedBuf> result;  // bin sums of the estimate in flight
   double* dev_cat = nullptr;
-  size_t dev_cap = 0;      // doubles
+  size_t dev_cap = 0;        // doubles
 };
 
 struct Request {
@@ -319,9 +350,12 @@ struct Request {
   std::vector<double> edges;
   int64_t nd = 0, nr = 0;
   bool has_rand = false;
-  std::vector<double> host_cat;  // pos, w, nbar of data then randoms (copied at submit)
+  uint64_t cat_id = 0;           // registered catalog, or 0: host catalogs copied at submit
+  std::vector<double> host_cat;  // pos, w, nbar of data then randoms
   bool dw = false, dn = false, rw = false;
-  int64_t need = 0;
+  int64_t need = 0;              // footprint of a new plan for this request (catalog excluded)
+  int passed = 0;                // later requests admitted while this one waited
+  bool reused_mesh = false;      // served from the painted field its slot already held
   Slot* slot_plan = nullptr;
   hipEvent_t done = nullptr;
   Clock::time_point t_submit, t_done;
@@ -344,11 +378,15 @@ struct pkm_server {
   std::vector<std::shared_ptr<Request>> inflight;
   std::unordered_map<int64_t, std::shared_ptr<Request>> finished;
   std::vector<std::unique_ptr<Slot>> slots;
+  std::vector<std::unique_ptr<PinnedBuf>> spare_pinned;  // pinned buffers of evicted slots
+  std::unordered_map<uint64_t, RegCat> cats;
+  uint64_t next_cat = 1;
   int64_t next_ticket = 1;
-  int64_t resident = 0, peak_resident = 0;
+  int64_t resident = 0, peak_resident = 0;  // plans, their catalog buffers and registered catalogs
+  int64_t cat_bytes = 0;                    // of which registered catalogs
   int max_concurrent = 0;
-  std::vector<double> latencies_ms;
-  int64_t completed = 0, failed = 0;
+  std::vector<double> latencies_ms, latencies_prec[2];
+  int64_t completed = 0, failed = 0, mesh_reuses = 0;
   Clock::time_point t_first_submit, t_last_done;
   bool any_submit = false;
   bool stop = false;
@@ -358,39 +396,60 @@ struct pkm_server {
 
 namespace {
 
+// The server's device allocator: the caller's hooks when given, else the stream-ordered pool.
+void* dev_alloc(const pkm_server* sv, size_t bytes, hipStream_t s) {
+  return sv->cfg.alloc ? sv->cfg.alloc(bytes, s, sv->cfg.alloc_ctx) : pool_alloc(bytes, s, nullptr);
+}
+void dev_free(const pkm_server* sv, void* p, hipStream_t s) {
+  if (!p) return;
+  if (sv->cfg.alloc) sv->cfg.free(p, s, sv->cfg.alloc_ctx);
+  else pool_free(p, s, nullptr);
+}
+
+std::unique_ptr<PinnedBuf> take_pinned(pkm_server* sv) {
+  if (!sv->spare_pinned.empty()) {
+    std::unique_ptr<PinnedBuf> b = std::move(sv->spare_pinned.back());
+    sv->spare_pinned.pop_back();
+    return b;
+  }
+  return std::unique_ptr<PinnedBuf>(new (std::nothrow) PinnedBuf());
+}
+
+// Evict an idle slot: its plan and catalog buffer go back to the pool on its own stream, its
+// pinned buffers to the server's spares (freeing pinned memory would synchronise the device).
 void free_slot(pkm_server* sv, Slot* s) {
   pkm_plan_destroy(s->plan);
-  if (s->dev_cat) (void)hipFree(s->dev_cat);
-  s->stage.release();
-  s->result.release();
+  dev_free(sv, s->dev_cat, s->stream);
   (void)hipStreamDestroy(s->stream);
+  if (s->stage) sv->spare_pinned.push_back(std::move(s->stage));
+  if (s->result) sv->spare_pinned.push_back(std::move(s->result));
   sv->resident -= s->bytes;
 }
 
-// Copy the request's catalog through the slot's pinned staging to its device buffer.
-pkm_status stage_request(Request* r, Slot* sl) {
+// Copy the request's host catalog through the slot's pinned staging to its device buffer.
+pkm_status stage_request(const pkm_server* sv, Request* r, Slot* sl) {
   const size_t total = r->host_cat.size();
   if (sl->dev_cap < total) {
-    if (sl->dev_cat) (void)hipFree(sl->dev_cat);
-    sl->dev_cat = nullptr;
+    dev_free(sv, sl->dev_cat, sl->stream);
     sl->dev_cap = 0;
-    if (hipMalloc((void**)&sl->dev_cat, total * sizeof(double)) != hipSuccess) {
-      sl->dev_cat = nullptr;
+    sl->dev_cat = (double*)dev_alloc(sv, total * sizeof(double), sl->stream);
+    if (!sl->dev_cat) {
       r->err = "catalog allocation failed";
       return PKM_ENOMEM;
     }
     sl->dev_cap = total;
   }
-  if (sl->stage.resize(total) != hipSuccess) { r->err = "pinned staging allocation failed"; return PKM_ENOMEM; }
-  std::memcpy(sl->stage.p, r->host_cat.data(), total * sizeof(double));
-  const hipError_t e = hipMemcpyAsync(sl->dev_cat, sl->stage.p, total * sizeof(double), hipMemcpyHostToDevice,
+  if (sl->stage->resize(total) != hipSuccess) { r->err = "pinned staging allocation failed"; return PKM_ENOMEM; }
+  std::memcpy(sl->stage->p, r->host_cat.data(), total * sizeof(double));
+  const hipError_t e = hipMemcpyAsync(sl->dev_cat, sl->stage->p, total * sizeof(double), hipMemcpyHostToDevice,
                                       sl->stream);
   if (e != hipSuccess) { r->err = hipGetErrorString(e); return PKM_EDEVICE; }
   return PKM_OK;
 }
 
-void catalogs_of(const Request* r, const Slot* sl, pkm_catalog* d, pkm_catalog* rr) {
-  const double* p = sl->dev_cat;
+// Device catalogs of a request laid out from `base`: pos, w, nbar of data, then of randoms.
+void catalogs_of(const Request* r, const double* base, pkm_catalog* d, pkm_catalog* rr) {
+  const double* p = base;
   d->pos = p; p += 3 * r->nd;
   d->w = r->dw ? p : nullptr; if (r->dw) p += r->nd;
   d->nbar = r->dn ? p : nullptr; if (r->dn) p += r->nd;
@@ -412,12 +471,23 @@ void complete(pkm_server* sv, std::shared_ptr<Request> r, pkm_status st) {
   r->done = nullptr;
   std::vector<double>().swap(r->host_cat);
   if (r->slot_plan) {
-    r->slot_plan->busy = false;
-    r->slot_plan->last_used = r->t_done;
+    Slot* sl = r->slot_plan;
+    // the plan now holds the painted field of this request's catalog (none after a failure or
+    // for host catalogs, which cannot be named again)
+    if (!r->reused_mesh || st != PKM_OK) sl->painted_cat = st == PKM_OK ? r->cat_id : 0;
+    sl->busy = false;
+    sl->last_used = r->t_done;
     r->slot_plan = nullptr;
   }
+  if (r->cat_id) {
+    auto it = sv->cats.find(r->cat_id);
+    if (it != sv->cats.end()) --it->second.refs;
+  }
   if (st == PKM_OK) {
-    sv->latencies_ms.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
+    const double ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+    sv->latencies_ms.push_back(ms);
+    sv->latencies_prec[r->params.precision == PKM_FP64 ? 1 : 0].push_back(ms);
+    if (r->reused_mesh) ++sv->mesh_reuses;
     ++sv->completed;
   } else {
     ++sv->failed;
@@ -426,96 +496,169 @@ void complete(pkm_server* sv, std::shared_ptr<Request> r, pkm_status st) {
   sv->finished[r->ticket] = r;
 }
 
-// Try to start the request at the head of the queue.  Returns false when it must wait.
-bool admit_head(pkm_server* sv, std::unique_lock<std::mutex>& lk) {
-  if (sv->queue.empty() || (int)sv->inflight.size() >= sv->cfg.max_inflight) return false;
-  std::shared_ptr<Request> r = sv->queue.front();
-  const PlanKey key = key_of(r->params);
-  Slot* use = nullptr;
-  const int hint = std::max(r->ell_max, r->params.ell_max_hint);
-  for (auto& s : sv->slots)
-    if (!s->busy && s->hint >= r->ell_max && !(s->key < key) && !(key < s->key)) { use = s.get(); break; }
-  const int64_t cat_bytes = (int64_t)r->host_cat.size() * 8;
-  int64_t need = use ? std::max<int64_t>(0, cat_bytes - (int64_t)use->dev_cap * 8) : r->need + cat_bytes;
-  // evict idle plans (least recently used first) until the request fits
-  while (sv->resident + need > sv->cfg.hbm_budget_bytes) {
-    Slot* victim = nullptr;
-    for (auto& s : sv->slots)
-      if (!s->busy && s.get() != use && (!victim || s->last_used < victim->last_used)) victim = s.get();
-    if (!victim) break;
-    free_slot(sv, victim);
-    sv->slots.erase(std::find_if(sv->slots.begin(), sv->slots.end(), [&](auto& p) { return p.get() == victim; }));
+// Issue request r on slot `sl` (its plan created first when sl->plan is null).  Runs without
+// the server lock: only the worker thread touches a busy slot.
+pkm_status start_request(pkm_server* sv, Request* r, Slot* sl, const double* reg_base) {
+  if (!sl->plan) {
+    if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) {
+      sl->stream = nullptr;
+      r->err = "stream creation failed";
+      return PKM_EDEVICE;
+    }
+    pkm_device dev{};
+    dev.device_id = sv->cfg.device_id;
+    dev.hip_stream = sl->stream;
+    dev.alloc = sv->cfg.alloc ? sv->cfg.alloc : pool_alloc;
+    dev.free = sv->cfg.alloc ? sv->cfg.free : pool_free;
+    dev.alloc_ctx = sv->cfg.alloc ? sv->cfg.alloc_ctx : nullptr;
+    pkm_params pp = sl->key.p;
+    pp.ell_max_hint = sl->hint;
+    const pkm_status st = pkm_plan_create(&pp, &dev, &sl->plan);
+    if (st != PKM_OK) {
+      sl->plan = nullptr;
+      r->err = "plan creation failed";
+      return st;
+    }
   }
-  if (sv->resident + need > sv->cfg.hbm_budget_bytes) {
-    if (sv->inflight.empty()) {  // can never fit
-      sv->queue.pop_front();
-      r->err = "request footprint above the server's HBM budget";
-      complete(sv, r, PKM_ENOMEM);
+  r->slot_plan = sl;
+  pkm_status st = pkm_internal::prepare(sl->plan, r->ell_max, r->edges.data(), (int)r->edges.size(), r->nd + r->nr);
+  if (st != PKM_OK) { r->err = pkm_internal::error_of(sl->plan); return st; }
+  if (sl->result->resize(pkm_internal::slot_doubles(sl->plan)) != hipSuccess) {
+    r->err = "pinned result allocation failed";
+    return PKM_ENOMEM;
+  }
+  if (r->reused_mesh) {
+    st = pkm_internal::enqueue_compute_only(sl->plan, sl->result->p);
+  } else {
+    const double* base = reg_base;
+    if (!base) {
+      st = stage_request(sv, r, sl);
+      base = sl->dev_cat;
+    }
+    if (st == PKM_OK) {
+      pkm_catalog d{}, rr{};
+      catalogs_of(r, base, &d, &rr);
+      st = pkm_internal::enqueue(sl->plan, &d, r->has_rand ? &rr : nullptr, sl->result->p, false);
+    }
+  }
+  if (st != PKM_OK) {
+    if (r->err.empty()) r->err = pkm_internal::error_of(sl->plan);
+    return st;
+  }
+  if (hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(r->done, sl->stream) != hipSuccess) {
+    r->err = "event failed";
+    return PKM_EDEVICE;
+  }
+  return PKM_OK;
+}
+
+// Admit one request from the first ADMIT_WINDOW queued ones, in arrival order: the first that
+// fits the budget (after evicting idle plans, least recently used first) while fewer than
+// max_inflight estimates run.  A request is served from the painted field a slot already holds
+// when it names the catalog that slot painted last.  A request that cannot fit even with nothing
+// else running fails with PKM_ENOMEM.  Once the oldest request has been passed MAX_PASSES times,
+// nothing is admitted before it.  Returns true when the queue changed.
+bool admit_some(pkm_server* sv, std::unique_lock<std::mutex>& lk) {
+  if (sv->queue.empty() || (int)sv->inflight.size() >= sv->cfg.max_inflight) return false;
+  const size_t window = sv->queue.front()->passed >= MAX_PASSES ? 1 : std::min(sv->queue.size(), ADMIT_WINDOW);
+  for (size_t qi = 0; qi < window; ++qi) {
+    std::shared_ptr<Request> r = sv->queue[qi];
+    const PlanKey key = key_of(r->params);
+    // an idle plan of the same key: the one holding this catalog's painted field, else one
+    // holding no registered catalog's field, else the least recently used
+    Slot* use = nullptr;
+    bool hit = false;
+    for (auto& s : sv->slots) {
+      if (s->busy || s->hint < r->ell_max || !same_key(s->key, key)) continue;
+      if (r->cat_id && s->painted_cat == r->cat_id) { use = s.get(); hit = true; break; }
+      const bool blank = s->painted_cat == 0;
+      if (!use || (blank && use->painted_cat != 0) ||
+          (blank == (use->painted_cat == 0) && s->last_used < use->last_used))
+        use = s.get();
+    }
+    const int64_t cat_bytes = r->cat_id ? 0 : (int64_t)r->host_cat.size() * 8;
+    // a reused plan grows only by what this request needs beyond its present buffers
+    const int64_t need = use ? std::max<int64_t>(0, r->need - pkm_internal::device_bytes(use->plan)) +
+                                   std::max<int64_t>(0, cat_bytes - (int64_t)use->dev_cap * 8)
+                             : r->need + cat_bytes;
+    int64_t evictable = 0;
+    bool running = false;
+    for (auto& s : sv->slots) {
+      if (s->busy) running = true;
+      else if (s.get() != use) evictable += s->bytes;
+    }
+    if (sv->resident - evictable + need > sv->cfg.hbm_budget_bytes) {
+      if (!running && qi == 0) {  // cannot fit even with nothing else resident but catalogs
+        sv->queue.pop_front();
+        r->err = "request footprint above the server's HBM budget";
+        complete(sv, r, PKM_ENOMEM);
+        sv->cv_done.notify_all();
+        return true;
+      }
+      continue;  // wait for running estimates; look at the next request
+    }
+    while (sv->resident + need > sv->cfg.hbm_budget_bytes) {
+      Slot* victim = nullptr;
+      for (auto& s : sv->slots)
+        if (!s->busy && s.get() != use && (!victim || s->last_used < victim->last_used)) victim = s.get();
+      if (!victim) break;
+      free_slot(sv, victim);
+      sv->slots.erase(std::find_if(sv->slots.begin(), sv->slots.end(), [&](auto& p) { return p.get() == victim; }));
+    }
+    for (size_t k = 0; k < qi; ++k) ++sv->queue[k]->passed;
+    sv->queue.erase(sv->queue.begin() + (std::ptrdiff_t)qi);
+    r->reused_mesh = hit;
+    const double* reg_base = r->cat_id ? sv->cats[r->cat_id].dev : nullptr;
+    Slot* slot = use;
+    if (!slot) {  // a new slot, visible to no one else until it is added below
+      std::unique_ptr<Slot> fresh(new (std::nothrow) Slot());
+      if (fresh) {
+        fresh->key = key;
+        fresh->hint = std::max(r->ell_max, r->params.ell_max_hint);
+        fresh->stage = take_pinned(sv);
+        fresh->result = take_pinned(sv);
+      }
+      if (!fresh || !fresh->stage || !fresh->result) {
+        if (fresh && fresh->stage) sv->spare_pinned.push_back(std::move(fresh->stage));
+        if (fresh && fresh->result) sv->spare_pinned.push_back(std::move(fresh->result));
+        complete(sv, r, PKM_ENOMEM);
+        sv->cv_done.notify_all();
+        return true;
+      }
+      fresh->busy = true;
+      slot = fresh.get();
+      sv->slots.push_back(std::move(fresh));
+    }
+    slot->busy = true;
+    sv->resident += need;  // reserved until the plan's size is known
+    lk.unlock();           // device work below; clients touch only the queue and the results
+    pkm_status st = start_request(sv, r.get(), slot, reg_base);
+    lk.lock();
+    sv->resident -= need;
+    if (slot->plan) {
+      const int64_t b = pkm_internal::device_bytes(slot->plan) + (int64_t)slot->dev_cap * 8;
+      sv->resident += b - slot->bytes;
+      slot->bytes = b;
+    } else {  // the plan could not be created: drop the slot
+      r->slot_plan = nullptr;
+      if (slot->stream) (void)hipStreamDestroy(slot->stream);
+      if (slot->stage) sv->spare_pinned.push_back(std::move(slot->stage));
+      if (slot->result) sv->spare_pinned.push_back(std::move(slot->result));
+      sv->resident -= slot->bytes;
+      sv->slots.erase(std::find_if(sv->slots.begin(), sv->slots.end(), [&](auto& p) { return p.get() == slot; }));
+    }
+    sv->peak_resident = std::max(sv->peak_resident, sv->resident);
+    if (st != PKM_OK) {
+      complete(sv, r, st);
       sv->cv_done.notify_all();
       return true;
     }
-    return false;  // wait for a completion to free memory
-  }
-  sv->queue.pop_front();
-  lk.unlock();  // device work below; the client side only touches the queue and results
-  pkm_status st = PKM_OK;
-  if (!use) {
-    auto s = std::make_unique<Slot>();
-    s->key = key;
-    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    if (e != hipSuccess) st = PKM_EDEVICE;
-    if (st == PKM_OK) {
-      pkm_device dev{};
-      dev.device_id = sv->cfg.device_id;
-      dev.hip_stream = s->stream;
-      pkm_params pp = key.p;
-      pp.ell_max_hint = hint;
-      s->hint = hint;
-      st = pkm_plan_create(&pp, &dev, &s->plan);
-      if (st != PKM_OK) {
-        r->err = "plan creation failed";
-        (void)hipStreamDestroy(s->stream);
-      }
-    }
-    if (st == PKM_OK) {
-      use = s.get();
-      lk.lock();
-      sv->slots.push_back(std::move(s));
-      lk.unlock();
-    }
-  }
-  if (st == PKM_OK) {
-    use->busy = true;
-    r->slot_plan = use;
-    st = pkm_internal::prepare(use->plan, r->ell_max, r->edges.data(), (int)r->edges.size(), r->nd + r->nr);
-    if (st != PKM_OK) r->err = pkm_internal::error_of(use->plan);
-  }
-  if (st == PKM_OK && use->result.resize(pkm_internal::slot_doubles(use->plan)) != hipSuccess) st = PKM_ENOMEM;
-  if (st == PKM_OK) st = stage_request(r.get(), use);
-  if (st == PKM_OK) {
-    pkm_catalog d{}, rr{};
-    catalogs_of(r.get(), use, &d, &rr);
-    st = pkm_internal::enqueue(use->plan, &d, r->has_rand ? &rr : nullptr, use->result.p, false);
-    if (st != PKM_OK) r->err = pkm_internal::error_of(use->plan);
-  }
-  if (st == PKM_OK && (hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess ||
-                       hipEventRecord(r->done, use->stream) != hipSuccess))
-    st = PKM_EDEVICE;
-  lk.lock();
-  if (use) {
-    const int64_t b = pkm_internal::device_bytes(use->plan) + (int64_t)use->dev_cap * 8;
-    sv->resident += b - use->bytes;
-    use->bytes = b;
-  }
-  sv->peak_resident = std::max(sv->peak_resident, sv->resident);
-  if (st != PKM_OK) {
-    complete(sv, r, st);
-    sv->cv_done.notify_all();
+    sv->inflight.push_back(r);
+    sv->max_concurrent = std::max(sv->max_concurrent, (int)sv->inflight.size());
     return true;
   }
-  sv->inflight.push_back(r);
-  sv->max_concurrent = std::max(sv->max_concurrent, (int)sv->inflight.size());
-  return true;
+  return false;
 }
 
 void reap(pkm_server* sv, std::unique_lock<std::mutex>& lk) {
@@ -537,7 +680,7 @@ void reap(pkm_server* sv, std::unique_lock<std::mutex>& lk) {
       res.poles = r->poles.data();
       res.k_mean = r->kmean.data();
       res.n_modes = r->nmodes.data();
-      st = pkm_internal::finish(r->slot_plan->plan, r->slot_plan->result.p, r->nd, r->nr, &res, &r->err);
+      st = pkm_internal::finish(r->slot_plan->plan, r->slot_plan->result->p, r->nd, r->nr, &res, &r->err);
       r->alpha = res.alpha;
       r->norm_I = res.norm_I;
       r->shot = res.shot_noise;
@@ -556,7 +699,7 @@ void worker_loop(pkm_server* sv) {
     if (sv->stop && sv->inflight.empty()) break;
     reap(sv, lk);
     bool progressed = false;
-    while (!sv->stop && admit_head(sv, lk)) progressed = true;
+    while (!sv->stop && admit_some(sv, lk)) progressed = true;
     if (sv->inflight.empty() && sv->queue.empty()) {
       if (sv->stop) break;
       sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
@@ -599,6 +742,13 @@ double percentile(std::vector<double> v, double q) {
   return v[lo] + (pos - (double)lo) * (v[hi] - v[lo]);
 }
 
+// Doubles of a catalog pair laid out as catalogs_of reads them.
+size_t layout_doubles(const pkm_catalog* d, const pkm_catalog* r) {
+  size_t n = (size_t)d->n * (3 + (d->w ? 1 : 0) + (d->nbar ? 1 : 0));
+  if (r) n += (size_t)r->n * (4 + (r->w ? 1 : 0));
+  return n;
+}
+
 }  // namespace
 
 extern "C" {
@@ -606,6 +756,7 @@ extern "C" {
 pkm_status pkm_server_create(const pkm_server_config* cfg, pkm_server** out) {
   if (!cfg || !out) return PKM_EINVAL;
   if (cfg->max_inflight < 1 || cfg->max_inflight > 32) return PKM_EINVAL;
+  if ((cfg->alloc == nullptr) != (cfg->free == nullptr)) return PKM_EINVAL;
   pkm_server* sv = new (std::nothrow) pkm_server();
   if (!sv) return PKM_ENOMEM;
   sv->cfg = *cfg;
@@ -621,6 +772,13 @@ pkm_status pkm_server_create(const pkm_server_config* cfg, pkm_server** out) {
     }
     sv->cfg.hbm_budget_bytes = (int64_t)(0.8 * (double)free_b);
   }
+  // keep freed plan memory in the device's pool for the next plan instead of returning it
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, cfg->device_id) == hipSuccess && pool) {
+    uint64_t keep = (uint64_t)sv->cfg.hbm_budget_bytes;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
+  (void)hipGetLastError();
   try {
     sv->worker = std::thread(worker_loop, sv);
   } catch (...) {
@@ -631,48 +789,132 @@ pkm_status pkm_server_create(const pkm_server_config* cfg, pkm_server** out) {
   return PKM_OK;
 }
 
+pkm_status pkm_server_register_catalog(pkm_server* sv, const pkm_catalog* data, const pkm_catalog* randoms,
+                                       uint64_t* cat_id) {
+  if (!sv || !cat_id) return PKM_EINVAL;
+  if (pkm_check_catalogs(data, randoms) != PKM_OK) {
+    sv->err = "invalid catalogs (empty, missing positions or n-bar, or above PKM_MAX_PARTICLES)";
+    return PKM_EINVAL;
+  }
+  RegCat rc;
+  rc.nd = data->n;
+  rc.has_rand = randoms != nullptr;
+  rc.nr = randoms ? randoms->n : 0;
+  rc.dw = data->w != nullptr;
+  rc.dn = data->nbar != nullptr;
+  rc.rw = randoms && randoms->w != nullptr;
+  const size_t total = layout_doubles(data, randoms);
+  rc.bytes = (int64_t)(total * sizeof(double));
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    if (sv->stop) return PKM_ECANCELLED;
+    int64_t evictable = 0;
+    for (auto& s : sv->slots)
+      if (!s->busy) evictable += s->bytes;
+    if (sv->resident - evictable + rc.bytes > sv->cfg.hbm_budget_bytes) {
+      sv->err = "catalog does not fit the server's HBM budget";
+      return PKM_ENOMEM;
+    }
+    while (sv->resident + rc.bytes > sv->cfg.hbm_budget_bytes) {
+      Slot* victim = nullptr;
+      for (auto& s : sv->slots)
+        if (!s->busy && (!victim || s->last_used < victim->last_used)) victim = s.get();
+      if (!victim) break;
+      (void)hipSetDevice(sv->cfg.device_id);
+      free_slot(sv, victim);
+      sv->slots.erase(std::find_if(sv->slots.begin(), sv->slots.end(), [&](auto& p) { return p.get() == victim; }));
+    }
+    sv->resident += rc.bytes;  // reserved while the copy runs
+    sv->peak_resident = std::max(sv->peak_resident, sv->resident);
+  }
+  hipError_t e = hipSetDevice(sv->cfg.device_id);
+  if (e == hipSuccess) e = hipMalloc((void**)&rc.dev, std::max<size_t>(total, 1) * sizeof(double));
+  if (e == hipSuccess) {
+    double* p = rc.dev;
+    auto put = [&](const double* src, int64_t count) {
+      if (e == hipSuccess) e = hipMemcpy(p, src, (size_t)count * sizeof(double), hipMemcpyDefault);
+      p += count;
+    };
+    put(data->pos, 3 * data->n);
+    if (rc.dw) put(data->w, data->n);
+    if (rc.dn) put(data->nbar, data->n);
+    if (randoms) {
+      put(randoms->pos, 3 * randoms->n);
+      if (rc.rw) put(randoms->w, randoms->n);
+      put(randoms->nbar, randoms->n);
+    }
+  }
+  std::lock_guard<std::mutex> g(sv->mu);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    if (rc.dev) (void)hipFree(rc.dev);
+    sv->resident -= rc.bytes;
+    sv->err = std::string("catalog upload failed: ") + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? PKM_ENOMEM : PKM_EDEVICE;
+  }
+  *cat_id = sv->next_cat++;
+  sv->cat_bytes += rc.bytes;
+  sv->cats[*cat_id] = rc;
+  return PKM_OK;
+}
+
+pkm_status pkm_server_unregister_catalog(pkm_server* sv, uint64_t cat_id) {
+  if (!sv) return PKM_EINVAL;
+  double* dev = nullptr;
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    auto it = sv->cats.find(cat_id);
+    if (it == sv->cats.end()) { sv->err = "unknown catalog"; return PKM_EINVAL; }
+    if (it->second.refs > 0) { sv->err = "catalog named by queued or running requests"; return PKM_EBUSY; }
+    dev = it->second.dev;
+    sv->resident -= it->second.bytes;
+    sv->cat_bytes -= it->second.bytes;
+    sv->cats.erase(it);
+    for (auto& s : sv->slots)
+      if (s->painted_cat == cat_id) s->painted_cat = 0;  // the id is not reused, but no stale hit either
+  }
+  (void)hipSetDevice(sv->cfg.device_id);
+  (void)hipFree(dev);
+  return PKM_OK;
+}
+
 pkm_status pkm_server_submit(pkm_server* sv, const pkm_request* rq, int64_t* ticket) {
   if (!sv || !rq || !ticket) return PKM_EINVAL;
-  // validate what can be checked on the host
-  if (!rq->data.pos || rq->data.n <= 0 || rq->data.on_device) {
-    sv->err = "requests take a non-empty host data catalog";
-    return PKM_EINVAL;
-  }
-  if (rq->has_randoms && (!rq->randoms.pos || !rq->randoms.nbar || rq->randoms.n <= 0 || rq->randoms.on_device)) {
-    sv->err = "randoms need host positions and nbar and n > 0";
-    return PKM_EINVAL;
-  }
   if (!rq->k_edges || rq->n_edges < 2 || rq->ell_max < 0 || rq->ell_max > 16 || rq->ell_max % 2) {
     sv->err = "need even ell_max in 0..16 and at least two k edges";
     return PKM_EINVAL;
   }
-  if (rq->data.n + (rq->has_randoms ? rq->randoms.n : 0) > PKM_MAX_PARTICLES) {
-    sv->err = "data + random objects above PKM_MAX_PARTICLES";
-    return PKM_EINVAL;
-  }
+  for (int i = 0; i < rq->n_edges; ++i)
+    if (!(rq->k_edges[i] >= 0.0) || !std::isfinite(rq->k_edges[i]) || (i > 0 && !(rq->k_edges[i] > rq->k_edges[i - 1]))) {
+      sv->err = "k edges must be finite, >= 0 and strictly increasing";
+      return PKM_EINVAL;
+    }
   auto r = std::make_shared<Request>();
   r->params = rq->params;
   r->ell_max = rq->ell_max;
   r->edges.assign(rq->k_edges, rq->k_edges + rq->n_edges);
-  r->nd = rq->data.n;
-  r->has_rand = rq->has_randoms != 0;
-  r->nr = r->has_rand ? rq->randoms.n : 0;
-  r->dw = rq->data.w != nullptr;
-  r->dn = rq->data.nbar != nullptr;
-  r->rw = r->has_rand && rq->randoms.w != nullptr;
-  const size_t total = (size_t)r->nd * (3 + r->dw + r->dn) + (size_t)r->nr * (3 + r->rw + (r->has_rand ? 1 : 0));
-  r->need = pkm_internal::footprint(&rq->params, rq->ell_max, rq->n_edges, r->nd + r->nr);
-  if (r->need < 0) { sv->err = "invalid mesh parameters"; return PKM_EINVAL; }
-  if (rq->params.max_group == 0 && r->need > sv->cfg.hbm_budget_bytes / 2) {
-    // keep fewer weighted fields resident at once (field groups run one after another)
-    for (int g = 64; g >= 1; g /= 2) {
-      r->params.max_group = g;
-      r->need = pkm_internal::footprint(&r->params, rq->ell_max, rq->n_edges, r->nd + r->nr);
-      if (r->need <= sv->cfg.hbm_budget_bytes / 2) break;
+  r->cat_id = rq->catalog_id;
+  if (r->cat_id == 0) {
+    // host catalogs, copied now so the caller may release its arrays after submit
+    if (!rq->data.pos || rq->data.n <= 0 || rq->data.on_device) {
+      sv->err = "requests take a non-empty host data catalog or a registered catalog";
+      return PKM_EINVAL;
     }
-  }
-  {
-    // host copy so the caller may release its arrays after submit
+    if (rq->has_randoms && (!rq->randoms.pos || !rq->randoms.nbar || rq->randoms.n <= 0 || rq->randoms.on_device)) {
+      sv->err = "randoms need host positions and nbar and n > 0";
+      return PKM_EINVAL;
+    }
+    if (rq->data.n + (rq->has_randoms ? rq->randoms.n : 0) > PKM_MAX_PARTICLES) {
+      sv->err = "data + random objects above PKM_MAX_PARTICLES";
+      return PKM_EINVAL;
+    }
+    r->nd = rq->data.n;
+    r->has_rand = rq->has_randoms != 0;
+    r->nr = r->has_rand ? rq->randoms.n : 0;
+    r->dw = rq->data.w != nullptr;
+    r->dn = rq->data.nbar != nullptr;
+    r->rw = r->has_rand && rq->randoms.w != nullptr;
+    const size_t total = layout_doubles(&rq->data, r->has_rand ? &rq->randoms : nullptr);
     try {
       r->host_cat.resize(total);
     } catch (...) {
@@ -691,6 +933,24 @@ pkm_status pkm_server_submit(pkm_server* sv, const pkm_request* rq, int64_t* tic
   }
   std::lock_guard<std::mutex> g(sv->mu);
   if (sv->stop) return PKM_ECANCELLED;
+  if (r->cat_id) {
+    auto it = sv->cats.find(r->cat_id);
+    if (it == sv->cats.end()) { sv->err = "unknown catalog id"; return PKM_EINVAL; }
+    const RegCat& rc = it->second;
+    r->nd = rc.nd; r->nr = rc.nr; r->has_rand = rc.has_rand;
+    r->dw = rc.dw; r->dn = rc.dn; r->rw = rc.rw;
+  }
+  r->need = pkm_internal::footprint(&r->params, r->ell_max, (int)r->edges.size(), r->nd + r->nr);
+  if (r->need < 0) { sv->err = "invalid mesh parameters"; return PKM_EINVAL; }
+  if (rq->params.max_group == 0 && r->need > sv->cfg.hbm_budget_bytes / 2) {
+    // keep fewer weighted fields resident at once (field groups run one after another)
+    for (int gmax = 64; gmax >= 1; gmax /= 2) {
+      r->params.max_group = gmax;
+      r->need = pkm_internal::footprint(&r->params, r->ell_max, (int)r->edges.size(), r->nd + r->nr);
+      if (r->need <= sv->cfg.hbm_budget_bytes / 2) break;
+    }
+  }
+  if (r->cat_id) ++sv->cats[r->cat_id].refs;
   r->ticket = sv->next_ticket++;
   r->t_submit = Clock::now();
   if (!sv->any_submit) { sv->t_first_submit = r->t_submit; sv->any_submit = true; }
@@ -748,6 +1008,15 @@ pkm_status pkm_server_stats(pkm_server* sv, pkm_server_stats_t* out) {
     const double span = std::chrono::duration<double>(sv->t_last_done - sv->t_first_submit).count();
     out->throughput_per_s = span > 0 ? (double)sv->completed / span : 0.0;
   }
+  out->completed_fp32 = (int64_t)sv->latencies_prec[0].size();
+  out->completed_fp64 = (int64_t)sv->latencies_prec[1].size();
+  out->latency_p50_ms_fp32 = percentile(sv->latencies_prec[0], 0.50);
+  out->latency_p99_ms_fp32 = percentile(sv->latencies_prec[0], 0.99);
+  out->latency_p50_ms_fp64 = percentile(sv->latencies_prec[1], 0.50);
+  out->latency_p99_ms_fp64 = percentile(sv->latencies_prec[1], 0.99);
+  out->mesh_reuses = sv->mesh_reuses;
+  out->registered_catalogs = (int64_t)sv->cats.size();
+  out->registered_bytes = sv->cat_bytes;
   return PKM_OK;
 }
 
@@ -764,6 +1033,10 @@ void pkm_server_destroy(pkm_server* sv) {
   (void)hipSetDevice(sv->cfg.device_id);
   for (auto& s : sv->slots) free_slot(sv, s.get());
   sv->slots.clear();
+  for (auto& kv : sv->cats) (void)hipFree(kv.second.dev);
+  sv->cats.clear();
+  (void)hipDeviceSynchronize();
+  sv->spare_pinned.clear();
   delete sv;
 }
 

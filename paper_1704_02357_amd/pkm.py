@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-ABI_VERSION = 3
+ABI_VERSION = 4
 MAX_PARTICLES = 2 ** 31 - 2 ** 16   # PKM_MAX_PARTICLES: data + random objects per estimate
 NGP, CIC, TSC = 1, 2, 3
 FP32, FP64 = 0, 1
@@ -67,19 +67,24 @@ def _shape(d):
 
 
 class ServerConfig(C.Structure):
-    _fields_ = [("device_id", C.c_int32), ("hbm_budget_bytes", C.c_int64), ("max_inflight", C.c_int32)]
+    _fields_ = [("device_id", C.c_int32), ("hbm_budget_bytes", C.c_int64), ("max_inflight", C.c_int32),
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p)]
 
 
 class Request(C.Structure):
     _fields_ = [("params", Params), ("ell_max", C.c_int32), ("k_edges", C.c_void_p), ("n_edges", C.c_int32),
-                ("data", Catalog), ("randoms", Catalog), ("has_randoms", C.c_int32)]
+                ("data", Catalog), ("randoms", Catalog), ("has_randoms", C.c_int32), ("catalog_id", C.c_uint64)]
 
 
 class ServerStats(C.Structure):
     _fields_ = [("completed", C.c_int64), ("failed", C.c_int64), ("queued", C.c_int64), ("inflight", C.c_int64),
                 ("resident_plans", C.c_int64), ("resident_bytes", C.c_int64), ("peak_bytes", C.c_int64),
                 ("max_concurrent", C.c_int32), ("latency_p50_ms", C.c_double), ("latency_p99_ms", C.c_double),
-                ("latency_mean_ms", C.c_double), ("throughput_per_s", C.c_double)]
+                ("latency_mean_ms", C.c_double), ("throughput_per_s", C.c_double),
+                ("completed_fp32", C.c_int64), ("completed_fp64", C.c_int64),
+                ("latency_p50_ms_fp32", C.c_double), ("latency_p99_ms_fp32", C.c_double),
+                ("latency_p50_ms_fp64", C.c_double), ("latency_p99_ms_fp64", C.c_double),
+                ("mesh_reuses", C.c_int64), ("registered_catalogs", C.c_int64), ("registered_bytes", C.c_int64)]
 
 
 STAGES = ["sums", "fill", "paint", "zfwd", "ycol", "xcombine", "iycol", "zpre", "xpost", "reduce"]
@@ -147,6 +152,10 @@ def load_library():
         "pkm_batch_last_error": (C.c_char_p, [P]),
         "pkm_batch_destroy": (None, [P]),
         "pkm_server_create": (C.c_int, [C.POINTER(ServerConfig), C.POINTER(P)]),
+        "pkm_plan_footprint": (C.c_int64, [C.POINTER(Params), C.c_int32, C.c_int32, C.c_int64]),
+        "pkm_server_register_catalog": (C.c_int, [P, C.POINTER(Catalog), C.POINTER(Catalog),
+                                                  C.POINTER(C.c_uint64)]),
+        "pkm_server_unregister_catalog": (C.c_int, [P, C.c_uint64]),
         "pkm_server_submit": (C.c_int, [P, C.POINTER(Request), C.POINTER(C.c_int64)]),
         "pkm_server_poll": (C.c_int, [P, C.c_int64, C.POINTER(Result)]),
         "pkm_server_wait": (C.c_int, [P, C.c_int64, C.POINTER(Result)]),
@@ -188,6 +197,16 @@ def kaiser_wedge_gamma(ell_max: int, mu_edges, beta: float) -> np.ndarray:
     if st:
         raise PkmError(st, "pkm_kaiser_wedge_gamma rejected its arguments")
     return out
+
+
+def plan_footprint(nmesh, box_len, ell_max, n_edges, n_particles, **params) -> int:
+    """Device bytes a plan would hold for one estimate (the serving loop's admission figure);
+    keyword arguments as for Plan."""
+    p = make_params(nmesh, box_len, **params)
+    b = load_library().pkm_plan_footprint(C.byref(p), int(ell_max), int(n_edges), int(n_particles))
+    if b < 0:
+        raise PkmError(1, "pkm_plan_footprint rejected its arguments")
+    return int(b)
 
 
 def nonuniform_mu_edges(ell_max: int) -> np.ndarray:
@@ -254,6 +273,27 @@ def _result_dict(r, poles, kmean, nmodes, ell_max, all_ell: bool = False):
                 n_transforms=r.n_transforms, ells=list(range(0, ell_max + 1, 1 if all_ell else 2)))
 
 
+def _marshal_catalog(cat, keep):
+    """A pkm_catalog over (pos, w, nbar) of host arrays or CUDA tensors; the converted arrays
+    are appended to `keep`, which must outlive the call they are passed to."""
+    if cat is None:
+        return None
+    pos, w, nbar = cat if isinstance(cat, tuple) else (cat.pos, cat.w, getattr(cat, "nbar", None))
+    c = Catalog()
+    on_dev = hasattr(pos, "is_cuda") and pos.is_cuda
+    if on_dev:
+        import torch
+        arrs = [None if a is None else a.to(torch.float64).contiguous() for a in (pos, w, nbar)]
+        c.pos, c.w, c.nbar = [None if a is None else a.data_ptr() for a in arrs]
+    else:
+        arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (pos, w, nbar)]
+        c.pos, c.w, c.nbar = [None if a is None else a.ctypes.data for a in arrs]
+    c.n = int(arrs[0].shape[0])
+    c.on_device = int(on_dev)
+    keep.append(arrs)
+    return c
+
+
 class Plan:
     """One mesh configuration.  Inputs may be numpy arrays (host) or torch CUDA tensors."""
 
@@ -294,24 +334,7 @@ class Plan:
             raise PkmError(st, f"{what}: {msg.decode() if msg else ''}")
 
     def _catalog(self, cat):
-        if cat is None:
-            return None
-        pos, w, nbar = cat if isinstance(cat, tuple) else (cat.pos, cat.w, getattr(cat, "nbar", None))
-        c = Catalog()
-        on_dev = hasattr(pos, "is_cuda") and pos.is_cuda
-        if on_dev:
-            import torch
-            arrs = [None if a is None else a.to(torch.float64).contiguous() for a in (pos, w, nbar)]
-            c.pos, c.w, c.nbar = [None if a is None else a.data_ptr() for a in arrs]
-            c.n = int(arrs[0].shape[0])
-            c.on_device = 1
-        else:
-            arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (pos, w, nbar)]
-            c.pos, c.w, c.nbar = [None if a is None else a.ctypes.data for a in arrs]
-            c.n = int(arrs[0].shape[0])
-            c.on_device = 0
-        self._keep.append(arrs)
-        return c
+        return _marshal_catalog(cat, self._keep)
 
     # -- API ----------------------------------------------------------------------------
     def paint(self, data, randoms=None):
@@ -483,10 +506,15 @@ class Batch:
 class Server:
     """Request loop on one device: admission by HBM footprint, overlapping estimates."""
 
-    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, max_inflight: int = 4):
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, max_inflight: int = 4, allocator=None):
+        """allocator: None (the device's stream-ordered pool) or an object with ctypes
+        callbacks c_alloc / c_free of pkm_device's allocator signature."""
         self.lib = load_library()
         cfg = ServerConfig()
         cfg.device_id, cfg.hbm_budget_bytes, cfg.max_inflight = int(device), int(hbm_budget_bytes), int(max_inflight)
+        self._allocator = allocator
+        if allocator is not None:
+            cfg.alloc, cfg.free = allocator.c_alloc, allocator.c_free
         h = C.c_void_p()
         st = self.lib.pkm_server_create(C.byref(cfg), C.byref(h))
         if st:
@@ -499,23 +527,42 @@ class Server:
             msg = self.lib.pkm_server_last_error(self.h)
             raise PkmError(st, f"{what}: {msg.decode() if msg else ''}")
 
-    def submit(self, nmesh, box_len, ell_max, k_edges, data, randoms=None, **params) -> int:
-        """Queue one estimate of host catalogs; keyword arguments as for Plan."""
+    def register_catalog(self, data, randoms=None) -> int:
+        """Copy a catalog (and randoms) to the device once; requests name it by the id."""
+        keep = []
+        d = _marshal_catalog(data, keep)
+        r = _marshal_catalog(randoms, keep)
+        cid = C.c_uint64()
+        self._check(self.lib.pkm_server_register_catalog(self.h, C.byref(d), C.byref(r) if r is not None else None,
+                                                         C.byref(cid)), "pkm_server_register_catalog")
+        return cid.value
+
+    def unregister_catalog(self, catalog_id: int):
+        self._check(self.lib.pkm_server_unregister_catalog(self.h, int(catalog_id)), "pkm_server_unregister_catalog")
+
+    def submit(self, nmesh, box_len, ell_max, k_edges, data=None, randoms=None, *, catalog_id: int = 0,
+               **params) -> int:
+        """Queue one estimate of host catalogs, or of a registered catalog (catalog_id);
+        keyword arguments as for Plan."""
         rq = Request()
         rq.params = make_params(nmesh, box_len, **params)
         e = np.ascontiguousarray(k_edges, dtype=np.float64)
         rq.ell_max, rq.k_edges, rq.n_edges = int(ell_max), e.ctypes.data, e.size
+        rq.catalog_id = int(catalog_id)
         keep = [e]
-        for field, cat in (("data", data), ("randoms", randoms)):
-            if cat is None:
-                continue
-            arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64)
-                    for a in (cat.pos, cat.w, getattr(cat, "nbar", None))]
-            keep.append(arrs)
-            c = getattr(rq, field)
-            c.pos, c.w, c.nbar = [None if a is None else a.ctypes.data for a in arrs]
-            c.n, c.on_device = int(arrs[0].shape[0]), 0
-        rq.has_randoms = int(randoms is not None)
+        if not catalog_id:
+            if data is None:
+                raise ValueError("submit needs host catalogs or a registered catalog_id")
+            for field, cat in (("data", data), ("randoms", randoms)):
+                if cat is None:
+                    continue
+                arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+                        for a in (cat.pos, cat.w, getattr(cat, "nbar", None))]
+                keep.append(arrs)
+                c = getattr(rq, field)
+                c.pos, c.w, c.nbar = [None if a is None else a.ctypes.data for a in arrs]
+                c.n, c.on_device = int(arrs[0].shape[0]), 0
+            rq.has_randoms = int(randoms is not None)
         t = C.c_int64()
         self._check(self.lib.pkm_server_submit(self.h, C.byref(rq), C.byref(t)), "pkm_server_submit")
         self._shape[t.value] = (int(ell_max), e.size - 1)

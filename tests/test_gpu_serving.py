@@ -1,0 +1,222 @@
+"""GPU tests of the serving loop's catalog registration, painted-field reuse, admission past a
+blocked request, per-precision statistics and a failing allocator.
+
+Every served result is compared with the FP64 oracle (each precision form's tolerance) and
+with the same estimate run alone through the synchronous calls."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+from tests.parity_util import assert_pole_parity, oracle_params, small_catalogs
+
+pytestmark = pytest.mark.gpu
+
+OBS = (30.0, -40.0, -700.0)
+L = 300.0
+KW = dict(observer=OBS, window=3, interlaced=True, compensated=True)
+
+
+def _edges(n, dk=0.04):
+    return np.arange(0.0, math.pi * n / L, dk)
+
+
+def _alone(n, prec, lmax, d, r, edges):
+    from paper_1704_02357_amd import Plan
+    p = Plan(n, L, precision=prec, ell_max_hint=lmax, **KW)
+    p.paint(d, r)
+    out = p.compute_multipoles(lmax, edges)
+    p.close()
+    return out
+
+
+def _oracle(n, lmax, d, r, edges):
+    from oracle.estimator import multipoles
+    return multipoles(d, r, oracle_params(n, L, OBS, 3, True, True), lmax, edges)
+
+
+def _close(a, b, prec, label):
+    """Served and alone agree to rounding (painting accumulates with atomics)."""
+    assert np.array_equal(a["n_modes"], b["n_modes"]), label
+    pa, pb = np.asarray(a["poles"]), np.asarray(b["poles"])
+    scale = np.maximum(np.abs(pb), np.abs(pb[0] + b["shot_noise"])[None, :])
+    ok = np.isfinite(pb)
+    assert np.array_equal(ok, np.isfinite(pa)), label
+    err = float(np.max(np.abs(pa - pb)[ok] / scale[ok]))
+    print(f"[served vs alone] {label} {err:.2e}", flush=True)
+    assert err <= (2e-6 if prec == 0 else 1e-12), (label, err)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_registered_catalog_reuses_painted_field(gpu, prec):
+    """Requests for a registered catalog: the first paints, later ones on the same plan are
+    served from the painted field it holds (other l_max and edges too) and equal the oracle,
+    the estimate alone and, for the same request, the first result exactly (the transform,
+    weighting and binning passes add in a fixed order).  A host-catalog request on that plan
+    replaces the field, so the next request paints again."""
+    from paper_1704_02357_amd import PkmError, Server
+    n = 64
+    d, r = small_catalogs(3000, 15000, L, seed=40 + prec)
+    e4, e8 = _edges(n), _edges(n, 0.05)
+    sv = Server(max_inflight=1)
+    cid = sv.register_catalog(d, r)
+    st = sv.stats()
+    assert st["registered_catalogs"] == 1 and st["registered_bytes"] == (3000 * 5 + 15000 * 5) * 8
+    kw = dict(KW, precision=prec, ell_max_hint=8)
+    print(f"[case] registered catalog prec={prec}: first request", flush=True)
+    first = sv.wait(sv.submit(n, L, 4, e4, catalog_id=cid, **kw))
+    assert sv.stats()["mesh_reuses"] == 0
+    print(f"[case] registered catalog prec={prec}: reused field, l<=8", flush=True)
+    second = sv.wait(sv.submit(n, L, 8, e8, catalog_id=cid, **kw))
+    third = sv.wait(sv.submit(n, L, 4, e4, catalog_id=cid, **kw))
+    assert sv.stats()["mesh_reuses"] == 2
+    for k in ("poles", "k_mean", "n_modes"):
+        assert np.array_equal(np.asarray(first[k]), np.asarray(third[k])), k
+    for k in ("alpha", "norm_I", "shot_noise"):
+        assert first[k] == third[k] == second[k], k
+    # a host-catalog request on the same plan, then the registered catalog again: a miss
+    d2, r2 = small_catalogs(2500, 12000, L, seed=90 + prec)
+    other = sv.wait(sv.submit(n, L, 4, e4, d2, r2, **kw))
+    fourth = sv.wait(sv.submit(n, L, 4, e4, catalog_id=cid, **kw))
+    st = sv.stats()
+    print(f"[server] {st}", flush=True)
+    assert st["mesh_reuses"] == 2 and st["completed"] == 5 and st["resident_plans"] == 1
+    assert st[f"completed_fp{32 if prec == 0 else 64}"] == 5
+    for got, lmax, e, dd, rr, label in ((first, 4, e4, d, r, "first"), (second, 8, e8, d, r, "reused l<=8"),
+                                        (other, 4, e4, d2, r2, "host catalog"), (fourth, 4, e4, d, r, "repainted")):
+        assert_pole_parity(got, _oracle(n, lmax, dd, rr, e), prec, f"registered prec={prec} {label} vs oracle")
+        _close(got, _alone(n, prec, lmax, dd, rr, e), prec, f"registered prec={prec} {label}")
+    sv.unregister_catalog(cid)
+    assert sv.stats()["registered_catalogs"] == 0 and sv.stats()["registered_bytes"] == 0
+    with pytest.raises(PkmError) as exc:
+        sv.submit(n, L, 4, e4, catalog_id=cid, **kw)
+    assert exc.value.status == 1
+    with pytest.raises(PkmError) as exc:
+        sv.unregister_catalog(cid)
+    assert exc.value.status == 1
+    sv.close()
+
+
+def test_two_catalogs_each_keep_their_plan(gpu):
+    """Two registered catalogs served together land on two plans; served together again,
+    each request finds the plan holding its own painted field.  A catalog named by queued or
+    running requests cannot be unregistered."""
+    from paper_1704_02357_amd import PkmError, Server
+    n, prec, lmax = 48, 0, 4
+    cats = [small_catalogs(2000 + 1000 * i, 10000 + 4000 * i, L, seed=70 + i) for i in range(2)]
+    e = _edges(n)
+    sv = Server(max_inflight=2)
+    ids = [sv.register_catalog(d, r) for d, r in cats]
+    kw = dict(KW, precision=prec, ell_max_hint=lmax)
+    rounds = []
+    for rep in range(2):
+        ts = [sv.submit(n, L, lmax, e, catalog_id=c, **kw) for c in ids]
+        rounds.append([sv.wait(t) for t in ts])
+    st = sv.stats()
+    print(f"[server] {st}", flush=True)
+    assert st["resident_plans"] == 2 and st["mesh_reuses"] == 2
+    for i, (d, r) in enumerate(cats):
+        ref = _oracle(n, lmax, d, r, e)
+        for rep in range(2):
+            assert_pole_parity(rounds[rep][i], ref, prec, f"catalog {i} round {rep} vs oracle")
+        assert np.array_equal(np.asarray(rounds[0][i]["poles"]), np.asarray(rounds[1][i]["poles"]))
+    # queued work naming a catalog keeps it registered
+    ts = [sv.submit(n, L, lmax, e, catalog_id=ids[0], **kw) for _ in range(6)]
+    with pytest.raises(PkmError) as exc:
+        sv.unregister_catalog(ids[0])
+    assert exc.value.status == 5
+    for t in ts:
+        sv.wait(t)
+    sv.unregister_catalog(ids[0])
+    sv.unregister_catalog(ids[1])
+    sv.close()
+
+
+def test_admission_passes_a_request_blocked_on_memory(gpu):
+    """Budget: the footprint of one 128^3 plan plus a quarter of a 32^3 one.  Queued A (32^3), B (128^3), C (32^3,
+    another observer): B cannot run beside A, C can, so C is admitted past B while A runs and
+    B runs once both are done.  Every result equals the oracle, and the resident bytes stay
+    within the budget."""
+    from paper_1704_02357_amd import Server, plan_footprint
+    d, r = small_catalogs(2000, 10000, L, seed=11)
+    cat_bytes = (2000 + 10000) * 5 * 8
+    kw = dict(KW, precision=0, ell_max_hint=4, max_group=16)  # a set max_group: no automatic shrinking
+
+    def need(n):
+        return plan_footprint(n, L, 4, len(_edges(n)), 12000, **kw) + cat_bytes
+
+    small, big = need(32), need(128)
+    # A and C fit together, B fits alone; B beside a resident 32^3 plan (at least a quarter of
+    # its footprint) does not
+    budget = big + small // 4
+    sv = Server(max_inflight=3, hbm_budget_bytes=budget)
+    obs_c = (31.0, -40.0, -700.0)
+    reqs = [(32, OBS), (128, OBS), (32, obs_c)]
+    ts = [sv.submit(n, L, 4, _edges(n), d, r, **dict(kw, observer=o)) for n, o in reqs]
+    outs = [sv.wait(t) for t in ts]
+    st = sv.stats()
+    print(f"[server admission] budget={budget} small={small} big={big} {st}", flush=True)
+    assert st["completed"] == 3 and st["failed"] == 0
+    assert st["max_concurrent"] == 2 and st["peak_bytes"] <= budget
+    from oracle.estimator import multipoles
+    for (n, o), got in zip(reqs, outs):
+        ref = multipoles(d, r, oracle_params(n, L, o, 3, True, True), 4, _edges(n))
+        assert_pole_parity(got, ref, 0, f"admission n={n} observer={o}")
+    sv.close()
+
+
+class _FailingAllocator:
+    """torch's caching allocator, refusing every allocation above a size limit."""
+
+    def __init__(self, limit):
+        from paper_1704_02357_amd.pkm import _TorchAllocator
+        self.inner = _TorchAllocator(0)
+        self.limit = limit
+        self.refused = 0
+        from paper_1704_02357_amd.pkm import ALLOC_FN, FREE_FN
+        self.c_alloc = ALLOC_FN(self._alloc)
+        self.c_free = FREE_FN(self.inner._free)
+
+    def _alloc(self, size, stream, ctx):
+        if size > self.limit:
+            self.refused += 1
+            return None
+        return self.inner._alloc(size, stream, ctx)
+
+
+def test_allocator_failure_fails_one_request_alone(gpu):
+    """A server whose allocator refuses buffers above 4 MB (a 128^3 field is 8.5 MB, a 64^3
+    one 1.1 MB): the 128^3 request fails with PKM_ENOMEM, the requests beside it and after it
+    complete and equal the oracle and their estimates alone."""
+    from paper_1704_02357_amd import PkmError, Server
+    alloc = _FailingAllocator(4 << 20)
+    sv = Server(max_inflight=3, allocator=alloc)
+    plan = [(64, 0, 4), (128, 0, 4), (32, 1, 6), (64, 0, 2)]
+    cats = [small_catalogs(2000 + 300 * i, 9000, L, seed=500 + i) for i in range(len(plan))]
+    ts = [sv.submit(n, L, lmax, _edges(n), d, r, precision=prec, ell_max_hint=lmax, **KW)
+          for (n, prec, lmax), (d, r) in zip(plan, cats)]
+    outs = []
+    for i, t in enumerate(ts):
+        if plan[i][0] == 128:
+            with pytest.raises(PkmError) as exc:
+                sv.wait(t)
+            assert exc.value.status == 3
+            outs.append(None)
+        else:
+            outs.append(sv.wait(t))
+    assert alloc.refused >= 1
+    late = sv.wait(sv.submit(64, L, 4, _edges(64), *cats[0], precision=0, ell_max_hint=4, **KW))
+    st = sv.stats()
+    print(f"[server allocator] {st}", flush=True)
+    assert st["failed"] == 1 and st["completed"] == 4
+    assert st["completed_fp32"] == 3 and st["completed_fp64"] == 1
+    assert st["latency_p50_ms_fp32"] > 0 and st["latency_p50_ms_fp64"] > 0
+    for (n, prec, lmax), (d, r), got in zip(plan, cats, outs):
+        if got is None:
+            continue
+        assert_pole_parity(got, _oracle(n, lmax, d, r, _edges(n)), prec, f"beside a failed request n={n}")
+        _close(got, _alone(n, prec, lmax, d, r, _edges(n)), prec, f"beside a failed request n={n}")
+    _close(late, outs[0], 0, "after a failed request")
+    sv.close()
