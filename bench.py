@@ -535,66 +535,128 @@ def covariance_bench(args) -> dict:
                                    "l<=16, 9 uniform / 9 non-uniform wedges"}, **out}
 
 
-def serve_bench(args) -> dict:
-    """Poisson-arrival request stream mixing Nmesh 256-768, l_max 4/8/16, 1e5-3e6 galaxies
-    (2x randoms), FP32 and FP64, through the serving loop; throughput and latency."""
-    import threading
-    from paper_1704_02357_amd import Server
+def serve_pool(n_catalogs: int, random_factor: float):
+    """The serving workload's catalog pool: seeded lognormal surveys (L = 2500 Mpc/h, seeds
+    3000 + j) with N_gal log-uniform in [1e5, 3e6] and random_factor x randoms, generated on
+    host threads."""
+    from concurrent.futures import ThreadPoolExecutor
     from synth import SurveyGeometry, lognormal_survey
-    rng = np.random.default_rng(2026)
+    geom = SurveyGeometry(box_len=2500.0)
+    ngal = np.exp(np.random.default_rng(3000).uniform(math.log(1e5), math.log(3e6), n_catalogs))
+    done = [0]
+
+    def one(j):
+        d, r, _ = lognormal_survey(geom, int(ngal[j]), 3000 + j, ng=128, random_factor=random_factor, workers=2)
+        done[0] += 1
+        log(f"[serve] catalog {j}: {len(d.pos)} galaxies, {len(r.pos)} randoms ({done[0]} of {n_catalogs} done)")
+        return d, r
+
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        return list(ex.map(one, range(n_catalogs)))
+
+
+def serve_bench(args) -> dict:
+    """Serving workload in one precision form: a pool of registered catalogs, requests that
+    each pick a catalog, Nmesh in {256, 384, 512, 768} and l_max in {4, 8, 16} uniformly.
+    The capacity is measured first by a closed burst (every request queued at once); then
+    Poisson streams arrive at the given fractions of that capacity, each reporting
+    throughput and p50/p99 latency (submit to result)."""
+    from paper_1704_02357_amd import Server
+    prec = args.serve_precision
     L = 2500.0
-    geom = SurveyGeometry(box_len=L)
     t0 = time.perf_counter()
-    pool = [lognormal_survey(geom, int(ng), 4000 + i, ng=128, random_factor=2.0)[:2]
-            for i, ng in enumerate(np.geomspace(1e5, 3e6, 5))]
-    log(f"[serve] catalog pool generated in {time.perf_counter() - t0:.1f} s")
+    pool = serve_pool(args.catalogs, args.serve_random_factor)
+    log(f"[serve] pool of {len(pool)} catalogs generated in {time.perf_counter() - t0:.0f} s")
     sizes, lmaxes = [256, 384, 512, 768], [4, 8, 16]
-    reqs = []
-    for i in range(args.requests):
-        n = int(rng.choice(sizes))
-        lmax = int(rng.choice(lmaxes))
-        prec = int(rng.integers(0, 2))
-        d, r = pool[int(rng.integers(0, len(pool)))]
-        edges = np.arange(int(math.floor(math.pi * n / L / 0.01)) + 1, dtype=np.float64) * 0.01
-        reqs.append((n, lmax, prec, d, r, edges))
-    gaps = rng.exponential(1.0 / args.rate, size=len(reqs))
     sv = Server(max_inflight=args.inflight)
-    tickets = [None] * len(reqs)
+    ids = [sv.register_catalog(d, r) for d, r in pool]
+    n_obj = sum(len(d.pos) + len(r.pos) for d, r in pool)
+    reg = sv.stats()["registered_bytes"]
+    log(f"[serve] {len(ids)} catalogs registered, {n_obj} objects, {reg / 2 ** 30:.1f} GiB resident")
+    del pool
+    rng = np.random.default_rng(2026 + prec)
 
-    def submitter():
-        start = time.perf_counter()
-        due = 0.0
-        for i, (n, lmax, prec, d, r, edges) in enumerate(reqs):
-            due += gaps[i]
-            delay = start + due - time.perf_counter()
-            if delay > 0:
-                time.sleep(delay)
-            tickets[i] = sv.submit(n, L, lmax, edges, d, r, observer=OBSERVER, window=3, interlaced=True,
-                                   compensated=True, precision=prec, ell_max_hint=lmax)
-            if (i + 1) % 50 == 0:
-                log(f"[serve] {i + 1} of {len(reqs)} requests submitted at {time.perf_counter() - start:.0f} s, "
-                    f"{sv.stats()['completed']} completed")
+    def draw(k):
+        out = []
+        for _ in range(k):
+            n, lmax = int(rng.choice(sizes)), int(rng.choice(lmaxes))
+            edges = np.arange(int(math.floor(math.pi * n / L / 0.01)) + 1, dtype=np.float64) * 0.01
+            out.append((n, lmax, int(rng.integers(0, len(ids))), edges))
+        return out
 
-    s0 = time.perf_counter()
-    th = threading.Thread(target=submitter)
-    th.start()
-    th.join()
-    for i, t in enumerate(tickets):
-        sv.wait(t)
-        if (i + 1) % 100 == 0:
-            log(f"[serve] {i + 1} of {len(reqs)} results collected at {time.perf_counter() - s0:.0f} s")
-    wall = time.perf_counter() - s0
+    def submit(req):
+        n, lmax, j, edges = req
+        return sv.submit(n, L, lmax, edges, catalog_id=ids[j], observer=OBSERVER, window=3, interlaced=True,
+                         compensated=True, precision=prec, ell_max_hint=lmax)
+
+    def stream(reqs, rate, label):
+        """Submit at Poisson arrivals (rate 0: all at once) from a thread; wait for all.  The
+        server's statistics are reset first, so latency covers this stream only."""
+        import threading
+        sv.reset_stats()
+        gaps = rng.exponential(1.0 / rate, size=len(reqs)) if rate > 0 else np.zeros(len(reqs))
+        tickets = [None] * len(reqs)
+
+        def submitter():
+            start, due = time.perf_counter(), 0.0
+            for i, rq in enumerate(reqs):
+                due += gaps[i]
+                delay = start + due - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                tickets[i] = (submit(rq), time.perf_counter())
+
+        s0 = time.perf_counter()
+        th = threading.Thread(target=submitter)
+        th.start()
+        done = 0
+        while done < len(reqs):
+            while tickets[done] is None:
+                time.sleep(0.001)
+            sv.wait(tickets[done][0])
+            done += 1
+            if done % 50 == 0:
+                log(f"[serve] {label}: {done} of {len(reqs)} results at {time.perf_counter() - s0:.0f} s")
+        th.join()
+        wall = time.perf_counter() - s0
+        st = sv.stats()
+        form = "fp64" if prec else "fp32"
+        return {"requests": len(reqs), "arrival_rate_per_s": round(rate, 3), "wall_s": round(wall, 2),
+                "served_per_s": round(len(reqs) / wall, 3), "completed": st["completed"], "failed": st["failed"],
+                "latency_ms": {"p50": round(st[f"latency_p50_ms_{form}"], 2),
+                               "p99": round(st[f"latency_p99_ms_{form}"], 2), "mean": round(st["latency_mean_ms"], 2)},
+                "max_concurrent": st["max_concurrent"], "mesh_reuses": st["mesh_reuses"]}
+
+    # warm the plan pool (one request per (N, l_max) configuration), then the capacity burst
+    warm = [(n, lmax, k % len(ids), np.arange(int(math.floor(math.pi * n / L / 0.01)) + 1, dtype=np.float64) * 0.01)
+            for k, (n, lmax) in enumerate((n, l) for n in sizes for l in lmaxes)]
+    for rq in warm:
+        sv.wait(submit(rq))
+    log(f"[serve] plan pool warmed: {sv.stats()['resident_plans']} plans")
+    burst = stream(draw(args.burst), 0.0, "capacity burst")
+    capacity = burst["served_per_s"]
+    log(f"[serve] capacity {capacity:.3f} requests/s")
+    runs = []
+    for frac in args.load_fractions:
+        n_req = args.requests if abs(frac - 0.8) < 1e-9 else args.sweep_requests
+        if args.stream_seconds:  # shorten the stream to about that many seconds of arrivals
+            n_req = max(20, min(n_req, int(args.stream_seconds * frac * capacity)))
+        runs.append(dict(stream(draw(n_req), frac * capacity, f"stream at {frac} x capacity"), load_fraction=frac))
+        log(f"[serve] {runs[-1]}")
     st = sv.stats()
     sv.close()
-    return {"metric": "served P_l(k) requests/s (Poisson stream, Nmesh 256-768, l_max 4/8/16, FP32+FP64), "
+    main = next((r for r in runs if abs(r["load_fraction"] - 0.8) < 1e-9), runs[0] if runs else burst)
+    form = "fp64" if prec else "fp32"
+    return {"metric": f"served P_l(k) requests/s, {form.upper()} form (Poisson stream at 0.8 x capacity), "
                       "p50/p99 latency",
-            "value": round(len(reqs) / wall, 3), "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
-            "latency_ms": {"p50": round(st["latency_p50_ms"], 2), "p99": round(st["latency_p99_ms"], 2),
-                           "mean": round(st["latency_mean_ms"], 2)},
-            "server": {k: st[k] for k in ("completed", "failed", "max_concurrent", "resident_plans", "peak_bytes")},
-            "dtype": "f32+f64", "data": "synthetic (seeded lognormal catalogs, 5 sizes 1e5-3e6 galaxies, 2x randoms)",
-            "config": {"workload": f"{len(reqs)} requests, Poisson arrivals at {args.rate}/s, Nmesh in {sizes}, "
-                                   f"l_max in {lmaxes}, half FP32 / half FP64, L=2500 Mpc/h",
+            "value": main["served_per_s"], "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
+            "latency_ms": main["latency_ms"], "capacity_per_s": capacity, "capacity_burst": burst, "streams": runs,
+            "server": {k: st[k] for k in ("resident_plans", "peak_bytes", "registered_catalogs", "registered_bytes")},
+            "dtype": "f64" if prec else "f32",
+            "data": f"synthetic (seeded lognormal surveys, {args.catalogs} catalogs, N_gal log-uniform 1e5-3e6, "
+                    f"{args.serve_random_factor:g}x randoms, registered once)",
+            "config": {"workload": f"per request: catalog, Nmesh in {sizes}, l_max in {lmaxes} uniform; "
+                                   f"L=2500 Mpc/h, TSC + interlacing, dk=0.01; {form.upper()}",
                        "max_inflight": args.inflight}}
 
 
@@ -618,8 +680,16 @@ def main():
                          "basis: spherical against Cartesian decomposition; covariance: Kaiser-mock wedge "
                          "covariance; fft: the 3D transform against ROCm's FFT library")
     ap.add_argument("--mocks", type=int, default=64)
-    ap.add_argument("--requests", type=int, default=48)
-    ap.add_argument("--rate", type=float, default=1.0, help="request arrivals per second (serve mode)")
+    ap.add_argument("--requests", type=int, default=2000, help="serve mode: requests of the 0.8 x capacity stream")
+    ap.add_argument("--sweep-requests", type=int, default=200, help="serve mode: requests of the other streams")
+    ap.add_argument("--burst", type=int, default=100, help="serve mode: requests of the capacity burst")
+    ap.add_argument("--load-fractions", type=lambda v: [float(x) for x in v.split(",")], default=[0.8, 0.5, 1.2],
+                    help="serve mode: arrival rates as fractions of the measured capacity")
+    ap.add_argument("--stream-seconds", type=float, default=None,
+                    help="serve mode: cap each stream at about this many seconds of arrivals")
+    ap.add_argument("--catalogs", type=int, default=32, help="serve mode: registered catalogs")
+    ap.add_argument("--serve-random-factor", type=float, default=10.0)
+    ap.add_argument("--serve-precision", type=int, choices=[0, 1], default=0, help="serve mode: 0 FP32, 1 FP64")
     ap.add_argument("--inflight", type=int, default=4)
     args = ap.parse_args()
     if args.summarize_profile:

@@ -35,7 +35,8 @@
  *   distinct plans are independent.
  *
  * Errors.  Every function returns a pkm_status; nothing aborts or throws across the ABI.
- *   On error the outputs are untouched and pkm_plan_last_error() holds a message.
+ *   On error the outputs are untouched and pkm_plan_last_error() holds a message;
+ *   pkm_plan_last_error(NULL) gives why the calling thread's last plan creation failed.
  *   PKM_EINVAL leaves the plan unchanged, except for the normalisation check of painting
  *   (pkm_paint, pkm_finish), which leaves it unpainted.  After PKM_EDEVICE the plan must be
  *   destroyed.
@@ -422,6 +423,9 @@ void pkm_batch_destroy(pkm_batch* batch);
  *                      latency percentiles (submit to completion, ms) over all requests and
  *                      per precision, throughput, requests served from a held painted field,
  *                      registered catalogs and their bytes.
+ *   pkm_server_reset_stats  starts the statistics afresh (counts, latencies, the largest
+ *                      concurrency, the peak bytes and the throughput window); requests
+ *                      in flight when it is called count when they finish.
  *   pkm_server_destroy finishes the requests in flight, cancels queued ones, frees all
  *                      (registered catalogs included).
  * The server functions are thread safe.
@@ -470,6 +474,7 @@ pkm_status pkm_server_submit(pkm_server* server, const pkm_request* request, int
 pkm_status pkm_server_poll(pkm_server* server, int64_t ticket, pkm_result* out);
 pkm_status pkm_server_wait(pkm_server* server, int64_t ticket, pkm_result* out);
 pkm_status pkm_server_stats(pkm_server* server, pkm_server_stats_t* out);
+pkm_status pkm_server_reset_stats(pkm_server* server);
 const char* pkm_server_last_error(const pkm_server* server);
 void pkm_server_destroy(pkm_server* server);
 

@@ -1345,6 +1345,11 @@ int64_t footprint(const pkm_params* p, int ell_max, int n_edges, int64_t n_parti
 // -------------------------------------------------------------------------------------------
 // C ABI
 // -------------------------------------------------------------------------------------------
+namespace {
+// why the calling thread's last pkm_plan_create failed (pkm_plan_last_error(NULL))
+thread_local std::string g_create_err = "no plan";
+}  // namespace
+
 extern "C" {
 
 int pkm_abi_version(void) { return PKM_ABI_VERSION; }
@@ -1380,17 +1385,18 @@ pkm_status pkm_plan_create(const pkm_params* p, const pkm_device* dev, pkm_plan*
 
 pkm_status pkm_plan_create_shaped(const pkm_params* p, const pkm_device* dev, const pkm_shape* shape,
                                   pkm_plan** out) {
+  g_create_err = "no plan";
   if (!out) return PKM_EINVAL;
   std::string why;
   pkm_status st = validate_params(p, &why);
-  if (st != PKM_OK) return st;
+  if (st != PKM_OK) { g_create_err = why; return st; }
   FftShape fs0{};
   int ts0 = 8;
-  if (!make_shape(*p, &fs0)) return PKM_EINVAL;
+  if (!make_shape(*p, &fs0)) { g_create_err = "no launch shape for these parameters"; return PKM_EINVAL; }
   while (p->nmesh % ts0) ts0 /= 2;
-  if (shape && !apply_shape(*p, *shape, &fs0, &ts0, &why)) return PKM_EINVAL;
+  if (shape && !apply_shape(*p, *shape, &fs0, &ts0, &why)) { g_create_err = why; return PKM_EINVAL; }
   pkm_plan* pl = new (std::nothrow) pkm_plan();
-  if (!pl) return PKM_ENOMEM;
+  if (!pl) { g_create_err = "host allocation failed"; return PKM_ENOMEM; }
   pl->p = *p;
   pl->frame = harmonic_frame(pl->p);
   if (pl->p.ell_max_hint == 0) pl->p.ell_max_hint = 4;
@@ -1438,6 +1444,7 @@ pkm_status pkm_plan_create_shaped(const pkm_params* p, const pkm_device* dev, co
     if (pl->fp64) upload_tables<double>(pl); else upload_tables<float>(pl);
   });
   if (st != PKM_OK) {
+    g_create_err = pl->err;
     free_all(pl);
     delete pl;
     return st;
@@ -1568,7 +1575,7 @@ pkm_status pkm_reset_stats(pkm_plan* pl) {
   return PKM_OK;
 }
 
-const char* pkm_plan_last_error(const pkm_plan* pl) { return pl ? pl->err.c_str() : "no plan"; }
+const char* pkm_plan_last_error(const pkm_plan* pl) { return pl ? pl->err.c_str() : g_create_err.c_str(); }
 
 void pkm_plan_destroy(pkm_plan* pl) {
   if (!pl) return;

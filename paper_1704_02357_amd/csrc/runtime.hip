@@ -305,10 +305,28 @@ bool same_key(const PlanKey& a, const PlanKey& b) { return !(a < b) && !(b < a);
 // a catalog buffer does not wait for the estimates in flight on other streams.  An allocation
 // waits for its own stream only (idle when a plan is created or grown), so the memory is ready
 // for the plan's table uploads, which are not ordered on that stream.
+thread_local hipError_t g_pool_err = hipSuccess;  // the worker's last pool failure
+
+// Hand the free memory the current device's pool keeps back to the device.
+void trim_pool() {
+  int dev = 0;
+  hipMemPool_t pool = nullptr;
+  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool)
+    (void)hipMemPoolTrimTo(pool, 0);
+  (void)hipGetLastError();
+}
+
 void* pool_alloc(size_t bytes, void* stream, void*) {
   void* p = nullptr;
-  if (hipMallocAsync(&p, bytes, (hipStream_t)stream) != hipSuccess ||
-      hipStreamSynchronize((hipStream_t)stream) != hipSuccess) {
+  hipError_t e = hipMallocAsync(&p, bytes, (hipStream_t)stream);
+  if (e == hipErrorOutOfMemory) {  // the pool's kept free blocks may not fit: release them, retry once
+    (void)hipGetLastError();
+    trim_pool();
+    e = hipMallocAsync(&p, bytes, (hipStream_t)stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) {
+    g_pool_err = e;
     (void)hipGetLastError();
     if (p) (void)hipFreeAsync(p, (hipStream_t)stream);
     return nullptr;
@@ -415,11 +433,36 @@ std::unique_ptr<PinnedBuf> take_pinned(pkm_server* sv) {
   return std::unique_ptr<PinnedBuf>(new (std::nothrow) PinnedBuf());
 }
 
-// Evict an idle slot: its plan and catalog buffer go back to the pool on its own stream, its
-// pinned buffers to the server's spares (freeing pinned memory would synchronise the device).
+// The device's pool keeps the blocks of evicted plans for reuse, and reserves fresh memory when
+// those do not fit a new plan's buffers.  Its reserved bytes (live plus kept) are held within
+// the plan budget (the server budget less the registered catalogs), less `extra` bytes about to
+// be allocated, so the device keeps the headroom outside the budget that the runtime itself
+// needs (scratch for kernel launches, queues).  Kept blocks are released, live ones never.
+void bound_pool(const pkm_server* sv, int64_t extra) {
+  if (sv->cfg.alloc) return;
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, sv->cfg.device_id) != hipSuccess || !pool) {
+    (void)hipGetLastError();
+    return;
+  }
+  uint64_t reserved = 0;
+  if (hipMemPoolGetAttribute(pool, hipMemPoolAttrReservedMemCurrent, &reserved) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  const int64_t bound = std::max<int64_t>(0, sv->cfg.hbm_budget_bytes - sv->cat_bytes - extra);
+  if ((int64_t)reserved > bound) (void)hipMemPoolTrimTo(pool, (size_t)bound);
+  (void)hipGetLastError();
+}
+
+// Evict an idle slot: its plan and catalog buffer go back to the pool on its own stream (which
+// runs nothing else, so waiting for it waits for the frees only and lets any stream reuse the
+// blocks at once), its pinned buffers to the server's spares (freeing pinned memory would
+// synchronise the device).
 void free_slot(pkm_server* sv, Slot* s) {
   pkm_plan_destroy(s->plan);
   dev_free(sv, s->dev_cat, s->stream);
+  (void)hipStreamSynchronize(s->stream);
   (void)hipStreamDestroy(s->stream);
   if (s->stage) sv->spare_pinned.push_back(std::move(s->stage));
   if (s->result) sv->spare_pinned.push_back(std::move(s->result));
@@ -516,7 +559,9 @@ pkm_status start_request(pkm_server* sv, Request* r, Slot* sl, const double* reg
     const pkm_status st = pkm_plan_create(&pp, &dev, &sl->plan);
     if (st != PKM_OK) {
       sl->plan = nullptr;
-      r->err = "plan creation failed";
+      r->err = std::string("plan creation failed: ") + pkm_plan_last_error(nullptr);
+      if (g_pool_err != hipSuccess) r->err += std::string(" (") + hipGetErrorString(g_pool_err) + ")";
+      g_pool_err = hipSuccess;
       return st;
     }
   }
@@ -632,9 +677,11 @@ bool admit_some(pkm_server* sv, std::unique_lock<std::mutex>& lk) {
     }
     slot->busy = true;
     sv->resident += need;  // reserved until the plan's size is known
+    bound_pool(sv, need);
     lk.unlock();           // device work below; clients touch only the queue and the results
     pkm_status st = start_request(sv, r.get(), slot, reg_base);
     lk.lock();
+    bound_pool(sv, 0);
     sv->resident -= need;
     if (slot->plan) {
       const int64_t b = pkm_internal::device_bytes(slot->plan) + (int64_t)slot->dev_cap * 8;
@@ -772,11 +819,15 @@ pkm_status pkm_server_create(const pkm_server_config* cfg, pkm_server** out) {
     }
     sv->cfg.hbm_budget_bytes = (int64_t)(0.8 * (double)free_b);
   }
-  // keep freed plan memory in the device's pool for the next plan instead of returning it
+  // keep freed plan memory in the device's pool for the next plan instead of returning it,
+  // reusable by any stream once its free has completed
   hipMemPool_t pool = nullptr;
   if (hipDeviceGetDefaultMemPool(&pool, cfg->device_id) == hipSuccess && pool) {
-    uint64_t keep = (uint64_t)sv->cfg.hbm_budget_bytes;
+    uint64_t keep = (uint64_t)sv->cfg.hbm_budget_bytes;  // bound_pool keeps it within the plan budget
+    int yes = 1;
     (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolReuseAllowOpportunistic, &yes);
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolReuseAllowInternalDependencies, &yes);
   }
   (void)hipGetLastError();
   try {
@@ -829,6 +880,11 @@ pkm_status pkm_server_register_catalog(pkm_server* sv, const pkm_catalog* data, 
   }
   hipError_t e = hipSetDevice(sv->cfg.device_id);
   if (e == hipSuccess) e = hipMalloc((void**)&rc.dev, std::max<size_t>(total, 1) * sizeof(double));
+  if (e == hipErrorOutOfMemory) {  // free blocks kept by the plans' pool: release them, retry once
+    (void)hipGetLastError();
+    trim_pool();
+    e = hipMalloc((void**)&rc.dev, std::max<size_t>(total, 1) * sizeof(double));
+  }
   if (e == hipSuccess) {
     double* p = rc.dev;
     auto put = [&](const double* src, int64_t count) {
@@ -855,6 +911,7 @@ pkm_status pkm_server_register_catalog(pkm_server* sv, const pkm_catalog* data, 
   *cat_id = sv->next_cat++;
   sv->cat_bytes += rc.bytes;
   sv->cats[*cat_id] = rc;
+  bound_pool(sv, 0);
   return PKM_OK;
 }
 
@@ -1017,6 +1074,19 @@ pkm_status pkm_server_stats(pkm_server* sv, pkm_server_stats_t* out) {
   out->mesh_reuses = sv->mesh_reuses;
   out->registered_catalogs = (int64_t)sv->cats.size();
   out->registered_bytes = sv->cat_bytes;
+  return PKM_OK;
+}
+
+pkm_status pkm_server_reset_stats(pkm_server* sv) {
+  if (!sv) return PKM_EINVAL;
+  std::lock_guard<std::mutex> g(sv->mu);
+  sv->latencies_ms.clear();
+  sv->latencies_prec[0].clear();
+  sv->latencies_prec[1].clear();
+  sv->completed = sv->failed = sv->mesh_reuses = 0;
+  sv->max_concurrent = (int)sv->inflight.size();
+  sv->peak_resident = sv->resident;
+  sv->any_submit = false;
   return PKM_OK;
 }
 

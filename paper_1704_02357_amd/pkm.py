@@ -160,6 +160,7 @@ def load_library():
         "pkm_server_poll": (C.c_int, [P, C.c_int64, C.POINTER(Result)]),
         "pkm_server_wait": (C.c_int, [P, C.c_int64, C.POINTER(Result)]),
         "pkm_server_stats": (C.c_int, [P, C.POINTER(ServerStats)]),
+        "pkm_server_reset_stats": (C.c_int, [P]),
         "pkm_server_last_error": (C.c_char_p, [P]),
         "pkm_server_destroy": (None, [P]),
     }
@@ -588,6 +589,9 @@ class Server:
         s = ServerStats()
         self._check(self.lib.pkm_server_stats(self.h, C.byref(s)), "pkm_server_stats")
         return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def reset_stats(self):
+        self._check(self.lib.pkm_server_reset_stats(self.h), "pkm_server_reset_stats")
 
     def close(self):
         if getattr(self, "h", None):
