@@ -372,11 +372,20 @@ def batch_bench(args) -> dict:
     seq = {n: Plan(n, L, observer=OBSERVER, window=3, interlaced=True, compensated=True, precision=0,
                    ell_max_hint=lmax) for n in maxp}
     errs = []
+    model_bytes = 0.0
+    by_size = {}  # n -> [estimates, device ms, model bytes]
     torch.cuda.synchronize()
     s0 = time.perf_counter()
     for i, (d, r, info, n) in enumerate(mocks):
         seq[n].paint(cats[i][0], cats[i][1])
         ref = seq[n].compute_multipoles(lmax, edges[n])
+        st = seq[n].stats()
+        mb = st["model_bytes_paint"] + st["model_bytes_compute"]
+        model_bytes += mb
+        acc = by_size.setdefault(n, [0, 0.0, 0.0])
+        acc[0] += 1
+        acc[1] += st["ms_paint"] + st["ms_compute"]
+        acc[2] += mb
         got = b.result(i)
         scale = np.maximum(np.abs(ref["poles"]), np.abs(ref["poles"][0] + ref["shot_noise"])[None, :])
         ok = np.isfinite(ref["poles"])
@@ -384,6 +393,9 @@ def batch_bench(args) -> dict:
     torch.cuda.synchronize()
     t_seq = (time.perf_counter() - s0) * 1e3
     med = float(np.median(t_graph))
+    sizes_out = {str(n): {"estimates": a[0], "ms_per_estimate_sync": round(a[1] / a[0], 3),
+                          "model_gb_per_s_sync": round(a[2] / (a[1] * 1e-3) / 1e9, 1)}
+                 for n, a in sorted(by_size.items())}
     for p in list(plans.values()) + list(seq.values()):
         p.close()
     b.close()
@@ -391,12 +403,61 @@ def batch_bench(args) -> dict:
                       "one graph launch)",
             "value": round(n_mocks / (med * 1e-3), 2), "unit": "estimates/s", "n_gpus": 1, "steps": args.steps,
             "ms_per_batch_graph": round(med, 2), "ms_per_batch_direct": round(t_direct, 2),
-            "ms_per_batch_sequential_sync": round(t_seq, 2), "higher_is_better": True, "dtype": "f32",
+            "ms_per_batch_sequential_sync": round(t_seq, 2),
+            "model_gb_per_batch": round(model_bytes / 1e9, 2),
+            "model_gb_per_s_graph": round(model_bytes / (med * 1e-3) / 1e9, 1),
+            "per_size": sizes_out, "higher_is_better": True, "dtype": "f32",
             "data": "synthetic (seeded lognormal mocks, resident in HBM)",
             "config": {"workload": f"{n_mocks} mocks, Nmesh cycling 128/256/384, L=2000 Mpc/h, 5e4-8e5 galaxies, "
                                    "10x randoms, TSC + interlacing + compensation, l<=4, 0.01 h/Mpc bins",
                        "plans_per_size": per_size},
             "max_scaled_err_vs_sequential": max(errs)}
+
+
+def sizes_bench(args) -> dict:
+    """The radix-3 mesh sizes of the batch and serving workloads, one estimate at a time in
+    both forms: Nmesh 384 (L = 2000 Mpc/h, a covariance mock of 8e5 galaxies) and 768
+    (L = 2500 Mpc/h, 3e6 galaxies, the largest served catalog), 10x randoms, TSC + interlacing
+    + compensation, l <= 4.  Device time of paint and multipoles per estimate (the last of
+    `steps` after `warmup`), the byte model's rate, and the per-stage times of one more
+    estimate with per-launch timing on."""
+    import torch
+    from paper_1704_02357_amd import Plan
+    from synth import SurveyGeometry, lognormal_survey
+    rows = []
+    for n, box, ngal in ((384, 2000.0, 800_000), (768, 2500.0, 3_000_000)):
+        d, r, _ = lognormal_survey(SurveyGeometry(box_len=box), ngal, 2000 + n, ng=256)
+        log(f"[sizes] {n}^3: {len(d.pos)} galaxies, {len(r.pos)} randoms")
+        dev = lambda c: (torch.tensor(c.pos, device="cuda"), torch.tensor(c.w, device="cuda"),
+                         torch.tensor(c.nbar, device="cuda"))
+        dd, rr = dev(d), dev(r)
+        edges = np.arange(int(math.floor(math.pi * n / box / 0.01)) + 1, dtype=np.float64) * 0.01
+        for prec in (0, 1):
+            p = Plan(n, box, observer=OBSERVER, window=3, interlaced=True, compensated=True, precision=prec,
+                     ell_max_hint=4)
+            for _ in range(args.warmup + args.steps):
+                p.paint(dd, rr)
+                p.compute_multipoles(4, edges)
+            st = p.stats()
+            p.set_stage_timing(True)
+            p.reset_stats()
+            p.paint(dd, rr)
+            p.compute_multipoles(4, edges)
+            stages = {k: round(v, 3) for k, v in p.stats()["stage_ms"].items() if v > 0}
+            shape = p.shape()
+            p.close()
+            ms = st["ms_paint"] + st["ms_compute"]
+            gb = (st["model_bytes_paint"] + st["model_bytes_compute"]) / 1e9
+            rows.append({"nmesh": n, "dtype": "f64" if prec else "f32", "ms_paint": round(st["ms_paint"], 3),
+                         "ms_multipoles": round(st["ms_compute"], 3), "model_gb": round(gb, 2),
+                         "model_gb_per_s": round(gb / (ms * 1e-3), 1), "stage_ms": stages, "shape": shape})
+            log(f"[sizes] {rows[-1]}")
+    return {"metric": "P_l(k) estimates/s at the radix-3 sizes (384^3, 768^3, l<=4), per form",
+            "value": round(1e3 / (rows[0]["ms_paint"] + rows[0]["ms_multipoles"]), 2), "unit": "estimates/s (384^3 FP32)",
+            "higher_is_better": True, "n_gpus": 1, "dtype": "f32+f64", "data": "synthetic (seeded lognormal surveys)",
+            "config": {"workload": "384^3 (L=2000, 8e5 galaxies) and 768^3 (L=2500, 3e6 galaxies), 10x randoms, "
+                                   "TSC + interlacing + compensation, l<=4, dk=0.01"},
+            "rows": rows}
 
 
 def basis_bench(args) -> dict:
@@ -445,13 +506,20 @@ def basis_bench(args) -> dict:
 
 
 def covariance_study(n: int = 128, box_len: float = 1000.0, n_mocks: int = 1000, beta: float = 0.35,
-                     k_range=(0.1, 0.35), n_plans: int = 4, per_plan: int = 8, seed0: int = 10_000) -> dict:
+                     k_range=(0.1, 0.35), n_plans: int = 4, per_plan: int = 8, seed0: int = 10_000,
+                     theory=None) -> dict:
     """Sec. 4.1 on the GPU: Gaussian Kaiser mocks (synth.kaiser) estimated to l <= 16 in batches
     replayed as one HIP graph, wedges from l <= 4 and l <= 16 with uniform and non-uniform mu
     bins (9 each), their correlation matrices over the mocks (averaged over the k bins in
-    k_range) against linear theory (eq. gamma), and condition numbers for N_mu = l_max/2 + 1."""
+    k_range) against linear theory (eq. gamma), and condition numbers for N_mu = l_max/2 + 1.
+
+    theory: None (the library's host functions) or a pair (gamma, wedges) with the signatures
+    gamma(l_max, mu_edges, beta) and wedges(poles, l_max, mu_edges), used for the theory
+    matrices and for turning the measured multipoles into wedges."""
     import torch
     from paper_1704_02357_amd import NGP, Batch, Plan, kaiser_wedge_gamma, nonuniform_mu_edges, wedges
+    if theory is not None:
+        kaiser_wedge_gamma, wedges = theory
     from synth.kaiser import KaiserBox, node_positions
     far = (0.0, 0.0, -1.0e9)   # line of sight along z everywhere
     edges = np.arange(int(math.floor(math.pi * n / box_len / 0.01)) + 1, dtype=np.float64) * 0.01
@@ -675,7 +743,8 @@ def main():
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="print the kernel summary of a rocprofv3 CSV output directory and exit")
     ap.add_argument("--cov-mocks", type=int, default=1000, help="mocks of the covariance mode")
-    ap.add_argument("--mode", choices=["estimate", "batch", "serve", "basis", "covariance", "fft"], default="estimate",
+    ap.add_argument("--mode", choices=["estimate", "batch", "serve", "basis", "covariance", "fft", "sizes"],
+                    default="estimate",
                     help="estimate: the 512^3 l<=4 line (default); batch: covariance mocks; serve: request stream; "
                          "basis: spherical against Cartesian decomposition; covariance: Kaiser-mock wedge "
                          "covariance; fft: the 3D transform against ROCm's FFT library")
@@ -704,7 +773,7 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     if args.mode != "estimate":
-        out = {"batch": batch_bench, "serve": serve_bench, "basis": basis_bench,
+        out = {"batch": batch_bench, "serve": serve_bench, "basis": basis_bench, "sizes": sizes_bench,
                "covariance": covariance_bench, "fft": fft_bench}[args.mode](args)
         print(json.dumps(out), flush=True)
         return

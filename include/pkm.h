@@ -78,7 +78,15 @@ enum { PKM_LOS_LOCAL = 0, PKM_LOS_GLOBAL = 1 };
  *   compensated  0/1: divide the combined field by the assignment window.
  *   precision    PKM_FP32 (FP32 meshes/transforms, FP64 index math and sums) or PKM_FP64.
  *   ell_max_hint largest ell_max later requested (sizes the field buffers); 0 means 4.
- *   max_group    upper bound on weighted fields kept in HBM at once; 0 = automatic.      */
+ *   max_group    upper bound on weighted fields kept in HBM at once; 0 = automatic.
+ *   deterministic 0/1: bitwise-repeatable estimates.  Painting then rounds every tap to a
+ *                multiple of 1/s of one fixed-point scale s shared by all tiles (chosen per
+ *                paint so that no node's sum can exceed 2^60 / s) and sums the integers in
+ *                LDS and in 64-bit accumulators (8 N^3 bytes per mesh, allocated with the
+ *                plan), so no floating-point addition depends on scheduling; the post-pass
+ *                keeps one histogram per wavefront (PKM_ENOMEM when that does not fit LDS).
+ *                Slower; the environment variable PKM_DETERMINISTIC=1 turns it on for
+ *                every plan.  pkm_kmu_global is not covered.                              */
 typedef struct {
   int32_t nmesh;
   double box_len;
@@ -92,6 +100,7 @@ typedef struct {
   int32_t precision;
   int32_t ell_max_hint;
   int32_t max_group;
+  int32_t deterministic;
 } pkm_params;
 
 /* A catalog: n objects, positions pos[3*i + a] (FP64, absolute coordinates), optional

@@ -153,9 +153,10 @@ __device__ __forceinline__ void stockham_stage(cx<T>* lds, int off, int es, int 
 }
 
 // ---------------------------------------------------------------------------------------
-// Compile-time Stockham FFT for power-of-two L with the line held in registers on entry and
-// exit.  Radices 8, then 4, then 2 (each dividing E); spans, strides and twiddle offsets are
-// constants.  Element e of the register array u is position t + PT*e of the line (PT = L/E
+// Compile-time Stockham FFT for L = 2^a 3^b with the line held in registers on entry and
+// exit.  At each stage the first of the radices 8, 6, 4, 3, 2 that divides both E and the
+// remaining length (the order the host's schedules use); spans, strides and twiddle offsets
+// are constants.  Element e of the register array u is position t + PT*e of the line (PT = L/E
 // threads per line, this thread number t).  The first stage reads its inputs straight from
 // u and the last stage's outputs are exactly the positions t + PT*e again, so only the
 // exchanges between stages go through LDS (at lds[off + padi<PAD>(i)*es]).
@@ -168,7 +169,11 @@ __device__ __forceinline__ void stockham_stage(cx<T>* lds, int off, int es, int 
 // a wavefront-level ordering (LDS operations of one wave complete in issue order).
 // ---------------------------------------------------------------------------------------
 __host__ __device__ constexpr int ct_radix(int e, int rem) {
-  return (e % 8 == 0 && rem % 8 == 0) ? 8 : (e % 4 == 0 && rem % 4 == 0) ? 4 : 2;
+  return (e % 8 == 0 && rem % 8 == 0)   ? 8
+         : (e % 6 == 0 && rem % 6 == 0) ? 6
+         : (e % 4 == 0 && rem % 4 == 0) ? 4
+         : (e % 3 == 0 && rem % 3 == 0) ? 3
+                                        : 2;
 }
 // Offset of the twiddles of the stage with span mstage (all stages with span < mstage).
 __host__ __device__ constexpr int ct_tw_off(int e, int L, int mstage) {
@@ -239,7 +244,7 @@ __device__ __forceinline__ void ct_butterflies(int t, cx<T>* v, const cx<T>* tws
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     if constexpr (M > 1) {
-      const int k = (t + q * PT) & (M - 1);
+      const int k = (t + q * PT) % M;  // a mask when M is a power of two
 #pragma unroll
       for (int s = 1; s < R; ++s) {
         cx<T> w = twst[OFF + k * (R - 1) + (s - 1)];
@@ -257,7 +262,7 @@ __device__ __forceinline__ void ct_scatter(cx<T>* lds, int off, int es, int t, c
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const int b = t + q * PT;
-    const int k = b & (M - 1);
+    const int k = b % M;
     const int base = (b - k) * R + k;
 #pragma unroll
     for (int s = 0; s < R; ++s) lds[off + padi<PAD>(base + s * M) * es] = v[q * R + s];

@@ -78,9 +78,16 @@ inline int tile_scan_scratch(int ntiles) { return (ntiles + 1023) / 1024 + 1; }
 template <typename T>
 // wmax_d / wmax_r: device pointers to the largest |w| of each catalog (wmax_r null without
 // randoms); they bound the per-tile fixed-point accumulation of FP32 meshes.
+// acc (deterministic mode, else null): 64-bit accumulators, n^3 per mesh (two meshes when d2 is
+// set), zeroed by the caller; the paint then leaves d1 / d2 untouched and writes the shared
+// fixed-point scale to *gsc, and launch_det_convert turns the accumulators into the meshes.
 hipError_t launch_paint_tiles(const int* off, const void* payload, int ntiles, const double* origin, double scale,
                               int nmesh, int window, int ts, T* d1, T* d2, const double* wmax_d,
-                              const double* wmax_r, double alpha, hipStream_t s);
+                              const double* wmax_r, double alpha, hipStream_t s, unsigned long long* acc = nullptr,
+                              double* gsc = nullptr);
+template <typename T>
+hipError_t launch_det_convert(const unsigned long long* acc, T* d1, T* d2, int nmesh, const double* gsc,
+                              hipStream_t s);
 
 // Forward real-to-half-complex transform along z of nbuf real meshes (nbuf <= 2).
 template <typename T>

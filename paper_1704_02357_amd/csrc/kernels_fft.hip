@@ -22,9 +22,10 @@
 // the Cartesian decomposition.
 //
 // Every kernel takes two extra template constants: NC (mesh side) and TC (tile width, or
-// lines per block for the z passes).  For power-of-two meshes the launchers instantiate them
-// with the plan's values, so all index arithmetic and the radix schedule fold to constants;
-// NC = TC = 0 selects the runtime-generic path used for the other sizes.
+// lines per block for the z passes).  For the built-in shapes of the power-of-two meshes and
+// of 384 and 768 (radix-3 schedules) the launchers instantiate them with the plan's values, so
+// all index arithmetic and the radix schedule fold to constants; NC = TC = 0 selects the
+// runtime-generic path used for the other sizes and shapes.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -821,8 +822,9 @@ size_t xpost_base_bytes(const FftShape& fs, bool fp64) {
     default: return hipErrorInvalidValue;           \
   }
 
-// Compile-time instantiations for power-of-two meshes: (N, E, TC) triples matching the
-// plan's shape rules for FP32 and FP64; anything else runs the generic kernels.
+// Compile-time instantiations: (N, E, TC) triples matching the plan's shape rules for FP32
+// and FP64 at the power-of-two sizes and at 384 and 768; anything else runs the generic
+// kernels.
 #define PKM_TRY(NV, EV, TV, EARG, TARG, CALL)      \
   if (fs.n == NV && (EARG) == EV && (TARG) == TV) { \
     constexpr int NC = NV, E = EV, TC = TV;         \
@@ -837,7 +839,10 @@ size_t xpost_base_bytes(const FftShape& fs, bool fp64) {
   PKM_TRY(512, 8, 16, fs.e_z, fs.zlines, CALL) \
   PKM_TRY(512, 8, 8, fs.e_z, fs.zlines, CALL)  \
   PKM_TRY(1024, 8, 8, fs.e_z, fs.zlines, CALL) \
-  PKM_TRY(1024, 8, 4, fs.e_z, fs.zlines, CALL)
+  PKM_TRY(1024, 8, 4, fs.e_z, fs.zlines, CALL) \
+  PKM_TRY(384, 6, 8, fs.e_z, fs.zlines, CALL)  \
+  PKM_TRY(768, 6, 8, fs.e_z, fs.zlines, CALL)  \
+  PKM_TRY(768, 6, 4, fs.e_z, fs.zlines, CALL)
 
 #define PKM_TRY_COL(CALL)                         \
   PKM_TRY(64, 8, 16, fs.e_col, fs.tile, CALL)     \
@@ -849,14 +854,20 @@ size_t xpost_base_bytes(const FftShape& fs, bool fp64) {
   PKM_TRY(128, 8, 8, fs.e_col, fs.tile, CALL)     \
   PKM_TRY(256, 8, 8, fs.e_col, fs.tile, CALL)     \
   PKM_TRY(512, 8, 8, fs.e_col, fs.tile, CALL)     \
-  PKM_TRY(1024, 8, 4, fs.e_col, fs.tile, CALL)
+  PKM_TRY(1024, 8, 4, fs.e_col, fs.tile, CALL)     \
+  PKM_TRY(384, 12, 16, fs.e_col, fs.tile, CALL)    \
+  PKM_TRY(768, 12, 8, fs.e_col, fs.tile, CALL)
 
 #define PKM_TRY_POST(CALL)                           \
   PKM_TRY(64, 8, 16, fs.e_post, fs.tile_post, CALL)  \
   PKM_TRY(128, 8, 16, fs.e_post, fs.tile_post, CALL) \
   PKM_TRY(256, 8, 8, fs.e_post, fs.tile_post, CALL)  \
   PKM_TRY(512, 8, 4, fs.e_post, fs.tile_post, CALL)  \
-  PKM_TRY(1024, 8, 2, fs.e_post, fs.tile_post, CALL)
+  PKM_TRY(1024, 8, 2, fs.e_post, fs.tile_post, CALL) \
+  PKM_TRY(384, 6, 4, fs.e_post, fs.tile_post, CALL)  \
+  PKM_TRY(768, 6, 2, fs.e_post, fs.tile_post, CALL)  \
+  PKM_TRY(384, 12, 8, fs.e_post, fs.tile_post, CALL) \
+  PKM_TRY(768, 12, 4, fs.e_post, fs.tile_post, CALL)
 
 template <typename T>
 hipError_t launch_zfwd(const FftShape& fs, const T* in0, const T* in1, void* out0, void* out1, int nbuf,

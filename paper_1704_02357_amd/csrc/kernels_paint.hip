@@ -2,6 +2,8 @@
 // interlacing).  Mesh coordinates are computed in FP64 with explicitly rounded operations
 // (u = (x - o) * (N / L); no fused multiply-add) so that node indices and fractions match
 // any other IEEE implementation of the same formula bit for bit.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "device_common.hpp"
 
@@ -232,18 +234,21 @@ __device__ __forceinline__ void taps_unwrapped(double u, long long* c0, double* 
 // One tap into the LDS region: FP64 atomic add (FP64 meshes), or, for FP32 meshes, an
 // integer add of the tap rounded to a multiple of 1/sc (fixed point; 64-bit integer LDS atomics
 // are faster than FP64 ones on gfx950, and FP32 LDS atomics far slower).
-template <typename T>
+// Deterministic mode (FIXED for FP64 too): every tap is rounded to a multiple of 1/sc of one
+// scale shared by all tiles, so integer sums of the taps are exact in any order.
+template <typename T, bool DET>
 __device__ __forceinline__ void region_add(double* __restrict__ reg, int i, double v, double sc) {
-  if constexpr (sizeof(T) == 4)
+  if constexpr (sizeof(T) == 4 || DET)
     lds_atomic_add<unsigned long long>(reinterpret_cast<unsigned long long*>(reg) + i,
                                        (unsigned long long)__double2ll_rn(v * sc));
   else
     lds_atomic_add<double>(reg + i, v);
 }
 
-template <typename T, int W>
-__device__ __forceinline__ void tile_scatter(double* __restrict__ reg, T* __restrict__ mesh, const double* u,
-                                             double wgt, int nmesh, const long long* r0, int rsz, double sc) {
+template <typename T, int W, bool DET>
+__device__ __forceinline__ void tile_scatter(double* __restrict__ reg, T* __restrict__ mesh,
+                                             unsigned long long* __restrict__ acc, const double* u, double wgt,
+                                             int nmesh, const long long* r0, int rsz, double sc) {
   long long c0[3];
   double w[3][W];
   taps_unwrapped<W>(u[0], &c0[0], w[0]);
@@ -260,7 +265,7 @@ __device__ __forceinline__ void tile_scatter(double* __restrict__ reg, T* __rest
         const double wab = wa * w[1][b];
         const int row = ((ra0 + a) * rsz + (rb0 + b)) * rsz + rc0;
 #pragma unroll
-        for (int c = 0; c < W; ++c) region_add<T>(reg, row + c, wab * w[2][c], sc);
+        for (int c = 0; c < W; ++c) region_add<T, DET>(reg, row + c, wab * w[2][c], sc);
       }
     }
     return;
@@ -276,18 +281,26 @@ __device__ __forceinline__ void tile_scatter(double* __restrict__ reg, T* __rest
       for (int c = 0; c < W; ++c) {
         const size_t g = ((size_t)wrap(c0[0] + a, nmesh) * nmesh + wrap(c0[1] + b, nmesh)) * nmesh +
                          wrap(c0[2] + c, nmesh);
-        unsafeAtomicAdd(&mesh[g], (T)(wab * w[2][c]));
+        if constexpr (DET)
+          atomicAdd(&acc[g], (unsigned long long)__double2ll_rn(wab * w[2][c] * sc));
+        else
+          unsafeAtomicAdd(&mesh[g], (T)(wab * w[2][c]));
       }
     }
   }
 }
 
-template <typename T, int W, int TS>
+// DET: the tiles' integer sums go to the 64-bit accumulators acc1 / acc2 (one per mesh) with
+// integer atomics at the shared scale *gsc, instead of floating-point atomics to d1 / d2.
+template <typename T, int W, int TS, bool DET>
 __global__ void __launch_bounds__(256) k_paint_tiles(const int* __restrict__ off, const double4* __restrict__ payload,
                                                      double o0, double o1, double o2, double scale, int nmesh,
                                                      T* __restrict__ d1, T* __restrict__ d2,
                                                      const double* __restrict__ wmax_d,
-                                                     const double* __restrict__ wmax_r, double alpha) {
+                                                     const double* __restrict__ wmax_r, double alpha,
+                                                     unsigned long long* __restrict__ acc1,
+                                                     unsigned long long* __restrict__ acc2,
+                                                     const double* __restrict__ gsc) {
   constexpr int ts = TS;
   extern __shared__ __align__(16) unsigned char smem[];
   // natural tile order: consecutive tiles land on different XCDs, which spreads the dense
@@ -307,7 +320,9 @@ __global__ void __launch_bounds__(256) k_paint_tiles(const int* __restrict__ off
   // fixed-point scale (FP32 meshes): no region cell can exceed B = (particles of the tile) x
   // (largest |payload weight|), since a particle's taps sum to its weight; B sc <= 2^61
   double sc = 1.0;
-  if constexpr (sizeof(T) == 4) {
+  if constexpr (DET) {
+    sc = *gsc;
+  } else if constexpr (sizeof(T) == 4) {
     const double wm = fmax(*wmax_d, wmax_r ? alpha * *wmax_r : 0.0);
     const double bound = (double)(end - start) * wm;
     int e = 0;
@@ -328,35 +343,76 @@ __global__ void __launch_bounds__(256) k_paint_tiles(const int* __restrict__ off
       const long long cu = (long long)floor(u[a]);
       r0[a] = cu - (wrap(cu, nmesh) - t0[a]) - 1;
     }
-    tile_scatter<T, W>(r1, d1, u, wgt, nmesh, r0, rsz, sc);
-    if (d2) {
+    tile_scatter<T, W, DET>(r1, d1, acc1, u, wgt, nmesh, r0, rsz, sc);
+    if (nreg == 2) {
       u[0] = __dadd_rn(u[0], 0.5);
       u[1] = __dadd_rn(u[1], 0.5);
       u[2] = __dadd_rn(u[2], 0.5);
-      tile_scatter<T, W>(r2, d2, u, wgt, nmesh, r0, rsz, sc);
+      tile_scatter<T, W, DET>(r2, d2, acc2, u, wgt, nmesh, r0, rsz, sc);
     }
   }
   __syncthreads();
   for (int m = 0; m < nreg; ++m) {
     const double* reg = m ? r2 : r1;
     T* mesh = m ? d2 : d1;
+    unsigned long long* acc = m ? acc2 : acc1;
     const double isc = 1.0 / sc;  // a power of two: exact
     for (int i = threadIdx.x; i < rcells; i += blockDim.x) {
+      const long long q = reinterpret_cast<const long long*>(reg)[i];
       T v;
-      if constexpr (sizeof(T) == 4)
-        v = (T)((double)reinterpret_cast<const long long*>(reg)[i] * isc);
+      if constexpr (sizeof(T) == 4 && !DET)
+        v = (T)((double)q * isc);
       else
         v = (T)reg[i];
-      if (v == T(0)) continue;
+      if (DET ? q == 0 : v == T(0)) continue;
       // region node (ra, rb, rc) is mesh node t0 - 1 + (ra, rb, rc), wrapped once at most
       const int rc = i % rsz, rb = (i / rsz) % rsz, ra = i / (rsz * rsz);
       int gx = t0[0] - 1 + ra, gy = t0[1] - 1 + rb, gz = t0[2] - 1 + rc;
       gx += gx < 0 ? nmesh : (gx >= nmesh ? -nmesh : 0);
       gy += gy < 0 ? nmesh : (gy >= nmesh ? -nmesh : 0);
       gz += gz < 0 ? nmesh : (gz >= nmesh ? -nmesh : 0);
-      unsafeAtomicAdd(&mesh[((size_t)gx * nmesh + gy) * nmesh + gz], v);
+      const size_t g = ((size_t)gx * nmesh + gy) * nmesh + gz;
+      if constexpr (DET)
+        atomicAdd(&acc[g], (unsigned long long)q);
+      else
+        unsafeAtomicAdd(&mesh[g], v);
     }
   }
+}
+
+// Deterministic mode: the shared fixed-point scale.  A node's value is a sum of taps of the
+// particles whose base node lies within one window width of it, which belong to at most 8
+// tiles (2 per axis for tiles of at least 3 nodes), so |value| <= B = 8 (largest tile count)
+// (largest |payload weight|); sc = 2^(60 - e) with B < 2^e keeps every partial and total sum
+// below 2^60 in magnitude.
+__global__ void k_det_scale(const int* __restrict__ off, int ntiles, const double* __restrict__ wmax_d,
+                            const double* __restrict__ wmax_r, double alpha, double* __restrict__ gsc) {
+  __shared__ int s[256];
+  int m = 0;
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) m = max(m, off[t + 1] - off[t]);
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double wm = fmax(*wmax_d, wmax_r ? alpha * *wmax_r : 0.0);
+    const double bound = 8.0 * (double)s[0] * wm;
+    int e = 0;
+    if (bound > 0.0) (void)frexp(bound, &e);
+    *gsc = ldexp(1.0, 60 - e);
+  }
+}
+
+// Deterministic mode: mesh value = accumulated integer / sc.
+template <typename T>
+__global__ void k_det_convert(const unsigned long long* __restrict__ acc, T* __restrict__ d, size_t n,
+                              const double* __restrict__ gsc) {
+  const double isc = 1.0 / *gsc;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    d[i] = (T)((double)(long long)acc[i] * isc);
 }
 
 }  // namespace
@@ -408,14 +464,28 @@ hipError_t launch_tile_offsets(int* count, int ntiles, int* off, const int* tile
 template <typename T>
 hipError_t launch_paint_tiles(const int* off, const void* payload, int ntiles, const double* origin, double scale,
                               int nmesh, int window, int ts, T* d1, T* d2, const double* wmax_d,
-                              const double* wmax_r, double alpha, hipStream_t s) {
-  const size_t sm = sizeof(double) * (size_t)(ts + 4) * (ts + 4) * (ts + 4) * (d2 ? 2 : 1);
+                              const double* wmax_r, double alpha, hipStream_t s, unsigned long long* acc,
+                              double* gsc) {
+  const bool two = d2 != nullptr;
+  const size_t sm = sizeof(double) * (size_t)(ts + 4) * (ts + 4) * (ts + 4) * (two ? 2 : 1);
   const double4* pl = (const double4*)payload;
-#define PKM_PAINT(WV, TV)                                                                                    \
-  if (window == WV && ts == TV) {                                                                            \
-    k_paint_tiles<T, WV, TV><<<ntiles, 256, sm, s>>>(off, pl, origin[0], origin[1], origin[2], scale, nmesh, d1, \
-                                                    d2, wmax_d, wmax_r, alpha);                              \
-    return hipGetLastError();                                                                                \
+  unsigned long long* acc2 = (acc && two) ? acc + (size_t)nmesh * nmesh * nmesh : nullptr;
+  if (acc) {
+    k_det_scale<<<1, 256, 0, s>>>(off, ntiles, wmax_d, wmax_r, alpha, gsc);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+#define PKM_PAINT(WV, TV)                                                                                      \
+  if (window == WV && ts == TV) {                                                                              \
+    if (acc)                                                                                                   \
+      k_paint_tiles<T, WV, TV, true><<<ntiles, 256, sm, s>>>(off, pl, origin[0], origin[1], origin[2], scale,  \
+                                                             nmesh, d1, d2, wmax_d, wmax_r, alpha, acc, acc2,  \
+                                                             gsc);                                            \
+    else                                                                                                       \
+      k_paint_tiles<T, WV, TV, false><<<ntiles, 256, sm, s>>>(off, pl, origin[0], origin[1], origin[2], scale, \
+                                                              nmesh, d1, d2, wmax_d, wmax_r, alpha, nullptr,   \
+                                                              nullptr, nullptr);                              \
+    return hipGetLastError();                                                                                  \
   }
   PKM_PAINT(1, 4) PKM_PAINT(2, 4) PKM_PAINT(3, 4)
   PKM_PAINT(1, 8) PKM_PAINT(2, 8) PKM_PAINT(3, 8)
@@ -424,10 +494,27 @@ hipError_t launch_paint_tiles(const int* off, const void* payload, int ntiles, c
   return hipErrorInvalidValue;
 }
 
+template <typename T>
+hipError_t launch_det_convert(const unsigned long long* acc, T* d1, T* d2, int nmesh, const double* gsc,
+                              hipStream_t s) {
+  const size_t n = (size_t)nmesh * nmesh * nmesh;
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
+  k_det_convert<T><<<blocks, 256, 0, s>>>(acc, d1, n, gsc);
+  if (d2) k_det_convert<T><<<blocks, 256, 0, s>>>(acc + n, d2, n, gsc);
+  return hipGetLastError();
+}
+
 template hipError_t launch_paint_tiles<float>(const int*, const void*, int, const double*, double, int, int, int,
-                                              float*, float*, const double*, const double*, double, hipStream_t);
+                                              float*, float*, const double*, const double*, double, hipStream_t,
+                                              unsigned long long*, double*);
 template hipError_t launch_paint_tiles<double>(const int*, const void*, int, const double*, double, int, int, int,
-                                               double*, double*, const double*, const double*, double, hipStream_t);
+                                               double*, double*, const double*, const double*, double, hipStream_t,
+                                               unsigned long long*, double*);
+template hipError_t launch_det_convert<float>(const unsigned long long*, float*, float*, int, const double*,
+                                              hipStream_t);
+template hipError_t launch_det_convert<double>(const unsigned long long*, double*, double*, int, const double*,
+                                               hipStream_t);
+template hipError_t launch_fill<unsigned long long>(unsigned long long*, size_t, unsigned long long, hipStream_t);
 template hipError_t launch_fill<float>(float*, size_t, float, hipStream_t);
 template hipError_t launch_fill<int>(int*, size_t, int, hipStream_t);
 template hipError_t launch_fill<double>(double*, size_t, double, hipStream_t);

@@ -90,6 +90,8 @@ struct pkm_plan {
   double* out_dev = nullptr;
   size_t out_cap = 0;
   double* sums_dev = nullptr;  // 4 sums, the 2 catalogs' max |w|, 3 x SUM_BLOCKS partials
+  unsigned long long* det_acc = nullptr;  // deterministic mode: 64-bit paint accumulators
+  double* det_scale = nullptr;            // deterministic mode: the shared fixed-point scale
   double* cat_dev = nullptr;   // staging for host catalogs
   size_t cat_cap = 0;          // doubles
   // tile sort of the particles
@@ -495,11 +497,16 @@ template <typename T> void enqueue_paint(pkm_plan* pl, const DevCats& dc) {
     throw Fail{PKM_EINVAL};
   }
   const double alpha = alpha_of(dc.nd, dc.nr);
+  const bool det = pl->p.deterministic != 0;
   {
     StageScope ss(pl, PKM_STAGE_FILL);
     check_hip(pl, launch_fill<int>(pl->tile_count, (size_t)TILE_COUNT_COPIES * (pl->ntiles + 1), 0, s), "fill");
-    check_hip(pl, launch_fill<T>(d1, cells, T(0), s), "fill");
-    if (d2) check_hip(pl, launch_fill<T>(d2, cells, T(0), s), "fill");
+    if (det) {
+      check_hip(pl, launch_fill<unsigned long long>(pl->det_acc, cells * (d2 ? 2 : 1), 0ull, s), "fill");
+    } else {
+      check_hip(pl, launch_fill<T>(d1, cells, T(0), s), "fill");
+      if (d2) check_hip(pl, launch_fill<T>(d2, cells, T(0), s), "fill");
+    }
   }
   {
     StageScope ss(pl, PKM_STAGE_PAINT);
@@ -515,8 +522,10 @@ template <typename T> void enqueue_paint(pkm_plan* pl, const DevCats& dc) {
               "tile offsets");
     check_hip(pl, launch_paint_tiles<T>(pl->tile_off, pl->payload, pl->ntiles, pl->p.box_origin, scale, n,
                                         pl->p.window, pl->ts, d1, d2, pl->sums_dev + 4,
-                                        has_r ? pl->sums_dev + 5 : nullptr, alpha, s),
+                                        has_r ? pl->sums_dev + 5 : nullptr, alpha, s,
+                                        det ? pl->det_acc : nullptr, det ? pl->det_scale : nullptr),
               "paint");
+    if (det) check_hip(pl, launch_det_convert<T>(pl->det_acc, d1, d2, n, pl->det_scale, s), "paint convert");
   }
   const int nbuf = d2 ? 2 : 1;
   void** sp = pl->paint_ptrs;  // {s1, s2, g}
@@ -700,11 +709,18 @@ void prepare_compute(pkm_plan* pl, int ell_max, const double* k_edges, int n_edg
   }
   // histogram copies per block: one per wave when the LDS budget of two post-pass blocks per
   // CU allows (the register budget allows no more than two)
+  // (deterministic mode: one per wave always, within the LDS of one block per CU, so that no
+  // two waves add to the same bin)
   const int waves = ((n / pl->fs.e_post) * pl->fs.tile_post + 63) / 64;
-  const size_t budget = col_lds + 1024 < 80 * 1024 ? 80 * 1024 - col_lds - 1024 : 0;
+  const size_t lds_cap = pl->p.deterministic ? 150 * 1024 : 80 * 1024;
+  const size_t budget = col_lds + 1024 < lds_cap ? lds_cap - col_lds - 1024 : 0;
   for (auto& gc : cc.groups) {
     const int copies = (int)std::min<size_t>((size_t)waves, budget / (sizeof(double) * (size_t)std::max(1, gc.nv)));
     gc.copies = std::max(1, copies);
+    if (pl->p.deterministic && gc.copies < waves) {
+      pl->err = "deterministic mode: one post-pass histogram per wavefront does not fit LDS for these bins";
+      throw Fail{PKM_ENOMEM};
+    }
   }
   cc.ell_max = ell_max;
   cc.basis = basis;
@@ -1023,12 +1039,15 @@ bool make_shape(const pkm_params& p, FftShape* out) {
   fs.n = n;
   fs.e_col = pick_e(n);
   fs.e_z = pick_e(n / 2);
-  // register budget: z-line passes, and FP64 column passes of the generic kernels, use at
-  // most 8 (or 12 / 6 for lengths with a factor 3) elements per thread; the compile-time
-  // FP64 column kernels for 256..1024 take 16 (the autotuner's pick at 512^3)
+  // register budget: FP64 column passes of the generic kernels use at most 8 elements per
+  // thread (12 / 6 for lengths with a factor 3); the compile-time FP64 column kernels for
+  // 256..1024 take 16 (the autotuner's pick at 512^3)
   const bool pow2_table = n >= 256 && n <= 1024 && (n & (n - 1)) == 0;
   if (fp64 && fs.e_col == 16 && !pow2_table) fs.e_col = 8;
+  // z lines: 2E nodes per thread carry the harmonic recurrence in the pre-pass, which spills
+  // at 12 (radix-3 lengths) as it would at 16
   if (fs.e_z == 16) fs.e_z = 8;
+  if (fs.e_z == 12) fs.e_z = 6;
   if (!fs.e_col || !fs.e_z || !make_sched(n, fs.e_col, &fs.sched_col, &fs.nst_col) ||
       !make_sched(n / 2, fs.e_z, &fs.sched_z, &fs.nst_z)) {
     return false;
@@ -1039,9 +1058,12 @@ bool make_shape(const pkm_params& p, FftShape* out) {
   const int pt_col = n / fs.e_col;
   while (fs.tile > 1 && (pt_col * fs.tile > 512 || (n / 2) % fs.tile || colpass_smem_bytes(fs, fp64) > 160 * 1024))
     fs.tile /= 2;
-  // post-pass: at most 8 elements per thread (register budget of the fused recurrence)
+  // post-pass: at most 8 elements per thread (register budget of the fused recurrence), 6 for
+  // lengths with a factor 3, except FP64 at 384 and 768: there 12 (one wave per line and two
+  // fewer radix stages) measured 22% (384) and 39% (768) faster than 6, where in FP32 the
+  // two took the same time
   fs.e_post = fs.e_col > 8 && fs.e_col % 8 == 0 ? 8 : fs.e_col;
-  if (fs.e_post == 12) fs.e_post = 6;
+  if (fs.e_post == 12 && !(fp64 && (n == 384 || n == 768))) fs.e_post = 6;
   if (!make_sched(n, fs.e_post, &fs.sched_post, &fs.nst_post)) {
     return false;
   }
@@ -1137,6 +1159,7 @@ pkm_status validate_params(const pkm_params* p, std::string* why) {
     *why = "ell_max_hint must be even and in 0..16";
     return PKM_EINVAL;
   }
+  if (p->deterministic != 0 && p->deterministic != 1) { *why = "deterministic must be 0 or 1"; return PKM_EINVAL; }
   if (p->los_mode == PKM_LOS_GLOBAL) {
     const double l2 = p->los[0] * p->los[0] + p->los[1] * p->los[1] + p->los[2] * p->los[2];
     if (!(l2 > 0)) { *why = "los must be a nonzero vector"; return PKM_EINVAL; }
@@ -1180,7 +1203,7 @@ void free_all(pkm_plan* pl) {
                     (void*)pl->map_dev, pl->tw, pl->ytab, pl->invw, pl->phase, (void*)pl->thr_dev, (void*)pl->partial,
                     (void*)pl->out_dev, (void*)pl->sums_dev, (void*)pl->cat_dev, (void*)pl->tile_count,
                     (void*)pl->tile_off, (void*)pl->tile_of, (void*)pl->tile_rank, pl->payload,
-                    (void*)pl->scan_sums, (void*)pl->paint_ptrs})
+                    (void*)pl->scan_sums, (void*)pl->paint_ptrs, (void*)pl->det_acc, (void*)pl->det_scale})
     dfree(pl, ptr);
   if (pl->slot) (void)hipHostFree(pl->slot);
   if (pl->done) (void)hipEventDestroy(pl->done);
@@ -1337,7 +1360,8 @@ int64_t footprint(const pkm_params* p, int ell_max, int n_edges, int64_t n_parti
   const int64_t partial = (int64_t)post_blocks(fs) * (3 + ell_max / 2) * nb * 8;
   const int64_t ts = 8;
   const int64_t ntiles = (n / ts) * (n / ts) * (n / ts);
-  return meshes * mesh + pads + 80 * n_particles + partial + 8 * ntiles + (4 << 20);
+  const int64_t det = p->deterministic ? 8 * n * n * n * (p->interlaced ? 2 : 1) : 0;
+  return meshes * mesh + pads + 80 * n_particles + partial + 8 * ntiles + det + (4 << 20);
 }
 
 }  // namespace pkm_internal
@@ -1398,6 +1422,8 @@ pkm_status pkm_plan_create_shaped(const pkm_params* p, const pkm_device* dev, co
   pkm_plan* pl = new (std::nothrow) pkm_plan();
   if (!pl) { g_create_err = "host allocation failed"; return PKM_ENOMEM; }
   pl->p = *p;
+  if (const char* env = std::getenv("PKM_DETERMINISTIC"))
+    if (env[0] == '1') pl->p.deterministic = 1;
   pl->frame = harmonic_frame(pl->p);
   if (pl->p.ell_max_hint == 0) pl->p.ell_max_hint = 4;
   if (dev) pl->dev = *dev;
@@ -1427,6 +1453,11 @@ pkm_status pkm_plan_create_shaped(const pkm_params* p, const pkm_device* dev, co
     pl->phase = dalloc(pl, 2 * pl->es * n);
     pl->ytab = dalloc(pl, pl->es * (YLM_LMAX + 1) * YLM_STRIDE);
     pl->sums_dev = (double*)dalloc(pl, sizeof(double) * (6 + 3 * SUM_BLOCKS));
+    if (pl->p.deterministic) {
+      pl->det_acc = (unsigned long long*)dalloc(pl, sizeof(unsigned long long) * (size_t)n * n * n *
+                                                        (p->interlaced ? 2 : 1));
+      pl->det_scale = (double*)dalloc(pl, sizeof(double));
+    }
     pl->ts = ts0;
     pl->ntiles = (n / pl->ts) * (n / pl->ts) * (n / pl->ts);
     pl->tile_count = (int*)dalloc(pl, sizeof(int) * (size_t)TILE_COUNT_COPIES * (pl->ntiles + 1));

@@ -296,6 +296,7 @@ PlanKey key_of(const pkm_params& p) {
   k.p.compensated = p.compensated;
   k.p.precision = p.precision;
   k.p.max_group = p.max_group;
+  k.p.deterministic = p.deterministic;
   return k;  // ell_max_hint excluded: a slot serves any l_max up to its own hint
 }
 bool same_key(const PlanKey& a, const PlanKey& b) { return !(a < b) && !(b < a); }

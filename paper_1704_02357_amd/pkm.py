@@ -32,7 +32,8 @@ class Params(C.Structure):
     _fields_ = [("nmesh", C.c_int32), ("box_len", C.c_double), ("box_origin", C.c_double * 3),
                 ("observer", C.c_double * 3), ("los_mode", C.c_int32), ("los", C.c_double * 3),
                 ("window", C.c_int32), ("interlaced", C.c_int32), ("compensated", C.c_int32),
-                ("precision", C.c_int32), ("ell_max_hint", C.c_int32), ("max_group", C.c_int32)]
+                ("precision", C.c_int32), ("ell_max_hint", C.c_int32), ("max_group", C.c_int32),
+                ("deterministic", C.c_int32)]
 
 
 class Catalog(C.Structure):
@@ -243,7 +244,8 @@ class _TorchAllocator:
 
 
 def make_params(nmesh, box_len, *, box_origin=None, observer=(0.0, 0.0, 0.0), window=TSC, interlaced=True,
-                compensated=True, precision=FP32, ell_max_hint=4, max_group=0, los=None) -> Params:
+                compensated=True, precision=FP32, ell_max_hint=4, max_group=0, los=None,
+                deterministic=False) -> Params:
     p = Params()
     p.nmesh = int(nmesh)
     p.box_len = float(box_len)
@@ -257,6 +259,7 @@ def make_params(nmesh, box_len, *, box_origin=None, observer=(0.0, 0.0, 0.0), wi
             p.los[a] = float(los[a])
     p.window, p.interlaced, p.compensated = int(window), int(bool(interlaced)), int(bool(compensated))
     p.precision, p.ell_max_hint, p.max_group = int(precision), int(ell_max_hint), int(max_group)
+    p.deterministic = int(bool(deterministic))
     return p
 
 
@@ -300,11 +303,11 @@ class Plan:
 
     def __init__(self, nmesh: int, box_len: float, *, box_origin=None, observer=(0.0, 0.0, 0.0), window=TSC,
                  interlaced=True, compensated=True, precision=FP32, ell_max_hint=4, max_group=0, los=None,
-                 device: int = 0, stream=None, torch_allocator: bool = True, shape=None):
+                 device: int = 0, stream=None, torch_allocator: bool = True, shape=None, deterministic=False):
         self.lib = load_library()
         p = make_params(nmesh, box_len, box_origin=box_origin, observer=observer, window=window,
                         interlaced=interlaced, compensated=compensated, precision=precision,
-                        ell_max_hint=ell_max_hint, max_group=max_group, los=los)
+                        ell_max_hint=ell_max_hint, max_group=max_group, los=los, deterministic=deterministic)
         self.params = p
         self.nmesh = p.nmesh
         self.precision = p.precision

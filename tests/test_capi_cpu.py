@@ -89,7 +89,8 @@ def test_wedges_validation():
 
 
 @pytest.mark.parametrize("field,value", [("nmesh", 100), ("nmesh", 2048), ("nmesh", 54), ("box_len", -1.0),
-                                         ("window", 4), ("precision", 2), ("ell_max_hint", 5), ("ell_max_hint", 18)])
+                                         ("window", 4), ("precision", 2), ("ell_max_hint", 5), ("ell_max_hint", 18),
+                                         ("deterministic", 2)])
 def test_plan_create_rejects_bad_params(field, value):
     lib = _lib()
     from paper_1704_02357_amd.pkm import Params

@@ -4,8 +4,12 @@ spherical-harmonic path, against the oracle's definition of P_l.
 
 Both decompositions compute the same P_l; the Cartesian one combines its degree sums with the
 coefficients c_lp of L_l = sum_p c_lp mu^p, whose cancellation multiplies the rounding error by
-A_l = sum_p |c_lp| (1, 2, 8.5, 41, 208 ... 1.7e5 at l = 16).  The pass rule is therefore
-the spherical path's, per l, times A_l.
+A_l = sum_p |c_lp| (1, 2, 8.5, 41, 208 ... 1.7e5 at l = 16).  The pass rule per l is the larger
+of the spherical path's tolerance and 16 unit roundoffs of the form times A_l: the degree sums
+carry a few roundoffs each (measured at 64^3 for 4 <= l <= 16: 0.6 to 1.7 u times A_l in FP32,
+2.7 to 3.9 u in FP64), and the cancellation scales that by A_l.  So FP32 Cartesian multipoles lose about 1e-2 at l = 16
+(a property of the decomposition, which is why the spherical path is the default); the bound
+still fails a degree sum wrong by more than about 16 roundoffs.
 """
 from __future__ import annotations
 
@@ -17,6 +21,7 @@ from tests.parity_util import TOL, oracle_params, pole_errors, small_catalogs
 pytestmark = pytest.mark.gpu
 
 OBS = (30.0, -40.0, -700.0)
+UNIT_ROUNDOFF = {0: 2.0 ** -24, 1: 2.0 ** -53}
 
 
 def amplification(ell: int) -> float:
@@ -37,7 +42,7 @@ def assert_per_ell(got, ref, prec, label):
         scale = np.maximum(np.abs(po[i]), np.abs(raw0))
         ok = np.isfinite(po[i])
         err = float(np.max(np.abs(np.asarray(got["poles"])[i] - po[i])[ok] / scale[ok])) if ok.any() else 0.0
-        tol = TOL[prec] * amplification(ell)
+        tol = max(TOL[prec], 16.0 * UNIT_ROUNDOFF[prec] * amplification(ell))
         print(f"[parity] {label} l={ell} scaled_err={err:.3e} tol={tol:.1e}", flush=True)
         assert err <= tol, f"{label} l={ell}: {err:.3e} > {tol:.1e}"
 
