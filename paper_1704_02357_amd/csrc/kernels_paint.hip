@@ -107,21 +107,42 @@ __device__ __forceinline__ void mesh_u(const double* __restrict__ pos, int64_t i
 constexpr int NCOPY = TILE_COUNT_COPIES;
 constexpr int RANK_BITS = 28;
 
+// Each thread takes CPT particles per round (blockDim apart) and issues their counter atomics
+// back to back, so CPT atomics per thread are in flight at once: the pass is bound by the
+// latency of returning atomics, not by their number.
+constexpr int CPT = 4;
 __global__ void k_tile_count(const double* __restrict__ pos, int64_t n, int64_t base, double o0, double o1,
                              double o2, double scale, int nmesh, int ts, int ntiles, int* __restrict__ count,
                              int* __restrict__ tile_of, int* __restrict__ rank) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * CPT;
   const int tpa = nmesh / ts;
   const int copy = blockIdx.x % NCOPY;
   int* cnt = count + (size_t)copy * (ntiles + 1);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    double u[3];
-    mesh_u(pos, i, o0, o1, o2, scale, u);
-    int tc[3];
-    for (int a = 0; a < 3; ++a) tc[a] = wrap((long long)floor(u[a]), nmesh) / ts;
-    const int tile = (tc[0] * tpa + tc[1]) * tpa + tc[2];
-    tile_of[base + i] = tile;
-    rank[base + i] = atomicAdd(&cnt[tile], 1) | (copy << RANK_BITS);
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x * CPT + threadIdx.x; i0 < n; i0 += stride) {
+    int tile[CPT], r[CPT];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int64_t i = i0 + (int64_t)j * blockDim.x;
+      tile[j] = -1;
+      if (i < n) {
+        double u[3];
+        mesh_u(pos, i, o0, o1, o2, scale, u);
+        int tc[3];
+        for (int a = 0; a < 3; ++a) tc[a] = wrap((long long)floor(u[a]), nmesh) / ts;
+        tile[j] = (tc[0] * tpa + tc[1]) * tpa + tc[2];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j)
+      if (tile[j] >= 0) r[j] = atomicAdd(&cnt[tile[j]], 1);
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int64_t i = i0 + (int64_t)j * blockDim.x;
+      if (tile[j] >= 0) {
+        tile_of[base + i] = tile[j];
+        rank[base + i] = r[j] | (copy << RANK_BITS);
+      }
+    }
   }
 }
 
@@ -191,20 +212,32 @@ __global__ void k_tile_scatter(const int* __restrict__ tile_of, const int* __res
                                int ntiles, const int* __restrict__ start, const double* __restrict__ dpos,
                                const double* __restrict__ dw, const double* __restrict__ rpos,
                                const double* __restrict__ rw, double alpha, double4* __restrict__ payload) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const bool isd = i < nd;
-    const int64_t k = isd ? i : i - nd;
-    const double* pos = isd ? dpos : rpos;
-    const double* wp = isd ? dw : rw;
-    double4 p;
-    p.x = pos[3 * k];
-    p.y = pos[3 * k + 1];
-    p.z = pos[3 * k + 2];
-    p.w = (wp ? wp[k] : 1.0) * (isd ? 1.0 : -alpha);
-    const int r = rank[i];
-    const int copy = (int)((unsigned)r >> RANK_BITS);
-    payload[start[(size_t)copy * (ntiles + 1) + tile_of[i]] + (r & ((1 << RANK_BITS) - 1))] = p;
+  // CPT particles per thread and round, loads first: several offset lookups in flight at once
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * CPT;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x * CPT + threadIdx.x; i0 < n; i0 += stride) {
+    int dst[CPT];
+    double4 p[CPT];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int64_t i = i0 + (int64_t)j * blockDim.x;
+      dst[j] = -1;
+      if (i < n) {
+        const bool isd = i < nd;
+        const int64_t k = isd ? i : i - nd;
+        const double* pos = isd ? dpos : rpos;
+        const double* wp = isd ? dw : rw;
+        p[j].x = pos[3 * k];
+        p[j].y = pos[3 * k + 1];
+        p[j].z = pos[3 * k + 2];
+        p[j].w = (wp ? wp[k] : 1.0) * (isd ? 1.0 : -alpha);
+        const int r = rank[i];
+        const int copy = (int)((unsigned)r >> RANK_BITS);
+        dst[j] = start[(size_t)copy * (ntiles + 1) + tile_of[i]] + (r & ((1 << RANK_BITS) - 1));
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j)
+      if (dst[j] >= 0) payload[dst[j]] = p[j];
   }
 }
 
@@ -437,7 +470,7 @@ template <typename T> hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s)
 hipError_t launch_tile_sort(const double* pos, int64_t n, int64_t base, const double* origin, double scale,
                             int nmesh, int ts, int* count, int* tile_of, int* rank, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
+  int64_t blocks = (n + 256 * CPT - 1) / (256 * CPT);
   if (blocks > 16384) blocks = 16384;
   const int tpa = nmesh / ts;
   k_tile_count<<<(unsigned)blocks, 256, 0, s>>>(pos, n, base, origin[0], origin[1], origin[2], scale, nmesh, ts,
@@ -454,7 +487,7 @@ hipError_t launch_tile_offsets(int* count, int ntiles, int* off, const int* tile
   k_scan_add<<<nblk, SCAN_THREADS, 0, s>>>(bsum, ntiles, off, count);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ntot == 0) return e;
-  int64_t blocks = (ntot + 255) / 256;
+  int64_t blocks = (ntot + 256 * CPT - 1) / (256 * CPT);
   if (blocks > 16384) blocks = 16384;
   k_tile_scatter<<<(unsigned)blocks, 256, 0, s>>>(tile_of, rank, nd, ntot, ntiles, count, dpos, dw, rpos, rw,
                                                   alpha, (double4*)payload);
