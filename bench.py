@@ -272,10 +272,10 @@ def cpu_baseline(data, rand, edges, workers: int) -> dict:
     """FP64 oracle timed on a bounded sample of one estimate, scaled to estimates/s.
 
     Sample: painting split into a per-cell part and a per-particle part, from two paints of
-    catalog subsamples (1/25 and 1/100) onto a 256^3 mesh (per-cell part x8 for 512^3, the
+    catalog subsamples (1/10 and 1/40) onto a 256^3 mesh (per-cell part x8 for 512^3, the
     per-particle part extrapolated to the whole catalog); one full-grid forward transform (x17
-    transforms); the harmonic weighting of one field on 1/16 of the nodes and of the modes
-    (x16 x14 fields); one binning pass (x3 multipoles)."""
+    transforms); the harmonic weighting of one field on 1/8 of the nodes and of the modes
+    (x8 x14 fields); one binning pass (x3 multipoles).  About 10-15 s of host work."""
     import scipy.fft as sfft
     from oracle.estimator import default_params, k_thresholds, mode_bins, node_vectors, mode_vectors, binned_sums
     from oracle.mesh import fkp_meshes
@@ -283,7 +283,7 @@ def cpu_baseline(data, rand, edges, workers: int) -> dict:
     from oracle.ylm import real_ylm
     from synth import Catalog
     p = default_params(NMESH, BOX, observer=OBSERVER, window=3, interlaced=True, compensated=True)
-    slab_div = 16
+    slab_div = 8
     nfields = sum(2 * l + 1 for l in range(2, ELL_MAX + 1, 2))
     t = {}
 
@@ -295,10 +295,10 @@ def cpu_baseline(data, rand, edges, workers: int) -> dict:
         meshes = fkp_meshes(sub_d, sub_r, sc["alpha"], nm, BOX, p["box_origin"], 3, True)
         return time.perf_counter() - t0, meshes[0]
 
-    ta, m = paint_time(25, NMESH // 2)
-    tb, _ = paint_time(100, NMESH // 2)
-    per_catalog = max(0.0, (ta - tb) / (1 / 25 - 1 / 100))
-    per_mesh = max(0.0, ta - per_catalog / 25) * 8
+    ta, m = paint_time(10, NMESH // 2)
+    tb, _ = paint_time(40, NMESH // 2)
+    per_catalog = max(0.0, (ta - tb) / (1 / 10 - 1 / 40))
+    per_mesh = max(0.0, ta - per_catalog / 10) * 8
     t["paint"] = per_mesh + per_catalog
     # a 512^3 density for the transform and field samples (the 256^3 mesh, each cell split in 8)
     d1 = m.repeat(2, axis=0).repeat(2, axis=1).repeat(2, axis=2)
@@ -321,7 +321,7 @@ def cpu_baseline(data, rand, edges, workers: int) -> dict:
     t["bin"] = (time.perf_counter() - t0) * 3
     sec = sum(t.values())
     return {"value": 1.0 / sec, "unit": "estimates/s", "cores": workers, "kind": "oracle",
-            "sample": f"FP64 numpy/scipy oracle: paint cost from 1/25 and 1/100 catalog subsamples on a 256^3 mesh "
+            "sample": f"FP64 numpy/scipy oracle: paint cost from 1/10 and 1/40 catalog subsamples on a 256^3 mesh "
                       f"(per-cell part x8, per-particle part extrapolated to the catalog), one 512^3 complex "
                       f"FFT (x{nfields + 3}), Y_lm(x) and Y_lm(k) weighting of one field on 1/{slab_div} of the "
                       f"grid (x{slab_div} x{nfields}), one binning pass (x3); seconds per estimate {sec:.1f} = "

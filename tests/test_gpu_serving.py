@@ -220,3 +220,23 @@ def test_allocator_failure_fails_one_request_alone(gpu):
         _close(got, _alone(n, prec, lmax, d, r, _edges(n)), prec, f"beside a failed request n={n}")
     _close(late, outs[0], 0, "after a failed request")
     sv.close()
+
+
+def test_reused_plan_growth_counts_against_budget(gpu):
+    """A plan made by a small request and reused by one with ten times the particles grows its
+    sort buffers; admission charges that growth, so under a budget of the large request's own
+    footprint both succeed, the plan is reused, and the peak stays within the budget."""
+    from paper_1704_02357_amd import Server, plan_footprint
+    small = small_catalogs(1000, 4000, L, seed=61)
+    large = small_catalogs(10000, 40000, L, seed=62)
+    kw = dict(KW, precision=0, ell_max_hint=4, max_group=16)
+    big = plan_footprint(64, L, 4, len(_edges(64)), 50000, **kw) + 50000 * 5 * 8
+    sv = Server(max_inflight=1, hbm_budget_bytes=big)
+    outs = [sv.wait(sv.submit(64, L, 4, _edges(64), d, r, **kw)) for d, r in (small, large)]
+    st = sv.stats()
+    print(f"[server growth] budget={big} {st}", flush=True)
+    assert st["completed"] == 2 and st["failed"] == 0 and st["resident_plans"] == 1
+    assert st["peak_bytes"] <= big
+    for (d, r), got in zip((small, large), outs):
+        assert_pole_parity(got, _oracle(64, 4, d, r, _edges(64)), 0, f"growth n={len(d.pos)}")
+    sv.close()
