@@ -636,7 +636,7 @@ def serve_bench(args) -> dict:
     pool = serve_pool(args.catalogs, args.serve_random_factor)
     log(f"[serve] pool of {len(pool)} catalogs generated in {time.perf_counter() - t0:.0f} s")
     sizes, lmaxes = [256, 384, 512, 768], [4, 8, 16]
-    sv = Server(max_inflight=args.inflight)
+    sv = Server(max_inflight=args.inflight, field_group=args.field_group)
     ids = [sv.register_catalog(d, r) for d, r in pool]
     n_obj = sum(len(d.pos) + len(r.pos) for d, r in pool)
     reg = sv.stats()["registered_bytes"]
@@ -725,7 +725,7 @@ def serve_bench(args) -> dict:
                     f"{args.serve_random_factor:g}x randoms, registered once)",
             "config": {"workload": f"per request: catalog, Nmesh in {sizes}, l_max in {lmaxes} uniform; "
                                    f"L=2500 Mpc/h, TSC + interlacing, dk=0.01; {form.upper()}",
-                       "max_inflight": args.inflight}}
+                       "max_inflight": args.inflight, "field_group": args.field_group}}
 
 
 def main():
@@ -760,6 +760,9 @@ def main():
     ap.add_argument("--serve-random-factor", type=float, default=10.0)
     ap.add_argument("--serve-precision", type=int, choices=[0, 1], default=0, help="serve mode: 0 FP32, 1 FP64")
     ap.add_argument("--inflight", type=int, default=4)
+    ap.add_argument("--field-group", type=int, default=16,
+                    help="serve mode: weighted fields per plan group; one plan per mesh size then serves every l_max "
+                         "(0: plans sized per request)")
     args = ap.parse_args()
     if args.summarize_profile:
         summarize_profile(args.summarize_profile)

@@ -449,6 +449,11 @@ typedef struct {
   void* (*alloc)(size_t bytes, void* stream, void* ctx);
   void (*free)(void* ptr, void* stream, void* ctx);
   void* alloc_ctx;
+  /* > 0: requests that leave max_group at 0 get max_group = field_group and ell_max_hint = 16,
+   * so one plan per mesh configuration serves every ell_max (a request with more fields than
+   * field_group runs its groups one after another) and plans stop being re-created as ell_max
+   * changes.  0: plans follow each request's own max_group and ell_max_hint.  At most 256. */
+  int32_t field_group;
 } pkm_server_config;
 
 typedef struct {

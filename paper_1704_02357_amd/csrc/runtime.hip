@@ -805,6 +805,7 @@ pkm_status pkm_server_create(const pkm_server_config* cfg, pkm_server** out) {
   if (!cfg || !out) return PKM_EINVAL;
   if (cfg->max_inflight < 1 || cfg->max_inflight > 32) return PKM_EINVAL;
   if ((cfg->alloc == nullptr) != (cfg->free == nullptr)) return PKM_EINVAL;
+  if (cfg->field_group < 0 || cfg->field_group > 256) return PKM_EINVAL;
   pkm_server* sv = new (std::nothrow) pkm_server();
   if (!sv) return PKM_ENOMEM;
   sv->cfg = *cfg;
@@ -949,6 +950,10 @@ pkm_status pkm_server_submit(pkm_server* sv, const pkm_request* rq, int64_t* tic
     }
   auto r = std::make_shared<Request>();
   r->params = rq->params;
+  if (sv->cfg.field_group > 0 && r->params.max_group == 0) {
+    r->params.max_group = sv->cfg.field_group;  // one plan per mesh configuration for every ell_max
+    r->params.ell_max_hint = 16;
+  }
   r->ell_max = rq->ell_max;
   r->edges.assign(rq->k_edges, rq->k_edges + rq->n_edges);
   r->cat_id = rq->catalog_id;

@@ -69,7 +69,7 @@ def _shape(d):
 
 class ServerConfig(C.Structure):
     _fields_ = [("device_id", C.c_int32), ("hbm_budget_bytes", C.c_int64), ("max_inflight", C.c_int32),
-                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p)]
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p), ("field_group", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -510,12 +510,15 @@ class Batch:
 class Server:
     """Request loop on one device: admission by HBM footprint, overlapping estimates."""
 
-    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, max_inflight: int = 4, allocator=None):
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, max_inflight: int = 4, allocator=None,
+                 field_group: int = 0):
         """allocator: None (the device's stream-ordered pool) or an object with ctypes
-        callbacks c_alloc / c_free of pkm_device's allocator signature."""
+        callbacks c_alloc / c_free of pkm_device's allocator signature.  field_group > 0: plans
+        keep that many weighted fields and serve every l_max (pkm_server_config.field_group)."""
         self.lib = load_library()
         cfg = ServerConfig()
         cfg.device_id, cfg.hbm_budget_bytes, cfg.max_inflight = int(device), int(hbm_budget_bytes), int(max_inflight)
+        cfg.field_group = int(field_group)
         self._allocator = allocator
         if allocator is not None:
             cfg.alloc, cfg.free = allocator.c_alloc, allocator.c_free

@@ -240,3 +240,21 @@ def test_reused_plan_growth_counts_against_budget(gpu):
     for (d, r), got in zip((small, large), outs):
         assert_pole_parity(got, _oracle(64, 4, d, r, _edges(64)), 0, f"growth n={len(d.pos)}")
     sv.close()
+
+
+def test_field_group_plan_serves_every_ell_max(gpu):
+    """With field_group set, requests of l_max 2, 8 and 4 for one mesh share one plan (field
+    buffers for 16 fields; l_max = 8 runs its 45 fields in three groups) and equal the
+    oracle."""
+    from paper_1704_02357_amd import Server
+    n = 48
+    d, r = small_catalogs(3000, 12000, L, seed=77)
+    sv = Server(max_inflight=1, field_group=16)
+    kw = dict(KW, precision=1)
+    outs = {lmax: sv.wait(sv.submit(n, L, lmax, _edges(n), d, r, **kw)) for lmax in (2, 8, 4)}
+    st = sv.stats()
+    print(f"[server field group] {st}", flush=True)
+    assert st["completed"] == 3 and st["resident_plans"] == 1
+    for lmax, got in outs.items():
+        assert_pole_parity(got, _oracle(n, lmax, d, r, _edges(n)), 1, f"field group l<={lmax}")
+    sv.close()
