@@ -139,3 +139,46 @@ def test_particle_limit_rejected_on_host():
     assert lib.pkm_check_catalogs(C.byref(cat(MAX_PARTICLES - 10)), C.byref(cat(10))) == 0
     nonbar = Catalog(fake, None, None, 10, 1)
     assert lib.pkm_check_catalogs(C.byref(ok_d), C.byref(nonbar)) == 1
+
+
+def test_server_config_validation_on_host():
+    """Bad server configurations are refused before any device call."""
+    lib = _lib()
+    from paper_1704_02357_amd.pkm import ALLOC_FN, ServerConfig
+    for field, value in (("max_inflight", 0), ("max_inflight", 33), ("field_group", -1), ("field_group", 257)):
+        cfg = ServerConfig()
+        cfg.device_id, cfg.max_inflight = 0, 2
+        setattr(cfg, field, value)
+        h = C.c_void_p()
+        assert lib.pkm_server_create(C.byref(cfg), C.byref(h)) == 1, field
+        assert not h.value
+    cfg = ServerConfig()
+    cfg.max_inflight = 2
+    cfg.alloc = ALLOC_FN(lambda size, stream, ctx: None)  # an allocator without a free
+    h = C.c_void_p()
+    assert lib.pkm_server_create(C.byref(cfg), C.byref(h)) == 1
+
+
+def test_plan_footprint_on_host():
+    """pkm_plan_footprint: host arithmetic only; grows with l_max and particles, caps at
+    max_group fields, adds the 64-bit paint accumulators in deterministic mode, and rejects
+    invalid parameters with -1."""
+    from paper_1704_02357_amd import plan_footprint
+    from paper_1704_02357_amd.pkm import PkmError
+    kw = dict(window=3, interlaced=True, compensated=True, precision=0)
+    a = plan_footprint(128, 500.0, 4, 40, 10_000, **kw)
+    b = plan_footprint(128, 500.0, 8, 40, 10_000, **kw)
+    c = plan_footprint(128, 500.0, 8, 40, 1_000_000, **kw)
+    g = plan_footprint(128, 500.0, 16, 40, 10_000, max_group=4, **kw)
+    d = plan_footprint(128, 500.0, 4, 40, 10_000, deterministic=True, **kw)
+    mesh = 4 * 128 ** 3
+    assert a < b < c and c - b == 80 * 990_000
+    assert g < plan_footprint(128, 500.0, 4, 40, 10_000, max_group=8, **kw)
+    assert d - a == 2 * 8 * 128 ** 3
+    assert b - a >= (45 - 15) * mesh  # 30 more weighted fields
+    for bad in (dict(nmesh=100), dict(ell_max=18), dict(n_edges=1)):
+        args = dict(nmesh=128, box_len=500.0, ell_max=4, n_edges=40, n_particles=10)
+        args.update(bad)
+        with pytest.raises(PkmError):
+            plan_footprint(args.pop("nmesh"), args.pop("box_len"), args.pop("ell_max"), args.pop("n_edges"),
+                           args.pop("n_particles"), **kw)
