@@ -842,7 +842,8 @@ size_t xpost_base_bytes(const FftShape& fs, bool fp64) {
   PKM_TRY(1024, 8, 4, fs.e_z, fs.zlines, CALL) \
   PKM_TRY(384, 6, 8, fs.e_z, fs.zlines, CALL)  \
   PKM_TRY(768, 6, 8, fs.e_z, fs.zlines, CALL)  \
-  PKM_TRY(768, 6, 4, fs.e_z, fs.zlines, CALL)
+  PKM_TRY(768, 6, 4, fs.e_z, fs.zlines, CALL)  \
+  PKM_TRY(512, 4, 4, fs.e_z, fs.zlines, CALL)
 
 #define PKM_TRY_COL(CALL)                         \
   PKM_TRY(64, 8, 16, fs.e_col, fs.tile, CALL)     \

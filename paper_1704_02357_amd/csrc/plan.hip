@@ -1048,6 +1048,9 @@ bool make_shape(const pkm_params& p, FftShape* out) {
   // at 12 (radix-3 lengths) as it would at 16
   if (fs.e_z == 16) fs.e_z = 8;
   if (fs.e_z == 12) fs.e_z = 6;
+  // FP64 at 512: 4 elements per thread keep the pre-pass at 228 VGPRs and two waves per SIMD
+  // (8 need 256 VGPRs and 149 AGPRs: one wave); measured 7% faster, the z pass 8% slower
+  if (fp64 && n == 512) fs.e_z = 4;
   if (!fs.e_col || !fs.e_z || !make_sched(n, fs.e_col, &fs.sched_col, &fs.nst_col) ||
       !make_sched(n / 2, fs.e_z, &fs.sched_z, &fs.nst_z)) {
     return false;
