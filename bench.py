@@ -274,8 +274,8 @@ def cpu_baseline(data, rand, edges, workers: int) -> dict:
     Sample: painting split into a per-cell part and a per-particle part, from two paints of
     catalog subsamples (1/10 and 1/40) onto a 256^3 mesh (per-cell part x8 for 512^3, the
     per-particle part extrapolated to the whole catalog); one full-grid forward transform (x17
-    transforms); the harmonic weighting of one field on 1/8 of the nodes and of the modes
-    (x8 x14 fields); one binning pass (x3 multipoles).  About 10-15 s of host work."""
+    transforms); the harmonic weighting of one field on 1/4 of the nodes and of the modes
+    (x4 x14 fields); one binning pass (x3 multipoles).  About 10-20 s of host work."""
     import scipy.fft as sfft
     from oracle.estimator import default_params, k_thresholds, mode_bins, node_vectors, mode_vectors, binned_sums
     from oracle.mesh import fkp_meshes
@@ -283,7 +283,7 @@ def cpu_baseline(data, rand, edges, workers: int) -> dict:
     from oracle.ylm import real_ylm
     from synth import Catalog
     p = default_params(NMESH, BOX, observer=OBSERVER, window=3, interlaced=True, compensated=True)
-    slab_div = 8
+    slab_div = 4
     nfields = sum(2 * l + 1 for l in range(2, ELL_MAX + 1, 2))
     t = {}
 

@@ -678,6 +678,7 @@ bool admit_some(pkm_server* sv, std::unique_lock<std::mutex>& lk) {
     }
     slot->busy = true;
     sv->resident += need;  // reserved until the plan's size is known
+    sv->peak_resident = std::max(sv->peak_resident, sv->resident);
     bound_pool(sv, need);
     lk.unlock();           // device work below; clients touch only the queue and the results
     pkm_status st = start_request(sv, r.get(), slot, reg_base);
