@@ -793,12 +793,13 @@ static size_t zpresmem(const FftShape& fs, size_t cs) {
 }
 int xpass_threads(const FftShape& fs) { return (fs.n / fs.e_col) * fs.tile; }
 int xpass_blocks(const FftShape& fs) { return fs.n * ((fs.n / 2) / fs.tile); }
-// Persistent post-pass grid: two blocks per compute unit (the register budget allows no
-// more), at most one block per tile.
+// Persistent post-pass grid: two blocks of 256 threads per compute unit (the register budget
+// allows no more), or as many smaller blocks as hold the same threads, at most one per tile.
 int post_blocks(const FftShape& fs) {
   const int tiles = fs.n * ((fs.n / 2) / fs.tile_post);
   const int cus = fs.cus > 0 ? fs.cus : 256;
-  return std::min(tiles, 2 * cus);
+  const int nthr = (fs.n / fs.e_post) * fs.tile_post;
+  return std::min(tiles, std::max(2, 512 / nthr) * cus);
 }
 static size_t colsmem(const FftShape& fs, size_t cs) { return cs * ((size_t)fs.n * (fs.tile + 1) + fs.n); }
 size_t zpass_smem_bytes(const FftShape& fs, bool fp64) {
@@ -865,8 +866,10 @@ size_t xpost_base_bytes(const FftShape& fs, bool fp64) {
   PKM_TRY(256, 8, 8, fs.e_post, fs.tile_post, CALL)  \
   PKM_TRY(512, 8, 4, fs.e_post, fs.tile_post, CALL)  \
   PKM_TRY(1024, 8, 2, fs.e_post, fs.tile_post, CALL) \
+  PKM_TRY(1024, 8, 1, fs.e_post, fs.tile_post, CALL) \
   PKM_TRY(384, 6, 4, fs.e_post, fs.tile_post, CALL)  \
   PKM_TRY(768, 6, 2, fs.e_post, fs.tile_post, CALL)  \
+  PKM_TRY(768, 6, 1, fs.e_post, fs.tile_post, CALL)  \
   PKM_TRY(384, 12, 8, fs.e_post, fs.tile_post, CALL) \
   PKM_TRY(768, 12, 4, fs.e_post, fs.tile_post, CALL)
 

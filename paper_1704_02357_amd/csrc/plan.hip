@@ -1077,6 +1077,9 @@ bool make_shape(const pkm_params& p, FftShape* out) {
     int tp = std::max(1, 256 / pt_post);
     tp = std::min(tp, 16);
     while (tp > 1 && (n / 2) % tp) tp /= 2;
+    // a line wider than a wavefront synchronises its whole block at every radix stage: one
+    // line per block (with more blocks per CU) measured 8-16% faster at 768 and 1024
+    if (pt_post > 64) tp = 1;
     fs.tile_post = tp;
   }
   // z lines per block: a power of two dividing n (a block's lines share one x plane, and the
