@@ -335,7 +335,7 @@ def batch_bench(args) -> dict:
     import torch
     from paper_1704_02357_amd import Batch, Plan
     from synth import batch_mock
-    n_mocks, lmax, per_size = args.mocks, 4, 4
+    n_mocks, lmax, per_size = args.mocks, 4, args.plans_per_size
     t0 = time.perf_counter()
     mocks = [batch_mock(i) for i in range(n_mocks)]
     log(f"[batch] {n_mocks} mocks generated in {time.perf_counter() - t0:.1f} s")
@@ -410,7 +410,8 @@ def batch_bench(args) -> dict:
             "data": "synthetic (seeded lognormal mocks, resident in HBM)",
             "config": {"workload": f"{n_mocks} mocks, Nmesh cycling 128/256/384, L=2000 Mpc/h, 5e4-8e5 galaxies, "
                                    "10x randoms, TSC + interlacing + compensation, l<=4, 0.01 h/Mpc bins",
-                       "plans_per_size": per_size},
+                       "plans_per_size": per_size,
+                       "hip_hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "runtime default")},
             "max_scaled_err_vs_sequential": max(errs)}
 
 
@@ -749,6 +750,7 @@ def main():
                          "basis: spherical against Cartesian decomposition; covariance: Kaiser-mock wedge "
                          "covariance; fft: the 3D transform against ROCm's FFT library")
     ap.add_argument("--mocks", type=int, default=64)
+    ap.add_argument("--plans-per-size", type=int, default=4, help="batch mode: plans (streams) per mesh size")
     ap.add_argument("--requests", type=int, default=2000, help="serve mode: requests of the 0.8 x capacity stream")
     ap.add_argument("--sweep-requests", type=int, default=200, help="serve mode: requests of the other streams")
     ap.add_argument("--burst", type=int, default=100, help="serve mode: requests of the capacity burst")
