@@ -114,21 +114,31 @@ def summarize_profile(directory: str) -> None:
             print(f"{k:60s} {c:>14s} {len(d):10d} {v / len(d):18.6g}")
 
 
-def run_form(precision: int, data, rand, edges, steps: int, warmup: int):
-    """One estimate per step through the asynchronous calls: pkm_prepare once, then per step
+def run_form(precision: int, data, rand, edges, steps: int, warmup: int, pipeline: int = 2):
+    """Estimates through the asynchronous calls: pkm_prepare once per plan, then per step
     pkm_enqueue (paint, every transform, all (l, m) fields, binning; no host wait inside) and
-    pkm_finish (wait, normalise).  The headline loop runs with per-launch timing off; a second
-    loop of the same steps records HIP events on the plan's stream around every launch and
-    gives the per-stage device times (and its own wall time, to show the events' overhead)."""
+    pkm_finish (wait, normalise).  The headline loop keeps `pipeline` estimates in flight, each
+    on its own plan and stream (step i on plan i mod pipeline, whose previous estimate is
+    finished first), so the latency-bound painting of one estimate overlaps the transforms of
+    another; per-launch timing is off.  A serial loop on one plan gives the per-estimate latency
+    and the one-in-flight rate; a third loop of the same steps on that plan records HIP events
+    around every launch and gives the per-stage device times (and its own wall time, to show the
+    events' overhead)."""
     import torch
     from paper_1704_02357_amd import Plan
-    plan = Plan(NMESH, BOX, observer=OBSERVER, window=3, interlaced=True, compensated=True, precision=precision,
-                ell_max_hint=ELL_MAX)
-    plan.prepare(ELL_MAX, edges, int(data[0].shape[0] + rand[0].shape[0]))
+    pipeline = max(1, pipeline)
+    plans = [Plan(NMESH, BOX, observer=OBSERVER, window=3, interlaced=True, compensated=True, precision=precision,
+                  ell_max_hint=ELL_MAX, stream=torch.cuda.Stream()) for _ in range(pipeline)]
+    for p in plans:
+        p.prepare(ELL_MAX, edges, int(data[0].shape[0] + rand[0].shape[0]))
+        p.set_stage_timing(False)
     for _ in range(warmup):
-        plan.enqueue(data, rand)
-        res = plan.finish()
-    plan.set_stage_timing(False)
+        for p in plans:
+            p.enqueue(data, rand)
+        for p in plans:
+            res = p.finish()
+    plan = plans[0]
+    # one estimate in flight: latency and rate
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -138,8 +148,25 @@ def run_form(precision: int, data, rand, edges, steps: int, warmup: int):
         res = plan.finish()
         lat.append(time.perf_counter() - s0)
     torch.cuda.synchronize()
+    sec_one = time.perf_counter() - t0
+    # headline: `pipeline` estimates in flight
+    busy = [False] * pipeline
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        j = i % pipeline
+        if busy[j]:
+            res = plans[j].finish()
+        plans[j].enqueue(data, rand)
+        busy[j] = True
+    for i in range(steps, steps + pipeline):
+        j = i % pipeline
+        if busy[j]:
+            res = plans[j].finish()
+            busy[j] = False
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
-    # stage pass: the same steps with per-launch events
+    # stage pass: the same steps on one plan with per-launch events
     plan.reset_stats()
     plan.set_stage_timing(True)
     torch.cuda.synchronize()
@@ -150,8 +177,9 @@ def run_form(precision: int, data, rand, edges, steps: int, warmup: int):
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     st = plan.stats()
-    plan.close()
-    return res, (t1 - t0), np.array(lat), st, (t3 - t2)
+    for p in plans:
+        p.close()
+    return res, (t1 - t0), np.array(lat), st, (t3 - t2), sec_one
 
 
 def golden_poles(info, data, rand):
@@ -735,6 +763,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--pipeline", type=int, default=2,
+                    help="estimates in flight in the headline loop, each on its own plan and stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ngal", type=int, default=1_000_000)
     ap.add_argument("--random-factor", type=float, default=20.0)
@@ -800,15 +830,19 @@ def main():
     grand = (dev(rand.pos), dev(rand.w), dev(rand.nbar))
     torch.cuda.synchronize()
     upload = catalog_upload(data, rand, gdata + grand)
-    res32, sec32, lat32, st32, staged32 = run_form(0, gdata, grand, edges, args.steps, args.warmup)
-    log(f"[bench] fp32: {args.steps / sec32:.2f} est/s, {1e3 * sec32 / args.steps:.3f} ms/step "
+    res32, sec32, lat32, st32, staged32, one32 = run_form(0, gdata, grand, edges, args.steps, args.warmup,
+                                                          args.pipeline)
+    log(f"[bench] fp32: {args.steps / sec32:.2f} est/s, {1e3 * sec32 / args.steps:.3f} ms/step with "
+        f"{args.pipeline} in flight; one in flight {args.steps / one32:.2f} est/s "
         f"({1e3 * staged32 / args.steps:.3f} ms/step with per-launch events)")
     k64 = args.fp64_steps or max(2, args.steps // 2)
     if args.fp32_only:
-        res64, sec64, lat64, st64, staged64 = res32, float("nan"), np.full(1, np.nan), None, float("nan")
+        res64, sec64, lat64, st64, staged64, one64 = res32, float("nan"), np.full(1, np.nan), None, float("nan"), \
+            float("nan")
     else:
-        res64, sec64, lat64, st64, staged64 = run_form(1, gdata, grand, edges, k64, max(1, args.warmup // 2))
-        log(f"[bench] fp64: {k64 / sec64:.2f} est/s")
+        res64, sec64, lat64, st64, staged64, one64 = run_form(1, gdata, grand, edges, k64, max(1, args.warmup // 2),
+                                                              args.pipeline)
+        log(f"[bench] fp64: {k64 / sec64:.2f} est/s; one in flight {k64 / one64:.2f} est/s")
     ref = golden_poles(info, data, rand) if np.array_equal(edges, np.arange(len(edges)) * 0.01) else None
     vs_oracle = None
     if ref is not None and np.allclose(ref["edges"], edges, rtol=0, atol=1e-12):
@@ -859,9 +893,12 @@ def main():
                    "n_data": info["n_data"], "n_rand": info["n_rand"]},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat32, 50)), 3),
                        "p99": round(1e3 * float(np.percentile(lat32, 99)), 3)},
+        "estimates_in_flight": args.pipeline,
+        "one_in_flight": {"value": round(args.steps / one32, 3), "ms_per_step": round(1e3 * one32 / args.steps, 4)},
         "ms_per_step_with_stage_events": round(1e3 * staged32 / args.steps, 4),
         "err_vs_oracle": vs_oracle,
         "fp64": {"value": round(k64 / sec64, 3), "ms_per_step": round(1e3 * sec64 / k64, 4),
+                 "one_in_flight": {"value": round(k64 / one64, 3), "ms_per_step": round(1e3 * one64 / k64, 4)},
                  "stage_ms_per_step": ({k: round(v / k64, 3) for k, v in st64["stage_ms"].items() if v > 0}
                                        if not args.fp32_only else None),
                  "latency_ms": {"p50": round(1e3 * float(np.percentile(lat64, 50)), 3),
