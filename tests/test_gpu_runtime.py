@@ -114,6 +114,39 @@ def test_async_estimate_matches_sync(gpu, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_estimates_in_flight_on_two_plans(gpu, prec):
+    """The benchmark's headline loop: estimate i on plan i mod 2, each plan on its own stream, a
+    plan's previous estimate finished before its next is enqueued, so two estimates (of two
+    catalogs here) overlap on the device.  Every result equals its catalog's estimate alone and
+    the oracle."""
+    import torch
+    n, lmax = 48, 4
+    cats = [small_catalogs(3000, 20000, L, seed=s) for s in (81, 82)]
+    alone = [_alone(n, prec, lmax, d, r) for d, r in cats]
+    refs = [_oracle(n, lmax, d, r) for d, r in cats]
+    dev = [(_dev(d), _dev(r)) for d, r in cats]
+    plans = [_plan(n, prec, lmax, stream=torch.cuda.Stream()) for _ in range(2)]
+    for p in plans:
+        p.prepare(lmax, _edges(n), 30000)
+    busy = [None, None]
+    got = []
+    for i in range(6):
+        j = i % 2
+        if busy[j] is not None:
+            got.append((busy[j], plans[j].finish()))
+        plans[j].enqueue(*dev[i % 2])
+        busy[j] = i % 2
+    for j in range(2):
+        got.append((busy[j], plans[j].finish()))
+    assert len(got) == 6
+    for c, res in got:
+        _same(res, alone[c], prec, f"in flight cat={c} prec={prec}")
+        assert _scaled_err(res, refs[c]) <= (1e-5 if prec == 0 else 1e-12)
+    for p in plans:
+        p.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_zero_normalisation_rejected(gpu, prec):
     """A catalog whose normalisation I vanishes (every random weight zero, or every data
     weight zero in a periodic box) has no estimate: painting, the asynchronous finish, a
