@@ -114,6 +114,29 @@ def summarize_profile(directory: str) -> None:
             print(f"{k:60s} {c:>14s} {len(d):10d} {v / len(d):18.6g}")
 
 
+def run_in_flight(plans, steps: int, data, rand):
+    """Estimate i on plans[i mod len(plans)]: a plan's previous estimate is finished before its
+    next one is enqueued, so up to len(plans) estimates are in flight, and every estimate
+    enqueued is finished before returning.  Returns the last result and the number finished."""
+    k = len(plans)
+    busy = [False] * k
+    res, done = None, 0
+    for i in range(steps):
+        j = i % k
+        if busy[j]:
+            res = plans[j].finish()
+            done += 1
+        plans[j].enqueue(data, rand)
+        busy[j] = True
+    for i in range(steps, steps + k):  # drain in enqueue order
+        j = i % k
+        if busy[j]:
+            res = plans[j].finish()
+            done += 1
+            busy[j] = False
+    return res, done
+
+
 def run_form(precision: int, data, rand, edges, steps: int, warmup: int, pipeline: int = 2):
     """Estimates through the asynchronous calls: pkm_prepare once per plan, then per step
     pkm_enqueue (paint, every transform, all (l, m) fields, binning; no host wait inside) and
@@ -150,22 +173,12 @@ def run_form(precision: int, data, rand, edges, steps: int, warmup: int, pipelin
     torch.cuda.synchronize()
     sec_one = time.perf_counter() - t0
     # headline: `pipeline` estimates in flight
-    busy = [False] * pipeline
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(steps):
-        j = i % pipeline
-        if busy[j]:
-            res = plans[j].finish()
-        plans[j].enqueue(data, rand)
-        busy[j] = True
-    for i in range(steps, steps + pipeline):
-        j = i % pipeline
-        if busy[j]:
-            res = plans[j].finish()
-            busy[j] = False
+    res, done = run_in_flight(plans, steps, data, rand)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    assert done == steps
     # stage pass: the same steps on one plan with per-launch events
     plan.reset_stats()
     plan.set_stage_timing(True)

@@ -118,3 +118,41 @@ def test_err_vs_oracle_and_golden_guard(tmp_path, monkeypatch):
         "0.0 0.01 4 0.005 1.0 2.0 3.0\n")
     g = bench.golden_poles({"n_data": 2, "n_rand": 2}, cat, cat)
     assert g is not None and g["poles"].shape == (3, 1) and g["n_modes"][0] == 4
+
+
+class _FakePlan:
+    """Stands in for a plan: records the order of enqueue and finish calls."""
+
+    def __init__(self, name, log):
+        self.name, self.log, self.pending = name, log, []
+
+    def enqueue(self, data, rand):
+        assert not self.pending, f"{self.name}: enqueue while an estimate is in flight"
+        self.log.append(("enqueue", self.name))
+        self.pending.append(len([e for e in self.log if e[0] == "enqueue"]) - 1)
+
+    def finish(self):
+        assert self.pending, f"{self.name}: finish without an estimate"
+        self.log.append(("finish", self.name))
+        return self.pending.pop()
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("steps", [1, 2, 5, 20])
+def test_in_flight_loop_finishes_every_estimate(k, steps):
+    log = []
+    plans = [_FakePlan(i, log) for i in range(k)]
+    res, done = bench.run_in_flight(plans, steps, None, None)
+    assert done == steps
+    enq = [p for op, p in log if op == "enqueue"]
+    fin = [p for op, p in log if op == "finish"]
+    assert enq == [i % k for i in range(steps)]          # estimate i on plan i mod k
+    assert sorted(fin) == sorted(enq)                    # every estimate finished
+    assert all(not p.pending for p in plans)
+    assert res == steps - 1                              # the last estimate enqueued is finished last
+    # at most k estimates in flight at any time
+    inflight = peak = 0
+    for op, _ in log:
+        inflight += 1 if op == "enqueue" else -1
+        peak = max(peak, inflight)
+    assert peak == min(k, steps)
