@@ -777,7 +777,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--pipeline", type=int, default=2,
-                    help="estimates in flight in the headline loop, each on its own plan and stream")
+                    help="FP32 estimates in flight in the headline loop, each on its own plan and stream")
+    ap.add_argument("--pipeline-fp64", type=int, default=3, help="the same for the FP64 form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ngal", type=int, default=1_000_000)
     ap.add_argument("--random-factor", type=float, default=20.0)
@@ -848,13 +849,13 @@ def main():
     log(f"[bench] fp32: {args.steps / sec32:.2f} est/s, {1e3 * sec32 / args.steps:.3f} ms/step with "
         f"{args.pipeline} in flight; one in flight {args.steps / one32:.2f} est/s "
         f"({1e3 * staged32 / args.steps:.3f} ms/step with per-launch events)")
-    k64 = args.fp64_steps or max(2, args.steps // 2)
+    k64 = args.fp64_steps or args.steps
     if args.fp32_only:
         res64, sec64, lat64, st64, staged64, one64 = res32, float("nan"), np.full(1, np.nan), None, float("nan"), \
             float("nan")
     else:
         res64, sec64, lat64, st64, staged64, one64 = run_form(1, gdata, grand, edges, k64, max(1, args.warmup // 2),
-                                                              args.pipeline)
+                                                              args.pipeline_fp64)
         log(f"[bench] fp64: {k64 / sec64:.2f} est/s; one in flight {k64 / one64:.2f} est/s")
     ref = golden_poles(info, data, rand) if np.array_equal(edges, np.arange(len(edges)) * 0.01) else None
     vs_oracle = None
@@ -906,7 +907,7 @@ def main():
                    "n_data": info["n_data"], "n_rand": info["n_rand"]},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat32, 50)), 3),
                        "p99": round(1e3 * float(np.percentile(lat32, 99)), 3)},
-        "estimates_in_flight": args.pipeline,
+        "estimates_in_flight": {"fp32": args.pipeline, "fp64": args.pipeline_fp64},
         "one_in_flight": {"value": round(args.steps / one32, 3), "ms_per_step": round(1e3 * one32 / args.steps, 4)},
         "ms_per_step_with_stage_events": round(1e3 * staged32 / args.steps, 4),
         "err_vs_oracle": vs_oracle,
