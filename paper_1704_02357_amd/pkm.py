@@ -113,6 +113,14 @@ def load_library():
     path = lib_path()
     if not os.path.exists(path):
         raise OSError(f"{path} not found: build it with paper_1704_02357_amd/build.py")
+    # torch's ROCm build carries its own HIP runtime under the same soname as the system one
+    # the library links.  Loading torch first makes the library bind to that copy, so the
+    # process holds one HIP runtime whichever of the two the caller touches first (loading the
+    # library first and torch later would leave two, and the second finds no device).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     P = C.c_void_p
     sig = {
@@ -225,15 +233,19 @@ class _TorchAllocator:
 
     def __init__(self, device: int):
         import torch
+        # raw allocations need torch's device state, which torch sets up lazily on first use
+        torch.cuda.init()
         self.torch = torch
         self.device = device
+        self.error = None  # the last failed allocation's exception (callbacks cannot raise)
         self.c_alloc = ALLOC_FN(self._alloc)
         self.c_free = FREE_FN(self._free)
 
     def _alloc(self, size, stream, ctx):
         try:
             return int(self.torch.cuda.caching_allocator_alloc(int(size), self.device, stream or 0))
-        except Exception:
+        except Exception as e:
+            self.error = f"{type(e).__name__}: {e}"
             return None
 
     def _free(self, ptr, stream, ctx):
@@ -327,7 +339,12 @@ class Plan:
         st = self.lib.pkm_plan_create_shaped(C.byref(p), C.byref(d), C.byref(sh) if sh is not None else None,
                                              C.byref(h))
         if st:
-            raise PkmError(st, "pkm_plan_create failed" + (" (shape rejected)" if shape and st == 1 else ""))
+            msg = self.lib.pkm_plan_last_error(None)
+            why = msg.decode() if msg else ""
+            if self._alloc is not None and self._alloc.error:
+                why += f" (torch allocator: {self._alloc.error})"
+            raise PkmError(st, "pkm_plan_create failed" + (" (shape rejected)" if shape and st == 1 else "")
+                           + (f": {why}" if why else ""))
         self.h = h
         self._keep = []
 
