@@ -86,11 +86,11 @@ __device__ __forceinline__ int wrap(long long c, int n) {
 
 // ---------------------------------------------------------------------------------------
 // Tile-sorted painting.  Particles are counting-sorted by the tile (TS^3 nodes) holding
-// their base node floor(u); each workgroup accumulates one tile plus its halo
-// ([t0 - 1, t0 + TS + 3) per axis, which holds every tap of NGP/CIC/TSC on both the plain
-// and the +1/2 interlaced mesh) in LDS, then adds the non-zero region cells to the global
-// meshes with atomics.  A tap that falls outside the region (only possible through FP64
-// rounding at a cell face) goes straight to a global atomic.
+// their base node floor(u); each workgroup accumulates one tile plus the halo its window
+// reaches, one LDS region per mesh (for TSC (TS + 3)^3 nodes from t0 - 1 on the plain mesh and
+// (TS + 2)^3 from t0 on the +1/2 interlaced one; PaintReach), then adds the non-zero region
+// cells to the global meshes with atomics.  A tap that falls outside its region (only possible
+// through FP64 rounding at a cell face) goes straight to a global atomic.
 // ---------------------------------------------------------------------------------------
 __device__ __forceinline__ void mesh_u(const double* __restrict__ pos, int64_t i, double o0, double o1, double o2,
                                        double scale, double* u) {
@@ -323,6 +323,47 @@ __device__ __forceinline__ void tile_scatter(double* __restrict__ reg, T* __rest
   }
 }
 
+// Per-axis reach of a window from a particle's base node b = floor(u): the plain mesh's taps
+// lie on nodes b + LO1 .. b + LO1 + EXT1 - 1 + (0 .. ts - 1 over the tile's base nodes), the
+// interlaced mesh's (taps of u + 1/2) on b + LO2 ..; so the LDS region of a tile of ts base
+// nodes per axis is ts + EXT nodes wide from t0 + LO.  NGP: one tap at floor(u + 1/2), in
+// {b, b + 1} (plain) and b + 1 (interlaced).  CIC: b, b + 1 (plain) and floor(u + 1/2) + {0, 1}
+// within b .. b + 2.  TSC: floor(u + 1/2) + {-1, 0, 1} within b - 1 .. b + 2 (plain) and
+// b + 1 + {-1, 0, 1} (interlaced).  A tap that FP64 rounding of u + 1/2 at a cell face moves
+// outside goes to the mesh directly (tile_scatter).
+template <int W> struct PaintReach;
+template <> struct PaintReach<1> { static constexpr int LO1 = 0, EXT1 = 1, LO2 = 1, EXT2 = 0; };
+template <> struct PaintReach<2> { static constexpr int LO1 = 0, EXT1 = 1, LO2 = 0, EXT2 = 2; };
+template <> struct PaintReach<3> { static constexpr int LO1 = -1, EXT1 = 3, LO2 = 0, EXT2 = 2; };
+
+// Add the non-zero cells of one LDS region (side N, origin t0 + LO) to the mesh with global
+// atomics (or, DET, the integer sums to the 64-bit accumulators).
+template <typename T, bool DET, int N, int LO>
+__device__ __forceinline__ void flush_region(const double* __restrict__ reg, T* __restrict__ mesh,
+                                             unsigned long long* __restrict__ acc, const int* t0, int nmesh,
+                                             double isc) {
+  for (int i = threadIdx.x; i < N * N * N; i += blockDim.x) {
+    const long long q = reinterpret_cast<const long long*>(reg)[i];
+    T v;
+    if constexpr (sizeof(T) == 4 && !DET)
+      v = (T)((double)q * isc);
+    else
+      v = (T)reg[i];
+    if (DET ? q == 0 : v == T(0)) continue;
+    // region node (ra, rb, rc) is mesh node t0 + LO + (ra, rb, rc), wrapped once at most
+    const int rc = i % N, rb = (i / N) % N, ra = i / (N * N);
+    int gx = t0[0] + LO + ra, gy = t0[1] + LO + rb, gz = t0[2] + LO + rc;
+    gx += gx < 0 ? nmesh : (gx >= nmesh ? -nmesh : 0);
+    gy += gy < 0 ? nmesh : (gy >= nmesh ? -nmesh : 0);
+    gz += gz < 0 ? nmesh : (gz >= nmesh ? -nmesh : 0);
+    const size_t g = ((size_t)gx * nmesh + gy) * nmesh + gz;
+    if constexpr (DET)
+      atomicAdd(&acc[g], (unsigned long long)q);
+    else
+      unsafeAtomicAdd(&mesh[g], v);
+  }
+}
+
 // DET: the tiles' integer sums go to the 64-bit accumulators acc1 / acc2 (one per mesh) with
 // integer atomics at the shared scale *gsc, instead of floating-point atomics to d1 / d2.
 template <typename T, int W, int TS, bool DET>
@@ -335,18 +376,19 @@ __global__ void __launch_bounds__(256) k_paint_tiles(const int* __restrict__ off
                                                      unsigned long long* __restrict__ acc2,
                                                      const double* __restrict__ gsc) {
   constexpr int ts = TS;
+  using R = PaintReach<W>;
+  constexpr int n1 = ts + R::EXT1, n2 = ts + R::EXT2;  // region sides of the two meshes
   extern __shared__ __align__(16) unsigned char smem[];
   // natural tile order: consecutive tiles land on different XCDs, which spreads the dense
   // survey region evenly (measured faster than XCD-local orders that keep halos in one L2)
   const int tile = blockIdx.x;
   const int start = off[tile], end = off[tile + 1];
   if (start == end) return;
-  constexpr int rsz = ts + 4;
-  constexpr int rcells = rsz * rsz * rsz;
   double* r1 = reinterpret_cast<double*>(smem);   // FP64 accumulation for both precisions
-  double* r2 = r1 + rcells;
-  const int nreg = d2 ? 2 : 1;
-  for (int i = threadIdx.x; i < nreg * rcells; i += blockDim.x) r1[i] = 0.0;
+  double* r2 = r1 + n1 * n1 * n1;
+  const bool two = d2 != nullptr;
+  const int ncells = n1 * n1 * n1 + (two ? n2 * n2 * n2 : 0);
+  for (int i = threadIdx.x; i < ncells; i += blockDim.x) r1[i] = 0.0;
   const int tpa = nmesh / ts;
   const int tz = tile % tpa, ty = (tile / tpa) % tpa, tx = tile / (tpa * tpa);
   const int t0[3] = {tx * ts, ty * ts, tz * ts};
@@ -370,47 +412,26 @@ __global__ void __launch_bounds__(256) k_paint_tiles(const int* __restrict__ off
     u[0] = __dmul_rn(__dsub_rn(p.x, o0), scale);
     u[1] = __dmul_rn(__dsub_rn(p.y, o1), scale);
     u[2] = __dmul_rn(__dsub_rn(p.z, o2), scale);
-    // region origin (unwrapped) = base tile origin of this particle's floor(u) - 1
-    long long r0[3];
+    // region origins (unwrapped, in this particle's frame): the tile origin t0 plus LO
+    long long r01[3], r02[3];
     for (int a = 0; a < 3; ++a) {
       const long long cu = (long long)floor(u[a]);
-      r0[a] = cu - (wrap(cu, nmesh) - t0[a]) - 1;
+      const long long base = cu - (wrap(cu, nmesh) - t0[a]);
+      r01[a] = base + R::LO1;
+      r02[a] = base + R::LO2;
     }
-    tile_scatter<T, W, DET>(r1, d1, acc1, u, wgt, nmesh, r0, rsz, sc);
-    if (nreg == 2) {
+    tile_scatter<T, W, DET>(r1, d1, acc1, u, wgt, nmesh, r01, n1, sc);
+    if (two) {
       u[0] = __dadd_rn(u[0], 0.5);
       u[1] = __dadd_rn(u[1], 0.5);
       u[2] = __dadd_rn(u[2], 0.5);
-      tile_scatter<T, W, DET>(r2, d2, acc2, u, wgt, nmesh, r0, rsz, sc);
+      tile_scatter<T, W, DET>(r2, d2, acc2, u, wgt, nmesh, r02, n2, sc);
     }
   }
   __syncthreads();
-  for (int m = 0; m < nreg; ++m) {
-    const double* reg = m ? r2 : r1;
-    T* mesh = m ? d2 : d1;
-    unsigned long long* acc = m ? acc2 : acc1;
-    const double isc = 1.0 / sc;  // a power of two: exact
-    for (int i = threadIdx.x; i < rcells; i += blockDim.x) {
-      const long long q = reinterpret_cast<const long long*>(reg)[i];
-      T v;
-      if constexpr (sizeof(T) == 4 && !DET)
-        v = (T)((double)q * isc);
-      else
-        v = (T)reg[i];
-      if (DET ? q == 0 : v == T(0)) continue;
-      // region node (ra, rb, rc) is mesh node t0 - 1 + (ra, rb, rc), wrapped once at most
-      const int rc = i % rsz, rb = (i / rsz) % rsz, ra = i / (rsz * rsz);
-      int gx = t0[0] - 1 + ra, gy = t0[1] - 1 + rb, gz = t0[2] - 1 + rc;
-      gx += gx < 0 ? nmesh : (gx >= nmesh ? -nmesh : 0);
-      gy += gy < 0 ? nmesh : (gy >= nmesh ? -nmesh : 0);
-      gz += gz < 0 ? nmesh : (gz >= nmesh ? -nmesh : 0);
-      const size_t g = ((size_t)gx * nmesh + gy) * nmesh + gz;
-      if constexpr (DET)
-        atomicAdd(&acc[g], (unsigned long long)q);
-      else
-        unsafeAtomicAdd(&mesh[g], v);
-    }
-  }
+  const double isc = 1.0 / sc;  // a power of two: exact
+  flush_region<T, DET, n1, R::LO1>(r1, d1, acc1, t0, nmesh, isc);
+  if (two) flush_region<T, DET, n2, R::LO2>(r2, d2, acc2, t0, nmesh, isc);
 }
 
 // Deterministic mode: the shared fixed-point scale.  A node's value is a sum of taps of the
@@ -500,7 +521,12 @@ hipError_t launch_paint_tiles(const int* off, const void* payload, int ntiles, c
                               const double* wmax_r, double alpha, hipStream_t s, unsigned long long* acc,
                               double* gsc) {
   const bool two = d2 != nullptr;
-  const size_t sm = sizeof(double) * (size_t)(ts + 4) * (ts + 4) * (ts + 4) * (two ? 2 : 1);
+  int e1 = 0, e2 = 0;  // region sides ts + e1 (plain mesh) and ts + e2 (interlaced mesh)
+  if (window == 1) { e1 = PaintReach<1>::EXT1; e2 = PaintReach<1>::EXT2; }
+  else if (window == 2) { e1 = PaintReach<2>::EXT1; e2 = PaintReach<2>::EXT2; }
+  else { e1 = PaintReach<3>::EXT1; e2 = PaintReach<3>::EXT2; }
+  const size_t c1 = (size_t)(ts + e1) * (ts + e1) * (ts + e1), c2 = (size_t)(ts + e2) * (ts + e2) * (ts + e2);
+  const size_t sm = sizeof(double) * (c1 + (two ? c2 : 0));
   const double4* pl = (const double4*)payload;
   unsigned long long* acc2 = (acc && two) ? acc + (size_t)nmesh * nmesh * nmesh : nullptr;
   if (acc) {
