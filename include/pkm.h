@@ -407,8 +407,10 @@ void pkm_batch_destroy(pkm_batch* batch);
  * 8 queued ones in arrival order: the first whose footprint fits hbm_budget_bytes (idle plans
  * evicted least recently used first) while fewer than max_inflight estimates run, so a request
  * blocked on memory does not hold back smaller ones behind it; once the oldest request has been
- * passed 16 times, nothing else is admitted before it.  A request that cannot fit even with no
- * plan resident fails with PKM_ENOMEM.  Admitted requests run on separate streams and overlap
+ * passed 16 times, nothing else is admitted before it.  Admission also keeps the device's own
+ * free memory, after the request, at 2 GiB or 1% of the device (the larger) for the runtime's
+ * kernel scratch, evicting idle plans and releasing the pool's kept blocks first, else waiting.
+ * A request that cannot fit even with no plan resident fails with PKM_ENOMEM.  Admitted requests run on separate streams and overlap
  * on the device; plans (meshes, tables, staging) stay resident and are reused by later requests
  * with the same mesh, box, observer, window, precision and max_group.  A plan keeps the painted
  * field of the registered catalog it served last: a later request for that catalog on that plan

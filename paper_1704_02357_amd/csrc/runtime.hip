@@ -456,6 +456,27 @@ void bound_pool(const pkm_server* sv, int64_t extra) {
   (void)hipGetLastError();
 }
 
+// Whether the device keeps its headroom after `need` more bytes: the pool's reserved blocks
+// (live, kept or fragmented) count against the device's free memory, and the runtime allocates
+// a queue's kernel scratch from what is left when a kernel that spills first runs there, so a
+// pool that fills the device makes that dispatch fail.  The headroom is 2 GiB or 1% of the
+// device, whichever is larger; kept blocks are released before the second look.
+bool device_room(int64_t need) {
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;  // no reading: the budget alone decides
+  }
+  const int64_t headroom = std::max<int64_t>(int64_t(2) << 30, (int64_t)(tot / 100));
+  if ((int64_t)fr - need >= headroom) return true;
+  trim_pool();
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;
+  }
+  return (int64_t)fr - need >= headroom;
+}
+
 // Evict an idle slot: its plan and catalog buffer go back to the pool on its own stream (which
 // runs nothing else, so waiting for it waits for the frees only and lets any stream reuse the
 // blocks at once), its pinned buffers to the server's spares (freeing pinned memory would
@@ -644,13 +665,30 @@ bool admit_some(pkm_server* sv, std::unique_lock<std::mutex>& lk) {
       }
       continue;  // wait for running estimates; look at the next request
     }
-    while (sv->resident + need > sv->cfg.hbm_budget_bytes) {
+    auto evict_lru = [&]() {
       Slot* victim = nullptr;
       for (auto& s : sv->slots)
         if (!s->busy && s.get() != use && (!victim || s->last_used < victim->last_used)) victim = s.get();
-      if (!victim) break;
+      if (!victim) return false;
       free_slot(sv, victim);
       sv->slots.erase(std::find_if(sv->slots.begin(), sv->slots.end(), [&](auto& p) { return p.get() == victim; }));
+      return true;
+    };
+    while (sv->resident + need > sv->cfg.hbm_budget_bytes && evict_lru()) {
+    }
+    // the device's own free memory (budget or not): evict further idle plans while it lacks the
+    // headroom; if it still does, wait for the running estimates, or fail when none runs
+    bool room = device_room(need);
+    while (!room && evict_lru()) room = device_room(need);
+    if (!room) {
+      if (!running && qi == 0) {
+        sv->queue.pop_front();
+        r->err = "device memory below the request's footprint plus the runtime's headroom";
+        complete(sv, r, PKM_ENOMEM);
+        sv->cv_done.notify_all();
+        return true;
+      }
+      continue;
     }
     for (size_t k = 0; k < qi; ++k) ++sv->queue[k]->passed;
     sv->queue.erase(sv->queue.begin() + (std::ptrdiff_t)qi);
